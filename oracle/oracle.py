@@ -1,0 +1,181 @@
+"""ctypes loader for the C oracle (TEST INFRASTRUCTURE ONLY).
+
+Arrays are numpy float64 in C order with shape (ny, nx) in 2-D or
+(nz, ny, nx) in 3-D, i.e. x fastest, the layout the C file indexes.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+BC = {"periodic": 0, "insulating": 1}
+LIMITER = {"vanleer": 0, "minmod": 1, "mc": 2, "linear": 3}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _OrcGrid(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_long * 3),
+        ("h", ctypes.c_double * 3),
+        ("bc", ctypes.c_int),
+        ("limiter", ctypes.c_int),
+        ("chi_par", ctypes.c_double),
+        ("chi_perp", ctypes.c_double),
+        ("b", _dp * 3),
+        ("chi", _dp),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load liborc.so, building it with gcc only when it is missing."""
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.orc_lim2.restype = ctypes.c_double
+        L.orc_lim2.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_lim4.restype = ctypes.c_double
+        L.orc_lim4.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4
+        for name in ("orc_thomas", "orc_cyclic"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_long, _dp, _dp, _dp, _dp, _dp]
+        L.orc_sweep.restype = ctypes.c_int
+        L.orc_sweep.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_int, ctypes.c_double, _dp, _dp]
+        for name in ("orc_step_si", "orc_step_explicit"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.orc_energy.restype = ctypes.c_double
+        L.orc_energy.argtypes = [ctypes.POINTER(_OrcGrid), _dp]
+        L.orc_dt_from_ncfl.restype = ctypes.c_double
+        L.orc_dt_from_ncfl.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_double]
+        L.orc_grid_sizeof.restype = ctypes.c_long
+        assert L.orc_grid_sizeof() == ctypes.sizeof(_OrcGrid), "orc_grid layout mismatch"
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleGrid:
+    """A grid description for the oracle.
+
+    b: sequence of ndim cell-centred arrays (bx, by[, bz]), each of shape
+       (ny, nx) or (nz, ny, nx).  h: cell widths (hx, hy[, hz]).
+    """
+
+    def __init__(self, b, h, bc="periodic", limiter="vanleer", chi_par=1.0, chi_perp=0.0, chi=None):
+        self.b = [_f64(c) for c in b]
+        self.ndim = len(self.b)
+        if self.ndim not in (2, 3):
+            raise ValueError("ndim must be 2 or 3")
+        self.shape = self.b[0].shape
+        if len(self.shape) != self.ndim or any(c.shape != self.shape for c in self.b):
+            raise ValueError("b components must share one (ny,nx) or (nz,ny,nx) shape")
+        self.h = tuple(float(x) for x in h)
+        self.bc = bc
+        self.limiter = limiter
+        self.chi_par = float(chi_par)
+        self.chi_perp = float(chi_perp)
+        self.chi = None if chi is None else _f64(chi)
+        if self.chi is not None and self.chi.shape != self.shape:
+            raise ValueError("chi must have the grid shape")
+        s = _OrcGrid()
+        s.ndim = self.ndim
+        nxyz = tuple(reversed(self.shape)) + (1,) * (3 - self.ndim)
+        for q in range(3):
+            s.n[q] = nxyz[q]
+            s.h[q] = self.h[q] if q < self.ndim else 1.0
+            s.b[q] = _ptr(self.b[q]) if q < self.ndim else _dp()
+        s.bc = BC[bc]
+        s.limiter = LIMITER[limiter]
+        s.chi_par = self.chi_par
+        s.chi_perp = self.chi_perp
+        s.chi = _ptr(self.chi) if self.chi is not None else _dp()
+        self._s = s
+
+    @property
+    def ncells(self):
+        return int(np.prod(self.shape))
+
+    def _check(self, T):
+        T = _f64(T)
+        if T.shape != self.shape:
+            raise ValueError(f"field shape {T.shape} != grid shape {self.shape}")
+        return T
+
+    def sweep(self, axis, dt, U):
+        """One directional sweep along axis (0=x, 1=y, 2=z); returns a new array."""
+        U = self._check(U)
+        out = np.empty_like(U)
+        rc = lib().orc_sweep(ctypes.byref(self._s), int(axis), float(dt), _ptr(U), _ptr(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_sweep failed ({rc})")
+        return out
+
+    def step_si(self, T, dt, nsteps=1, energy=False):
+        """nsteps semi-implicit steps; returns T (and energies if asked)."""
+        T = self._check(T).copy()
+        e = np.empty(nsteps + 1) if energy else None
+        rc = lib().orc_step_si(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
+                               _ptr(e) if e is not None else _dp())
+        if rc != 0:
+            raise RuntimeError(f"orc_step_si failed ({rc})")
+        return (T, e) if energy else T
+
+    def step_explicit(self, T, dt, nsteps=1, energy=False):
+        """nsteps explicit limited steps; returns T (and energies if asked)."""
+        T = self._check(T).copy()
+        e = np.empty(nsteps + 1) if energy else None
+        rc = lib().orc_step_explicit(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
+                                     _ptr(e) if e is not None else _dp())
+        if rc != 0:
+            raise RuntimeError(f"orc_step_explicit failed ({rc})")
+        return (T, e) if energy else T
+
+    def energy(self, T):
+        T = self._check(T)
+        return lib().orc_energy(ctypes.byref(self._s), _ptr(T))
+
+    def dt_from_ncfl(self, ncfl):
+        return lib().orc_dt_from_ncfl(ctypes.byref(self._s), float(ncfl))
+
+
+def lim2(limiter, a, b):
+    return lib().orc_lim2(LIMITER[limiter], float(a), float(b))
+
+
+def lim4(limiter, a, b, c, d):
+    return lib().orc_lim4(LIMITER[limiter], float(a), float(b), float(c), float(d))
+
+
+def thomas(lo, di, up, r):
+    lo, di, up, r = (_f64(v) for v in (lo, di, up, r))
+    x = np.empty_like(r)
+    if lib().orc_thomas(len(r), _ptr(lo), _ptr(di), _ptr(up), _ptr(r), _ptr(x)) != 0:
+        raise RuntimeError("orc_thomas failed")
+    return x
+
+
+def cyclic(lo, di, up, r):
+    lo, di, up, r = (_f64(v) for v in (lo, di, up, r))
+    x = np.empty_like(r)
+    if lib().orc_cyclic(len(r), _ptr(lo), _ptr(di), _ptr(up), _ptr(r), _ptr(x)) != 0:
+        raise RuntimeError("orc_cyclic failed")
+    return x

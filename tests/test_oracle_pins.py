@@ -1,0 +1,664 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it relies on.  None of these tests re-types the
+oracle's own formula: they compare it with closed forms (the von Neumann
+factors of section 2.1), textbook reductions, library solvers, invariants
+stated in the paper, and brute-force assembly on tiny grids.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")
+
+LIMITERS = ["vanleer", "minmod", "mc", "linear"]
+
+
+def unit(v):
+    v = np.asarray(v, dtype=float)
+    return v / np.linalg.norm(v)
+
+
+def const_field(shape, comps):
+    return [np.full(shape, float(c)) for c in comps]
+
+
+# ---------------------------------------------------------------- limiters
+
+def test_limiter_hand_values(orc):
+    # van Leer, Eq. vanLeer: 2ab/(a+b) if ab > 0 else 0
+    assert orc.lim2("vanleer", 1, 1) == 1.0
+    assert orc.lim2("vanleer", 1, 3) == 1.5
+    assert orc.lim2("vanleer", 1, -1) == 0.0
+    assert orc.lim2("vanleer", 0, 5) == 0.0
+    assert orc.lim2("vanleer", -2, -2) == -2.0
+    # minmod and MC (the alternatives named in section 2), textbook values
+    assert orc.lim2("minmod", 1, 3) == 1.0
+    assert orc.lim2("minmod", -1, -3) == -1.0
+    assert orc.lim2("minmod", 1, -3) == 0.0
+    assert orc.lim2("mc", 1, 3) == 2.0
+    assert orc.lim2("mc", 1, 1) == 1.0
+    assert orc.lim2("mc", -1, -3) == -2.0
+    assert orc.lim2("linear", 1, 3) == 2.0
+
+
+def test_nested_vanleer_is_four_argument_harmonic_mean(orc):
+    """L(L(a,b),L(c,d)) = 4/(1/a+1/b+1/c+1/d) when all four share a strict
+    sign, else 0; and it is symmetric in its arguments (section 2)."""
+    rng = np.random.default_rng(1)
+    for _ in range(400):
+        v = rng.standard_normal(4) * rng.choice([1e-3, 1.0, 1e3])
+        if rng.random() < 0.4:
+            v = np.abs(v) * rng.choice([-1, 1])
+        got = orc.lim4("vanleer", *v)
+        if np.all(v > 0) or np.all(v < 0):
+            ref = 4.0 / np.sum(1.0 / v)
+            assert got == pytest.approx(ref, rel=1e-13)
+        else:
+            assert got == 0.0
+        for perm in itertools.permutations(range(4)):
+            assert orc.lim4("vanleer", *v[list(perm)]) == pytest.approx(got, rel=1e-13, abs=0)
+
+
+def test_nested_minmod_is_four_argument_minmod(orc):
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        v = rng.standard_normal(4)
+        if rng.random() < 0.5:
+            v = np.abs(v) * rng.choice([-1, 1])
+        same = np.all(v > 0) or np.all(v < 0)
+        ref = np.sign(v[0]) * np.min(np.abs(v)) if same else 0.0
+        assert orc.lim4("minmod", *v) == ref
+
+
+def test_linear_nested_is_arithmetic_mean(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        v = rng.standard_normal(4)
+        assert orc.lim4("linear", *v) == pytest.approx(v.mean(), rel=1e-14, abs=1e-15)
+
+
+# ---------------------------------------------------------------- solvers
+
+def _dd_system(n, rng, cyclic):
+    up = -rng.uniform(0, 3, n)
+    lo = -rng.uniform(0, 3, n)
+    if not cyclic:
+        lo[0] = 0.0
+        up[-1] = 0.0
+    di = 1.0 + np.abs(lo) + np.abs(up) + rng.uniform(0, 1, n)
+    r = rng.standard_normal(n)
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, i] = di[i]
+        A[i, (i - 1) % n] += lo[i]
+        A[i, (i + 1) % n] += up[i]
+    return lo, di, up, r, A
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257])
+def test_thomas_matches_dense_solve(orc, n):
+    rng = np.random.default_rng(n)
+    lo, di, up, r, A = _dd_system(n, rng, cyclic=False)
+    np.testing.assert_allclose(orc.thomas(lo, di, up, r), np.linalg.solve(A, r), rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 64, 255])
+def test_cyclic_matches_dense_solve(orc, n):
+    rng = np.random.default_rng(100 + n)
+    lo, di, up, r, A = _dd_system(n, rng, cyclic=True)
+    np.testing.assert_allclose(orc.cyclic(lo, di, up, r), np.linalg.solve(A, r), rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------- von Neumann factors
+
+def _angles(shape, k):
+    """Grid wavenumbers (radians per cell) of integer mode k on a periodic grid."""
+    return [2.0 * np.pi * k[q] / n for q, n in enumerate(reversed(shape))]
+
+
+def _mode(shape, theta, phase=0.3):
+    idx = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")  # (.., j, i)
+    arg = phase
+    for q in range(len(shape)):
+        arg = arg + theta[q] * idx[len(shape) - 1 - q]
+    return np.cos(arg)
+
+
+def _coefs(chi, chi_perp, b, h, dt):
+    nd = len(b)
+    a = [dt * (chi_perp + (chi - chi_perp) * b[d] ** 2) / h[d] ** 2 for d in range(nd)]
+    beta = {(d, t): dt * (chi - chi_perp) * b[d] * b[t] / (h[d] * h[t])
+            for d in range(nd) for t in range(nd) if d != t}
+    return a, beta
+
+
+def _r_sweep(d, theta, a, beta):
+    """Section 2.1 factor of the sweep along axis d (Eq. amp1 / amp2 and the
+    3-D r_1 of section 2.1), with linear averaging and constant b."""
+    num = 1.0
+    for (dd, t), bt in beta.items():
+        if dd == d:
+            num -= bt * np.sin(theta[d]) * np.sin(theta[t])
+    return num / (1.0 + 4.0 * a[d] * np.sin(theta[d] / 2.0) ** 2)
+
+
+@pytest.mark.parametrize("bc_ncfl", [0.5, 10.0, 1e4])
+@pytest.mark.parametrize("chi_perp", [0.0, 0.3])
+def test_si_2d_one_step_is_r1_r2(orc, bc_ncfl, chi_perp):
+    """One 2-D step multiplies a Fourier mode by r1*r2 (Eqs. amp1, amp2),
+    which equals Eq. amp_sym, for any dt (section 2.1) and also for a general
+    SPD tensor (chi_perp > 0)."""
+    rng = np.random.default_rng(int(bc_ncfl * 10) + int(chi_perp * 100))
+    shape = (24, 40)  # (ny, nx)
+    h = (1.0 / 40, 1.3 / 24)
+    for _ in range(6):
+        b = unit(rng.standard_normal(2))
+        k = (int(rng.integers(-19, 20)), int(rng.integers(-11, 12)))
+        theta = _angles(shape, k)
+        dt = bc_ncfl * min(h) ** 2 / 4.0
+        g = orc.OracleGrid(const_field(shape, b), h, bc="periodic", limiter="linear",
+                           chi_par=1.0, chi_perp=chi_perp)
+        T0 = _mode(shape, theta)
+        T1 = g.step_si(T0, dt, 1)
+        a, beta = _coefs(1.0, chi_perp, b, h, dt)
+        r = _r_sweep(0, theta, a, beta) * _r_sweep(1, theta, a, beta)
+        np.testing.assert_allclose(T1, r * T0, rtol=0, atol=1e-12)
+        if chi_perp == 0.0:
+            # Eq. amp_sym with A_x, A_y of section 2.1
+            Ax = 2 * np.sqrt(dt) * b[0] / h[0] * np.sin(theta[0] / 2)
+            Ay = 2 * np.sqrt(dt) * b[1] / h[1] * np.sin(theta[1] / 2)
+            rs = (1 - Ax * Ay * np.cos(theta[0] / 2) * np.cos(theta[1] / 2)) ** 2 / ((1 + Ax ** 2) * (1 + Ay ** 2))
+            assert r == pytest.approx(rs, rel=1e-12, abs=1e-14)
+            assert rs <= 1.0 + 1e-14  # unconditional 2-D stability (section 2.1)
+
+
+def test_si_2d_sweep_order_matters_for_the_pin(orc):
+    """Feeding T^n (not T*) to the second sweep would give (r1 - c)/den2,
+    which differs from r1*r2: the previous pin therefore fixes which state
+    the y sweep reads (Eq. yup)."""
+    shape = (16, 16)
+    h = (1 / 16, 1 / 16)
+    b = unit([1.0, 0.7])
+    theta = _angles(shape, (3, 2))
+    dt = 50 * h[0] ** 2 / 4
+    a, beta = _coefs(1.0, 0.0, b, h, dt)
+    r1 = _r_sweep(0, theta, a, beta)
+    c = beta[(1, 0)] * np.sin(theta[0]) * np.sin(theta[1])
+    wrong = (r1 - c) / (1 + 4 * a[1] * np.sin(theta[1] / 2) ** 2)
+    right = r1 * _r_sweep(1, theta, a, beta)
+    assert abs(wrong - right) > 1e-3
+    g = orc.OracleGrid(const_field(shape, b), h, limiter="linear")
+    T0 = _mode(shape, theta)
+    T1 = g.step_si(T0, dt, 1)
+    np.testing.assert_allclose(T1, right * T0, atol=1e-12)
+
+
+@pytest.mark.parametrize("alpha_max", [0.2, 2.5, 8.0])
+def test_si_3d_one_step_is_r1_r2_r3(orc, alpha_max):
+    """3-D: one step multiplies a mode by r1*r2*r3 with r1 of section 2.1 and
+    its analogues (each sweep carries both transverse terms of its input)."""
+    rng = np.random.default_rng(int(alpha_max * 10))
+    shape = (6, 8, 10)  # (nz, ny, nx)
+    h = (1 / 10, 1 / 8, 1 / 6)
+    for _ in range(4):
+        b = unit(rng.standard_normal(3))
+        k = tuple(int(rng.integers(-(n // 2) + 1, n // 2)) for n in (10, 8, 6))
+        theta = _angles(shape, k)
+        dt = alpha_max * min(h) ** 2
+        g = orc.OracleGrid(const_field(shape, b), h, bc="periodic", limiter="linear")
+        T0 = _mode(shape, theta)
+        T1 = g.step_si(T0, dt, 1)
+        a, beta = _coefs(1.0, 0.0, b, h, dt)
+        r = np.prod([_r_sweep(d, theta, a, beta) for d in range(3)])
+        np.testing.assert_allclose(T1, r * T0, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_explicit_one_step_fourier_factor(orc, ndim):
+    """Explicit step with linear averaging: factor
+    1 - sum_d 4 alpha_d sin^2(theta_d/2) - sum_{d != t} beta_dt sin(theta_d) sin(theta_t)."""
+    rng = np.random.default_rng(7 + ndim)
+    shape = (10, 12) if ndim == 2 else (6, 8, 10)
+    nxyz = tuple(reversed(shape))
+    h = tuple(1.0 / n for n in nxyz)
+    for _ in range(4):
+        b = unit(rng.standard_normal(ndim))
+        k = tuple(int(rng.integers(-(n // 2) + 1, n // 2)) for n in nxyz)
+        theta = _angles(shape, k)
+        dt = 0.2 * min(h) ** 2
+        g = orc.OracleGrid(const_field(shape, b), h, limiter="linear", chi_perp=0.1)
+        T0 = _mode(shape, theta)
+        T1 = g.step_explicit(T0, dt, 1)
+        a, beta = _coefs(1.0, 0.1, b, h, dt)
+        f = 1.0 - sum(4 * a[d] * np.sin(theta[d] / 2) ** 2 for d in range(ndim))
+        f -= sum(bt * np.sin(theta[d]) * np.sin(theta[t]) for (d, t), bt in beta.items())
+        np.testing.assert_allclose(T1, f * T0, rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------- stability thresholds
+
+def _max_growth_3d(alpha, starts):
+    """max over unit b and wavenumbers of |r1 r2 r3| at chi dt/dx^2 = alpha
+    (dx = dy = dz), by local maximisation from the given starting points."""
+    from scipy.optimize import minimize
+
+    def neg(p):
+        b = unit([np.cos(p[0]) * np.sin(p[1]), np.sin(p[0]) * np.sin(p[1]), np.cos(p[1])])
+        th = p[2:5]
+        a = [alpha * b[d] ** 2 for d in range(3)]
+        beta = {(d, t): alpha * b[d] * b[t] for d in range(3) for t in range(3) if d != t}
+        return -abs(np.prod([_r_sweep(d, th, a, beta) for d in range(3)]))
+
+    best = 0.0
+    for s in starts:
+        res = minimize(neg, s, method="Nelder-Mead", options=dict(xatol=1e-10, fatol=1e-13, maxiter=20000))
+        best = max(best, -res.fun)
+    return best
+
+
+def test_3d_two_step_limit_matches_paper():
+    """The paper's 3-D limit chi dt/dx^2 <= 8.25 (section 2.1) follows from
+    the r1 r2 r3 reading: stable just below, unstable just above."""
+    gold = json.load(open(GOLDEN))["si_3d_stability_limit"]["value"]
+    rng = np.random.default_rng(11)
+    # a start near the worst mode found by a coarse scan, plus random starts
+    b = unit([-0.358, -0.358, -0.863])
+    th0 = np.arccos(b[2])
+    ph0 = np.arctan2(b[1], b[0])
+    starts = [np.array([ph0, th0, 0.526, 0.526, -0.672])]
+    starts += [np.concatenate([rng.uniform(0, 2 * np.pi, 1), rng.uniform(0, np.pi, 1),
+                               rng.uniform(-np.pi, np.pi, 3)]) for _ in range(6)]
+    assert _max_growth_3d(gold - 0.05, starts) <= 1.0 + 1e-9
+    assert _max_growth_3d(gold + 0.05, starts) > 1.0 + 1e-6
+
+
+def test_explicit_limits_match_paper():
+    """Linear-averaged explicit step: the largest stable alpha is 0.5 in 2-D
+    (section 1) and about 0.444 in 3-D (section 2.1)."""
+    gold = json.load(open(GOLDEN))
+    th = np.linspace(-np.pi, np.pi, 121)
+    # 2-D: scan b angle and both wavenumbers
+    worst2 = 0.0
+    for phi in np.linspace(0, np.pi, 91):
+        b = (np.cos(phi), np.sin(phi))
+        TX, TY = np.meshgrid(th, th)
+        g = 4 * b[0] ** 2 * np.sin(TX / 2) ** 2 + 4 * b[1] ** 2 * np.sin(TY / 2) ** 2 \
+            + 2 * b[0] * b[1] * np.sin(TX) * np.sin(TY)
+        worst2 = max(worst2, g.max())
+    limit2 = 2.0 / worst2
+    assert limit2 == pytest.approx(gold["explicit_2d_stability_limit"]["value"], abs=2e-3)
+    # 3-D: 1 - alpha*G(b, theta) >= -1  <=>  alpha <= 2/max G
+    rng = np.random.default_rng(5)
+    th3 = np.linspace(-np.pi, np.pi, 41)
+    TX, TY, TZ = np.meshgrid(th3, th3, th3, indexing="ij")
+    worst3 = 0.0
+    dirs = [unit(rng.standard_normal(3)) for _ in range(300)] + [unit([1, 1, 1]), unit([1, 1, -1])]
+    for b in dirs:
+        s = [np.sin(TX), np.sin(TY), np.sin(TZ)]
+        s2 = [np.sin(TX / 2) ** 2, np.sin(TY / 2) ** 2, np.sin(TZ / 2) ** 2]
+        G = sum(4 * b[d] ** 2 * s2[d] for d in range(3))
+        G = G + sum(2 * b[d] * b[t] * s[d] * s[t] for d in range(3) for t in range(d + 1, 3))
+        worst3 = max(worst3, G.max())
+    limit3 = 2.0 / worst3
+    assert limit3 == pytest.approx(gold["explicit_3d_stability_limit"]["value"], abs=4e-3)
+
+
+def test_3d_oracle_grows_above_limit_and_not_below(orc):
+    """32^3 periodic, linear averaging, constant b along the worst direction:
+    at alpha = 12 the worst grid mode grows at the closed-form rate; at
+    alpha = 8 a random field does not grow in L2 (section 2.1)."""
+    n = 16
+    shape = (n, n, n)
+    h = (1.0 / n,) * 3
+    b = unit([-0.358, -0.358, -0.863])
+    g = orc.OracleGrid(const_field(shape, b), h, limiter="linear")
+    # worst grid mode at alpha = 12 from the closed form
+    ks = range(-n // 2 + 1, n // 2)
+    best, kbest = 0.0, None
+    alpha = 12.0
+    a = [alpha * b[d] ** 2 for d in range(3)]
+    beta = {(d, t): alpha * b[d] * b[t] for d in range(3) for t in range(3) if d != t}
+    for k in itertools.product(ks, ks, ks):
+        th = [2 * np.pi * k[q] / n for q in range(3)]
+        r = abs(np.prod([_r_sweep(d, th, a, beta) for d in range(3)]))
+        if r > best:
+            best, kbest = r, k
+    assert best > 1.01
+    T0 = _mode(shape, _angles(shape, kbest))
+    T3 = g.step_si(T0, alpha * h[0] ** 2, 3)
+    growth = np.linalg.norm(T3) / np.linalg.norm(T0)
+    assert growth == pytest.approx(best ** 3, rel=1e-9)
+    rng = np.random.default_rng(0)
+    T0 = rng.standard_normal(shape)
+    T = g.step_si(T0, 8.0 * h[0] ** 2, 20)
+    assert np.linalg.norm(T) <= np.linalg.norm(T0) * (1 + 1e-12)
+
+
+# ------------------------------------------------------------ invariants
+
+def _random_unit_field(shape, rng):
+    v = [rng.standard_normal(shape) for _ in range(len(shape))]
+    m = np.sqrt(sum(c * c for c in v))
+    return [c / m for c in v]
+
+
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+@pytest.mark.parametrize("limiter", LIMITERS)
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_energy_conserved_to_roundoff(orc, bc, limiter, ndim):
+    """The scheme is conservative (abstract, section 1, section 4): total
+    energy sum T dV is unchanged up to rounding, for any b, chi, limiter."""
+    rng = np.random.default_rng(hash((bc, limiter, ndim)) % 2 ** 31)
+    shape = (13, 17) if ndim == 2 else (5, 7, 6)
+    nxyz = tuple(reversed(shape))
+    h = tuple(1.0 / n for n in nxyz)
+    b = _random_unit_field(shape, rng)
+    chi = np.exp(rng.standard_normal(shape))
+    T0 = 1.0 + rng.random(shape)
+    g = orc.OracleGrid(b, h, bc=bc, limiter=limiter, chi_perp=0.01, chi=chi)
+    dt = g.dt_from_ncfl(50.0)
+    _, e = g.step_si(T0, dt, 20, energy=True)
+    assert np.max(np.abs(e - e[0])) <= 1e-13 * abs(e[0])
+    dte = g.dt_from_ncfl(0.5 if ndim == 2 else 0.4)
+    _, e = g.step_explicit(T0, dte, 20, energy=True)
+    assert np.max(np.abs(e - e[0])) <= 1e-13 * abs(e[0])
+
+
+def _laplacian_1d(n, periodic):
+    L = np.zeros((n, n))
+    for i in range(n):
+        for s in (-1, 1):
+            j = i + s
+            if 0 <= j < n:
+                L[i, j] += 1
+                L[i, i] -= 1
+            elif periodic:
+                L[i, j % n] += 1
+                L[i, i] -= 1
+    return L
+
+
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+def test_field_along_x_is_1d_backward_euler(orc, bc):
+    """b = x_hat: the transverse terms vanish and each row is the textbook
+    backward-Euler heat step (1 - chi dt delta_x^2) x = T; the y sweep is the
+    identity (Eq. amp1 with b_y = 0)."""
+    rng = np.random.default_rng(4)
+    shape = (9, 23)
+    h = (0.03, 0.05)
+    g = orc.OracleGrid(const_field(shape, (1.0, 0.0)), h, bc=bc, chi_par=0.7)
+    T0 = rng.standard_normal(shape)
+    dt = 0.013
+    T1 = g.step_si(T0, dt, 1)
+    M = np.eye(23) - 0.7 * dt / h[0] ** 2 * _laplacian_1d(23, bc == "periodic")
+    ref = np.linalg.solve(M, T0.T).T
+    np.testing.assert_allclose(T1, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_isotropic_reduces_to_standard_stencils(orc, bc, ndim):
+    """chi_perp = chi_par makes D isotropic: the semi-implicit step is the
+    locally one-dimensional implicit split (I - dt chi d_z^2)^-1 ..
+    (I - dt chi d_x^2)^-1, and the explicit step is the 5-/7-point FTCS
+    stencil, whatever b is."""
+    rng = np.random.default_rng(5 + ndim)
+    shape = (7, 11) if ndim == 2 else (4, 5, 6)
+    nxyz = tuple(reversed(shape))
+    h = tuple(0.1 * (q + 1) for q in range(ndim))
+    chi = 0.8
+    g = orc.OracleGrid(_random_unit_field(shape, rng), h, bc=bc, chi_par=chi, chi_perp=chi)
+    T0 = rng.standard_normal(shape)
+    dt = 0.37
+    per = bc == "periodic"
+    eyes = [np.eye(n) for n in nxyz]
+
+    def axis_op(d):
+        mats = [eyes[q] if q != d else _laplacian_1d(nxyz[q], per) / h[q] ** 2 for q in range(ndim)]
+        # kron in (z, y, x) order so that x is the fastest index
+        M = mats[ndim - 1]
+        for q in range(ndim - 2, -1, -1):
+            M = np.kron(M, mats[q])
+        return M
+
+    N = T0.size
+    x = T0.ravel()
+    for d in range(ndim):
+        x = np.linalg.solve(np.eye(N) - dt * chi * axis_op(d), x)
+    np.testing.assert_allclose(g.step_si(T0, dt, 1).ravel(), x, rtol=1e-11, atol=1e-12)
+    dte = 0.2 * min(h) ** 2 / chi
+    ref = T0.ravel() + dte * chi * sum(axis_op(d) for d in range(ndim)) @ T0.ravel()
+    np.testing.assert_allclose(g.step_explicit(T0, dte, 1).ravel(), ref, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("limiter", ["vanleer", "minmod", "mc"])
+def test_two_level_field_has_no_transverse_flux(orc, limiter):
+    """A two-level field has no three-cell window with two same-signed
+    differences, so every limited transverse difference is zero: the first x
+    sweep equals the pure normal solve (section 3.1: the first step respects
+    monotonicity because every point is an extremum)."""
+    rng = np.random.default_rng(6)
+    shape = (20, 18)
+    h = (1 / 18, 1 / 20)
+    b = _random_unit_field(shape, rng)
+    T0 = np.where(rng.random(shape) < 0.5, 0.1, 10.0)
+    for bc in ("periodic", "insulating"):
+        g = orc.OracleGrid(b, h, bc=bc, limiter=limiter)
+        g0 = orc.OracleGrid([b[0], np.zeros(shape)], h, bc=bc, limiter=limiter)
+        dt = g.dt_from_ncfl(100.0)
+        np.testing.assert_array_equal(g.sweep(0, dt, T0), g0.sweep(0, dt, T0))
+        # and the transverse term is active on a smooth field (not vacuous)
+        Ts = synth.smoothed_normal(shape, 3, 2.0)
+        assert np.max(np.abs(g.sweep(0, dt, Ts) - g0.sweep(0, dt, Ts))) > 1e-6
+
+
+def _strict_extrema(T, periodic):
+    ny, nx = T.shape
+    mx, mn = [], []
+    for j in range(ny):
+        for i in range(nx):
+            nb = []
+            for dj, di in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                jj, ii = j + dj, i + di
+                if periodic:
+                    jj, ii = jj % ny, ii % nx
+                elif not (0 <= jj < ny and 0 <= ii < nx):
+                    continue
+                nb.append(T[jj, ii])
+            if all(T[j, i] > v for v in nb):
+                mx.append((j, i))
+            if all(T[j, i] < v for v in nb):
+                mn.append((j, i))
+    return mx, mn
+
+
+@pytest.mark.parametrize("limiter", ["vanleer", "minmod", "mc"])
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+def test_explicit_does_not_accentuate_extrema(orc, limiter, bc):
+    """Explicit limited step inside its CFL step: at a strict 5-point local
+    maximum (minimum) of T^n the limited transverse differences vanish, so
+    T^{n+1} <= T^n (>=) there (section 3.1; sec. 1 on limiters)."""
+    rng = np.random.default_rng(8)
+    shape = (40, 48)
+    h = (1 / 48, 1 / 40)
+    b = _random_unit_field(shape, rng)
+    T0 = 1.0 + rng.random(shape)
+    g = orc.OracleGrid(b, h, bc=bc, limiter=limiter, chi_perp=0.0)
+    dt = g.dt_from_ncfl(1.0)
+    T1 = g.step_explicit(T0, dt, 1)
+    mx, mn = _strict_extrema(T0, bc == "periodic")
+    assert len(mx) > 20 and len(mn) > 20
+    for j, i in mx:
+        assert T1[j, i] <= T0[j, i]
+    for j, i in mn:
+        assert T1[j, i] >= T0[j, i]
+
+
+def test_unlimited_explicit_can_accentuate_extrema(orc):
+    """Negative control for the previous pin: with plain averaging (no
+    limiter) some strict extremum is accentuated (section 1)."""
+    rng = np.random.default_rng(8)
+    shape = (40, 48)
+    h = (1 / 48, 1 / 40)
+    b = _random_unit_field(shape, rng)
+    T0 = 1.0 + rng.random(shape)
+    g = orc.OracleGrid(b, h, bc="periodic", limiter="linear")
+    T1 = g.step_explicit(T0, g.dt_from_ncfl(1.0), 1)
+    mx, mn = _strict_extrema(T0, True)
+    bad = sum(T1[j, i] > T0[j, i] for j, i in mx) + sum(T1[j, i] < T0[j, i] for j, i in mn)
+    assert bad > 0
+
+
+# -------------------------------------------------------------- accuracy
+
+def test_spreading_gaussian_converges_second_order(orc):
+    """b = x_hat: T = 1 + (s0/s_t) exp(-(x-x0)^2/(2 s_t^2)), s_t^2 = s0^2 +
+    2 chi t.  At fixed ncfl (dt ~ dx^2) the L1 error falls ~4x per doubling
+    (second order in space, first order in time, Eq. amp and section 2.1)."""
+    s0, chi, t_end, ncfl = 0.05, 1.0, 0.004, 4.0
+    errs = []
+    for nx in (64, 128, 256):
+        ny = 3
+        h = (1.0 / nx, 1.0 / ny)
+        T0 = synth.gaussian_pulse_x(nx, ny, s0)
+        g = orc.OracleGrid(const_field((ny, nx), (1.0, 0.0)), h, chi_par=chi)
+        dt0 = ncfl * h[0] ** 2 / (4 * chi)
+        nsteps = int(round(t_end / dt0))
+        dt = t_end / nsteps
+        T = g.step_si(T0, dt, nsteps)
+        ref = synth.gaussian_pulse_x(nx, ny, s0, t=t_end, chi=chi)
+        errs.append(np.mean(np.abs(T - ref)))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    for r in ratios:
+        assert 3.3 < r < 4.7, (errs, ratios)
+
+
+# ----------------------------------------------------------- brute force
+
+def _brute_force_step(b, h, bc, limiter, T, dt, chi=1.0):
+    """Dense assembly of each sweep from the face definitions (section 2):
+    A_d = I + sum_faces alpha_f (e_c - e_c')(e_c - e_c')^T and the explicit
+    part S_d(U) = sum_faces F_f (e_c - e_c'), with coordinates handled by an
+    explicit neighbour table."""
+    shape = T.shape
+    nd = len(shape)
+    nxyz = tuple(reversed(shape))
+    N = T.size
+    coords = list(itertools.product(*[range(n) for n in reversed(nxyz)]))  # (z,y,x) order
+    index = {c: k for k, c in enumerate(coords)}
+
+    def lim2(a, c):
+        if limiter == "linear":
+            return 0.5 * (a + c)
+        if a * c <= 0:
+            return 0.0
+        if limiter == "vanleer":
+            return 2 * a * c / (a + c)
+        if limiter == "minmod":
+            return np.sign(a) * min(abs(a), abs(c))
+        return np.sign(a) * min(2 * abs(a), 2 * abs(c), abs(a + c) / 2)
+
+    def shift(c, axis, s):
+        # c in (.., y, x) order; axis 0 = x
+        pos = list(c)
+        k = nd - 1 - axis
+        m = pos[k] + s
+        if m < 0 or m >= nxyz[axis]:
+            if bc == "periodic":
+                m %= nxyz[axis]
+            else:
+                return None
+        pos[k] = m
+        return tuple(pos)
+
+    def val(U, c, axis, s):
+        c2 = shift(c, axis, s)
+        return U[index[c]] if c2 is None else U[index[c2]]  # mirror ghost at walls
+
+    x = T.ravel().copy()
+    bf = [bb.ravel() for bb in b]
+    for d in range(nd):
+        U = x.copy()
+        A = np.eye(N)
+        S = np.zeros(N)
+        for c in coords:
+            c1 = shift(c, d, +1)
+            if c1 is None:
+                continue  # wall face: no flux
+            k0, k1 = index[c], index[c1]
+            bface = [0.5 * (bf[q][k0] + bf[q][k1]) for q in range(nd)]
+            alpha = dt * chi * bface[d] ** 2 / h[d] ** 2
+            e = np.zeros(N)
+            e[k0], e[k1] = 1.0, -1.0
+            A += alpha * np.outer(e, e)
+            F = 0.0
+            for t in range(nd):
+                if t == d:
+                    continue
+                p1 = lim2(val(U, c1, t, +1) - U[k1], U[k1] - val(U, c1, t, -1))
+                p0 = lim2(val(U, c, t, +1) - U[k0], U[k0] - val(U, c, t, -1))
+                F += dt * chi * bface[d] * bface[t] / (h[d] * h[t]) * lim2(p1, p0)
+            S += F * e
+        x = np.linalg.solve(A, U + S)
+    return x.reshape(shape)
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (3, 3, 3), (3, 5), (4, 3, 3)])
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+@pytest.mark.parametrize("limiter", LIMITERS)
+def test_brute_force_dense_step(orc, shape, bc, limiter):
+    rng = np.random.default_rng(len(shape) * 100 + shape[0])
+    nxyz = tuple(reversed(shape))
+    h = tuple(0.1 + 0.05 * q for q in range(len(shape)))
+    b = _random_unit_field(shape, rng)
+    T0 = rng.random(shape) + 0.5
+    dt = 0.04
+    g = orc.OracleGrid(b, h, bc=bc, limiter=limiter)
+    ref = T0
+    for _ in range(3):
+        ref = _brute_force_step(b, h, bc, limiter, ref, dt)
+    np.testing.assert_allclose(g.step_si(T0, dt, 3), ref, rtol=1e-12, atol=1e-13)
+    assert nxyz  # shape used
+
+
+# ----------------------------------------------------- paper behaviours
+
+def test_ring_first_step_respects_monotonicity(orc):
+    """Section 3.1: the minimum temperature respects the monotonicity bound
+    on the first step (every point of the two-level initial state is an
+    extremum, so the transverse term of the first sweep vanishes)."""
+    gold = json.load(open(GOLDEN))
+    t_in, t_out = gold["ring_temperatures"]["value"]
+    p = synth.ring_problem(n=128, t_in=t_in, t_out=t_out, ncfl=1000.0, nsteps=1)
+    g = orc.OracleGrid(p.b, p.h, bc=p.bc, chi_par=p.chi_par)
+    T1 = g.step_si(p.T0, p.dt, 1)
+    assert T1.min() >= t_out * (1 - 1e-12)
+
+
+@pytest.mark.slow
+def test_ring_512_min_temperature_matches_paper(orc):
+    """Section 3.1, ring 10/0.1 on 512^2 to t = 20: at ncfl = 1000 the minimum
+    over time is about 0.08 (relative non-monotonicity ~0.2, Fig. tmin_nx),
+    and T stays positive up to ncfl = 10^4 (Fig. tmin)."""
+    gold = json.load(open(GOLDEN))
+    t_in, t_out = gold["ring_temperatures"]["value"]
+    t_end = gold["ring_t_end"]["value"]
+    res = {}
+    for ncfl in (1000.0, 1e4):
+        p = synth.ring_problem(n=512, t_in=t_in, t_out=t_out, ncfl=ncfl, nsteps=0)
+        g = orc.OracleGrid(p.b, p.h, bc=p.bc, chi_par=p.chi_par)
+        nsteps = int(np.ceil(t_end / p.dt))
+        T, tmin = p.T0, p.T0.min()
+        for _ in range(nsteps):
+            T = g.step_si(T, p.dt, 1)
+            tmin = min(tmin, T.min())
+        res[ncfl] = tmin
+    m = gold["ring_si_ncfl1000_min"]["value"]
+    assert 0.5 * m < res[1000.0] < 0.1 * (1 - 1e-3) + 1e-12, res
+    assert res[1e4] > 0.0, res
