@@ -1,0 +1,74 @@
+/*
+ * asd_extra.h — batched problems, launch tuning and measurement helpers of
+ * libasd.  Same conventions as asd.h (status codes, borrowed memory,
+ * caller-provided workspace, stream-ordered enqueue).
+ */
+#ifndef ASD_EXTRA_H
+#define ASD_EXTRA_H
+
+#include "asd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ batch
+ * Many independent 2-D problems of uneven sizes advanced together: the
+ * semi-implicit step of asd.h (section 2, Eqs. xup / yup) applied to each
+ * problem with its own grid, b field, chi_par and dt.  Problems share bc,
+ * dtype and limiter (taken from descs[0]); each desc gives n, h, chi_par,
+ * chi_perp of its problem.  FP32 or FP64; ndim must be 2. */
+typedef struct asd_batch_s *asd_batch;
+
+/* Workspace bytes for nprob problems (descs: host array of nprob). */
+int asd_batch_workspace_bytes(const asd_desc *descs, int32_t nprob, size_t *bytes);
+
+/* Create a batch; dev_ws as for asd_init_grid.  No device work is enqueued. */
+int asd_batch_init(const asd_desc *descs, int32_t nprob, void *dev_ws, size_t ws_bytes, void *stream,
+                   asd_batch *out);
+
+/* Borrow the device arrays of problem p (T advanced in place; bx, by read at
+ * the next step call) and set its time step dt (> 0, finite). */
+int asd_batch_set_problem(asd_batch b, int32_t p, void *dev_T, void *dev_bx, void *dev_by, double dt);
+
+/* nsteps steps of every problem.  mode 0: one persistent launch for all
+ * problems and all steps (work-groups own whole problems, assigned largest
+ * first); mode 1: one launch per problem per sweep (the sequential
+ * reference). */
+int asd_batch_step(asd_batch b, int32_t nsteps, int32_t mode);
+
+int asd_batch_destroy(asd_batch b);
+
+/* ----------------------------------------------------------------- tuning
+ * Launch shape of the sweep along `axis`: waves per line (wpl), lines per
+ * work-group (lpw), segments per line (P) and per-lane capacity (mmax). */
+int asd_get_sweep_config(asd_grid g, int32_t axis, int32_t *wpl, int32_t *lpw, int32_t *P, int32_t *mmax);
+
+/* Request a launch shape (wpl, lpw powers of two); EUNSUPPORTED if it does
+ * not fit the register or LDS budget. */
+int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw);
+
+/* Time every admissible (wpl, lpw) of each sweep on the grid's stream with
+ * HIP events (reps launches each, T -> workspace, T unchanged) and keep the
+ * fastest.  Needs T and b set.  Synchronises the stream. */
+int asd_tune(asd_grid g, double dt, int32_t reps);
+
+/* Enable (1) or disable (0) hipGraph capture of multi-step calls. */
+int asd_set_graphs(asd_grid g, int32_t on);
+
+/* ------------------------------------------------------------ measurement
+ * Time one sweep kernel in isolation.  reps == 0: enqueue one sweep chain
+ * from T into the workspace so that every sweep's input holds a valid
+ * state.  reps > 0: enqueue reps launches of the sweep along `axis`, from
+ * its input state to a workspace buffer.  T is never written. */
+int asd_bench_sweep(asd_grid g, int32_t axis, double dt, int32_t reps);
+
+/* Plain streaming copy of nbytes (multiple of 4) from src to dst on stream:
+ * the calibration kernel for HBM byte counters. */
+int asd_bench_copy(const void *src, void *dst, size_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASD_EXTRA_H */

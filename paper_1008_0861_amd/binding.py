@@ -1,0 +1,276 @@
+"""ctypes binding of libasd (include/asd.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels
+of libasd.so.  torch provides device memory (tensors, workspace) and the
+stream; nothing here computes any part of the scheme.  If the compiled
+library is missing, loading fails loudly: there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libasd.so")
+
+# status codes
+OK = 0
+ERRORS = {
+    -1: "EINVAL", -2: "ESHAPE", -3: "EDTYPE", -4: "ENOTSET", -5: "EWORKSPACE",
+    -6: "EUNSTABLE", -7: "EHIP", -8: "EUNSUPPORTED",
+}
+BC = {"periodic": 0, "insulating": 1}
+LIMITER = {"vanleer": 0, "minmod": 1, "mc": 2, "linear": 3}
+F32, F64 = 0, 1
+FIELD = {"T": 0, "bx": 1, "by": 2, "bz": 3, "chi": 4}
+FLAG_PER_CELL_CHI = 1
+FLAG_ALLOW_UNSTABLE = 2
+STATUS_NONFINITE, STATUS_NEG_T, STATUS_ENERGY_DRIFT = 1, 2, 4
+
+# every entry point of include/asd.h and include/asd_extra.h
+EXPORTED = [
+    "asd_last_error", "asd_workspace_bytes", "asd_init_grid", "asd_set_field",
+    "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_adjoint_workspace_bytes",
+    "asd_adjoint_step", "asd_status", "asd_destroy",
+    "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
+    "asd_batch_destroy",
+    "asd_get_sweep_config", "asd_set_sweep_config", "asd_tune", "asd_set_graphs",
+    "asd_bench_sweep", "asd_bench_copy",
+]
+
+
+class AsdError(RuntimeError):
+    def __init__(self, code, msg):
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+        super().__init__(f"{self.name}: {msg}")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("bc", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("limiter", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("h", ctypes.c_double * 3),
+        ("chi_par", ctypes.c_double),
+        ("chi_perp", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libasd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run python -m paper_1008_0861_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        P = ctypes.POINTER
+        sig = {
+            "asd_last_error": (ctypes.c_char_p, []),
+            "asd_workspace_bytes": (ctypes.c_int, [P(Desc), P(sz)]),
+            "asd_init_grid": (ctypes.c_int, [P(Desc), vp, sz, vp, P(vp)]),
+            "asd_set_field": (ctypes.c_int, [vp, i32, vp, i64, i32]),
+            "asd_step_semi_implicit": (ctypes.c_int, [vp, dbl, i32, vp]),
+            "asd_step_explicit_limited": (ctypes.c_int, [vp, dbl, i32, vp]),
+            "asd_adjoint_workspace_bytes": (ctypes.c_int, [vp, i32, i32, P(sz)]),
+            "asd_adjoint_step": (ctypes.c_int, [vp, dbl, i32, i32, vp, vp, vp, vp, vp, sz]),
+            "asd_status": (ctypes.c_int, [vp, P(ctypes.c_uint32), P(dbl)]),
+            "asd_destroy": (ctypes.c_int, [vp]),
+            "asd_batch_workspace_bytes": (ctypes.c_int, [P(Desc), i32, P(sz)]),
+            "asd_batch_init": (ctypes.c_int, [P(Desc), i32, vp, sz, vp, P(vp)]),
+            "asd_batch_set_problem": (ctypes.c_int, [vp, i32, vp, vp, vp, dbl]),
+            "asd_batch_step": (ctypes.c_int, [vp, i32, i32]),
+            "asd_batch_destroy": (ctypes.c_int, [vp]),
+            "asd_get_sweep_config": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
+            "asd_set_sweep_config": (ctypes.c_int, [vp, i32, i32, i32]),
+            "asd_tune": (ctypes.c_int, [vp, dbl, i32]),
+            "asd_set_graphs": (ctypes.c_int, [vp, i32]),
+            "asd_bench_sweep": (ctypes.c_int, [vp, i32, dbl, i32]),
+            "asd_bench_copy": (ctypes.c_int, [vp, vp, sz, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().asd_last_error().decode(errors="replace")
+
+
+def check(rc):
+    if rc != OK:
+        raise AsdError(rc, last_error())
+    return rc
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float32:
+        return F32
+    if dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0, chi_perp=0.0,
+              per_cell_chi=False, allow_unstable=False):
+    """Build an asd_desc.  shape is (ny, nx) or (nz, ny, nx), h is (hx, hy[, hz])."""
+    d = Desc()
+    d.ndim = len(shape)
+    d.bc = BC[bc]
+    d.dtype = _dtype_code(dtype)
+    d.limiter = LIMITER[limiter]
+    nxyz = list(reversed(shape)) + [1] * (3 - len(shape))
+    for q in range(3):
+        d.n[q] = int(nxyz[q])
+        d.h[q] = float(h[q]) if q < len(h) else 1.0
+    d.chi_par = float(chi_par)
+    d.chi_perp = float(chi_perp)
+    d.flags = (FLAG_PER_CELL_CHI if per_cell_chi else 0) | (FLAG_ALLOW_UNSTABLE if allow_unstable else 0)
+    d.reserved = 0
+    return d
+
+
+def workspace_bytes(desc):
+    n = ctypes.c_size_t()
+    check(lib().asd_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+class Grid:
+    """A problem on the GPU: owns the workspace tensor and the library handle.
+
+    Fields are torch tensors on the GPU with the grid's dtype and shape
+    (ny, nx) / (nz, ny, nx), contiguous.  The handle keeps references to them.
+    """
+
+    def __init__(self, shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0,
+                 chi_perp=0.0, per_cell_chi=False, allow_unstable=False, device="cuda", stream=None):
+        self.shape = tuple(int(s) for s in shape)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.desc = make_desc(self.shape, h, bc, dtype, limiter, chi_par, chi_perp, per_cell_chi, allow_unstable)
+        nbytes = workspace_bytes(self.desc)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._stream_ptr, self.stream = _stream_handle(stream)
+        h_out = ctypes.c_void_p()
+        check(lib().asd_init_grid(ctypes.byref(self.desc), ctypes.c_void_p(self.workspace.data_ptr()),
+                                  nbytes, self._stream_ptr, ctypes.byref(h_out)))
+        self.handle = h_out
+        self.fields = {}
+
+    @property
+    def ncells(self):
+        n = 1
+        for s in self.shape:
+            n *= s
+        return n
+
+    def _check_tensor(self, t):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError("fields must be CUDA tensors")
+        if t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"field must be contiguous {self.dtype} of shape {self.shape}")
+
+    def set_field(self, name, t):
+        self._check_tensor(t)
+        check(lib().asd_set_field(self.handle, FIELD[name], ctypes.c_void_p(t.data_ptr()), t.numel(),
+                                  _dtype_code(t.dtype)))
+        self.fields[name] = t
+
+    def set_b(self, *comps):
+        for name, c in zip(("bx", "by", "bz"), comps):
+            self.set_field(name, c)
+
+    @property
+    def T(self):
+        return self.fields["T"]
+
+    def step_semi_implicit(self, dt, nsteps=1, energy=False):
+        e = torch.empty(nsteps + 1, dtype=torch.float64, device=self.device) if energy else None
+        check(lib().asd_step_semi_implicit(self.handle, float(dt), int(nsteps),
+                                           ctypes.c_void_p(e.data_ptr()) if e is not None else None))
+        return e
+
+    def step_explicit(self, dt, nsteps=1, energy=False):
+        e = torch.empty(nsteps + 1, dtype=torch.float64, device=self.device) if energy else None
+        check(lib().asd_step_explicit_limited(self.handle, float(dt), int(nsteps),
+                                              ctypes.c_void_p(e.data_ptr()) if e is not None else None))
+        return e
+
+    def status(self):
+        f = ctypes.c_uint32()
+        st = (ctypes.c_double * 3)()
+        check(lib().asd_status(self.handle, ctypes.byref(f), st))
+        return f.value, (st[0], st[1], st[2])
+
+    def adjoint(self, dt, nsteps, ckpt_every, T0, lam, grad_chi=True):
+        """dL/dT0 (and dL/dchi) of nsteps semi-implicit steps from T0, given lam = dL/dT_N."""
+        self._check_tensor(T0)
+        self._check_tensor(lam)
+        gT = torch.empty_like(T0)
+        gC = torch.empty_like(T0) if grad_chi else None
+        n = ctypes.c_size_t()
+        check(lib().asd_adjoint_workspace_bytes(self.handle, int(nsteps), int(ckpt_every), ctypes.byref(n)))
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        check(lib().asd_adjoint_step(self.handle, float(dt), int(nsteps), int(ckpt_every),
+                                     ctypes.c_void_p(T0.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                     ctypes.c_void_p(gT.data_ptr()),
+                                     ctypes.c_void_p(gC.data_ptr()) if gC is not None else None,
+                                     ctypes.c_void_p(ws.data_ptr()), n.value))
+        self._adj_ws = ws  # keep alive until the stream has used it
+        return gT, gC
+
+    def sweep_config(self, axis):
+        w, l, p, m = (ctypes.c_int32() for _ in range(4))
+        check(lib().asd_get_sweep_config(self.handle, int(axis), ctypes.byref(w), ctypes.byref(l),
+                                         ctypes.byref(p), ctypes.byref(m)))
+        return dict(wpl=w.value, lpw=l.value, P=p.value, mmax=m.value)
+
+    def set_sweep_config(self, axis, wpl, lpw):
+        check(lib().asd_set_sweep_config(self.handle, int(axis), int(wpl), int(lpw)))
+
+    def tune(self, dt, reps=20):
+        check(lib().asd_tune(self.handle, float(dt), int(reps)))
+        return [self.sweep_config(a) for a in range(len(self.shape))]
+
+    def set_graphs(self, on):
+        check(lib().asd_set_graphs(self.handle, 1 if on else 0))
+
+    def bench_sweep(self, axis, dt, reps):
+        """Enqueue reps launches of one sweep kernel (T -> scratch) for timing."""
+        check(lib().asd_bench_sweep(self.handle, int(axis), float(dt), int(reps)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().asd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bench_copy(src, dst, stream=None):
+    """Plain device copy kernel of src.numel()*itemsize bytes (counter calibration)."""
+    sp, _ = _stream_handle(stream)
+    check(lib().asd_bench_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                               src.numel() * src.element_size(), sp))

@@ -1,0 +1,158 @@
+// Launch-shape control, the autotuner and single-kernel measurement helpers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "../../include/asd_extra.h"
+#include "asd_internal.h"
+
+using namespace asd;
+
+extern "C" int asd_get_sweep_config(asd_grid g, int32_t axis, int32_t* wpl, int32_t* lpw, int32_t* P,
+                                    int32_t* mmax) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
+    if (!wpl || !lpw || !P || !mmax) return asd_fail(ASD_EINVAL, "NULL output");
+    const SweepCfg& c = g->cfg[axis];
+    *wpl = c.wpl;
+    *lpw = c.lpw;
+    *P = c.P;
+    *mmax = c.mmax;
+    return ASD_OK;
+}
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+extern "C" int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
+    if (!is_pow2(wpl) || !is_pow2(lpw)) return asd_fail(ASD_EINVAL, "wpl and lpw must be powers of two");
+    SweepCfg c;
+    const bool chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) != 0;
+    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c) || c.wpl != wpl ||
+        c.lpw != lpw)
+        return asd_fail(ASD_EUNSUPPORTED, "launch shape wpl=%d lpw=%d does not fit", wpl, lpw);
+    g->cfg[axis] = c;
+    g->graph_valid = false;
+    return ASD_OK;
+}
+
+extern "C" int asd_set_graphs(asd_grid g, int32_t on) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    g->use_graphs = on != 0;
+    g->graph_valid = false;
+    return ASD_OK;
+}
+
+// Buffers of sweep `axis` run in isolation: input = the state that sweep
+// reads during a step (T for the first sweep, else a scratch state), output
+// = a scratch state that no later timed launch reads.  T is never written.
+static void bench_buffers(asd_grid g, int axis, const void** in, void** out) {
+    if (axis == 0) {
+        *in = g->T;
+        *out = g->tmp[0];
+    } else if (axis == 1) {
+        *in = g->tmp[0];
+        *out = g->tmp[1];
+    } else {
+        *in = g->tmp[1];
+        *out = g->tmp[0];
+    }
+}
+
+// Fill the scratch inputs of sweeps 1.. with one real sweep chain from T.
+static int bench_prepare_inputs(asd_grid g, double dt) {
+    for (int axis = 0; axis + 1 < g->d.ndim; ++axis) {
+        const void* in = axis == 0 ? g->T : g->tmp[axis - 1];
+        int rc = enqueue_sweep(g, axis, dt, in, g->tmp[axis], 0, no_reduce(), nullptr);
+        if (rc) return rc;
+    }
+    return ASD_OK;
+}
+
+extern "C" int asd_bench_sweep(asd_grid g, int32_t axis, double dt, int32_t reps) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
+    if (!(std::isfinite(dt) && dt > 0.0)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
+    if (reps < 0) return asd_fail(ASD_EINVAL, "reps must be >= 0");
+    int rc = check_fields(g, true);
+    if (rc) return rc;
+    rc = prepare(g);
+    if (rc) return rc;
+    if (reps == 0) return bench_prepare_inputs(g, dt);
+    const void* in;
+    void* out;
+    bench_buffers(g, axis, &in, &out);
+    for (int r = 0; r < reps; ++r) {
+        rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), nullptr);
+        if (rc) return rc;
+    }
+    return ASD_OK;
+}
+
+extern "C" int asd_bench_copy(const void* src, void* dst, size_t nbytes, void* stream) {
+    if (!src || !dst) return asd_fail(ASD_EINVAL, "NULL pointer");
+    if (nbytes % 4) return asd_fail(ASD_EINVAL, "nbytes must be a multiple of 4");
+    hipError_t e = launch_copy<float>((const float*)src, (float*)dst, (int64_t)(nbytes / 4), (hipStream_t)stream);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "copy launch: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+
+static int time_cfg(asd_grid g, int axis, double dt, int reps, const SweepCfg& c, float* ms) {
+    const void* in;
+    void* out;
+    bench_buffers(g, axis, &in, &out);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return asd_fail(ASD_EHIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return asd_fail(ASD_EHIP, "event create");
+    }
+    int rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), &c);  // warm-up
+    if (!rc && hipEventRecord(e0, g->st) != hipSuccess) rc = asd_fail(ASD_EHIP, "event record");
+    for (int r = 0; !rc && r < reps; ++r) rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), &c);
+    if (!rc && hipEventRecord(e1, g->st) != hipSuccess) rc = asd_fail(ASD_EHIP, "event record");
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = asd_fail(ASD_EHIP, "event sync");
+    if (!rc && hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = asd_fail(ASD_EHIP, "elapsed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (!(std::isfinite(dt) && dt > 0.0)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
+    if (reps < 1) return asd_fail(ASD_EINVAL, "reps must be >= 1");
+    int rc = check_fields(g, true);
+    if (rc) return rc;
+    rc = prepare(g);
+    if (rc) return rc;
+    const bool chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) != 0;
+    rc = bench_prepare_inputs(g, dt);  // T itself is untouched
+    if (rc) return rc;
+    for (int axis = 0; axis < g->d.ndim; ++axis) {
+        SweepCfg best = g->cfg[axis];
+        float best_ms = 1e30f;
+        for (int wpl = 1; wpl <= 16; wpl *= 2) {
+            for (int lpw = 1; wpl * lpw <= 16; lpw *= 2) {
+                SweepCfg c;
+                if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c)) continue;
+                if (c.wpl != wpl || c.lpw != lpw) continue;
+                // sweeps whose blocks exceed the reduction scratch are fine here
+                float ms = 0.f;
+                rc = time_cfg(g, axis, dt, reps, c, &ms);
+                if (rc) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+        g->cfg[axis] = best;
+    }
+    g->graph_valid = false;
+    return ASD_OK;
+}

@@ -1,0 +1,510 @@
+// C ABI of libasd: argument validation, workspace carve-up, data layouts
+// and the step drivers that enqueue the gfx950 kernels.
+//
+// Layouts.  The user's arrays are x-fastest ("A").  Each sweep reads its
+// input with the sweep axis contiguous and writes its output transposed so
+// that the next sweep's axis is contiguous again:
+//   2-D:  x-sweep  A=[y][x] -> B=[x][y];  y-sweep B -> A
+//   3-D:  x-sweep  A=[z][y][x] -> B=[z][x][y];  y-sweep B -> C=[y][x][z];
+//         z-sweep  C -> A
+// b (and a per-cell chi) are static, so their B and C copies are made once
+// per asd_set_field, in the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "../../include/asd.h"
+#include "asd_launch.h"
+#include "asd_internal.h"
+
+using namespace asd;
+
+static thread_local std::string g_err;
+
+int asd_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return ASD_OK;
+    return asd_fail(ASD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* asd_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------ description
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+static int validate_desc(const asd_desc* d) {
+    if (!d) return asd_fail(ASD_EINVAL, "desc is NULL");
+    if (d->ndim != 2 && d->ndim != 3) return asd_fail(ASD_EINVAL, "ndim must be 2 or 3 (got %d)", d->ndim);
+    if (d->bc != ASD_BC_PERIODIC && d->bc != ASD_BC_INSULATING)
+        return asd_fail(ASD_EINVAL, "bad boundary condition %d", d->bc);
+    if (d->dtype != ASD_F32 && d->dtype != ASD_F64) return asd_fail(ASD_EINVAL, "bad dtype %d", d->dtype);
+    if (d->limiter < ASD_LIM_VANLEER || d->limiter > ASD_LIM_LINEAR)
+        return asd_fail(ASD_EINVAL, "bad limiter %d", d->limiter);
+    if (d->reserved != 0) return asd_fail(ASD_EINVAL, "reserved must be 0");
+    if (d->flags & ~(ASD_FLAG_PER_CELL_CHI | ASD_FLAG_ALLOW_UNSTABLE))
+        return asd_fail(ASD_EINVAL, "unknown flags 0x%x", d->flags);
+    const int64_t nmin = d->bc == ASD_BC_PERIODIC ? 3 : 2;
+    for (int q = 0; q < d->ndim; ++q) {
+        if (d->n[q] < nmin)
+            return asd_fail(ASD_ESHAPE, "n[%d] = %lld, need >= %lld for this boundary", q,
+                            (long long)d->n[q], (long long)nmin);
+        if (d->n[q] > (1 << 20)) return asd_fail(ASD_EUNSUPPORTED, "n[%d] too large", q);
+        if (!finite_pos(d->h[q])) return asd_fail(ASD_EINVAL, "h[%d] must be finite and > 0", q);
+    }
+    if (d->ndim == 2 && d->n[2] != 1) return asd_fail(ASD_ESHAPE, "n[2] must be 1 in 2-D");
+    if (!finite_pos(d->chi_par)) return asd_fail(ASD_EINVAL, "chi_par must be finite and > 0");
+    if (!std::isfinite(d->chi_perp) || d->chi_perp < 0.0 || d->chi_perp > d->chi_par)
+        return asd_fail(ASD_EINVAL, "chi_perp must be in [0, chi_par]");
+    const int64_t N = d->n[0] * d->n[1] * (d->ndim == 3 ? d->n[2] : 1);
+    if (N > (int64_t)1 << 34) return asd_fail(ASD_EUNSUPPORTED, "grid too large");
+    for (int q = 0; q < d->ndim; ++q) {
+        SweepCfg c;
+        if (!choose_sweep_cfg(d->dtype == ASD_F64 ? 8 : 4, d->ndim, (int)d->n[q],
+                              (d->flags & ASD_FLAG_PER_CELL_CHI) != 0, 0, 0, &c))
+            return asd_fail(ASD_EUNSUPPORTED, "lines of %lld cells along axis %d do not fit in LDS",
+                            (long long)d->n[q], q);
+    }
+    return ASD_OK;
+}
+
+static int64_t cells(const asd_desc* d) { return d->n[0] * d->n[1] * (d->ndim == 3 ? d->n[2] : 1); }
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace plan: offsets of each region.
+struct WsPlan {
+    size_t tmp[2], bl[3][3], chil[3], partials, small, total;
+    int64_t max_blocks;
+};
+
+static int64_t max_reduce_blocks(const asd_desc* d) {
+    // sweeps at their smallest (one line per block), explicit tiles, reductions
+    int64_t N = cells(d), mb = 1024;
+    for (int q = 0; q < d->ndim; ++q) mb = std::max<int64_t>(mb, N / d->n[q]);
+    int n[3] = {(int)d->n[0], (int)d->n[1], d->ndim == 3 ? (int)d->n[2] : 1};
+    mb = std::max<int64_t>(mb, explicit_num_blocks(d->ndim, n));
+    return mb;
+}
+
+static WsPlan plan_ws(const asd_desc* d) {
+    WsPlan p{};
+    const size_t es = d->dtype == ASD_F64 ? 8 : 4;
+    const size_t fb = align256((size_t)cells(d) * es);
+    size_t off = 0;
+    const int ntmp = 2;  // sweep intermediates / explicit ping-pong / benchmark outputs
+    for (int i = 0; i < 2; ++i) p.tmp[i] = (size_t)-1;
+    for (int i = 0; i < ntmp; ++i) { p.tmp[i] = off; off += fb; }
+    for (int L = 0; L < 3; ++L) {
+        for (int q = 0; q < 3; ++q) p.bl[L][q] = (size_t)-1;
+        p.chil[L] = (size_t)-1;
+    }
+    const int nlay = d->ndim == 3 ? 3 : 2;  // layout 0 is the user's
+    for (int L = 1; L < nlay; ++L) {
+        for (int q = 0; q < d->ndim; ++q) { p.bl[L][q] = off; off += fb; }
+        if (d->flags & ASD_FLAG_PER_CELL_CHI) { p.chil[L] = off; off += fb; }
+    }
+    p.max_blocks = max_reduce_blocks(d);
+    p.partials = off;
+    off += align256((size_t)p.max_blocks * 3 * sizeof(double));
+    p.small = off;
+    off += 256;
+    p.total = off;
+    return p;
+}
+
+extern "C" int asd_workspace_bytes(const asd_desc* desc, size_t* bytes) {
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    if (!bytes) return asd_fail(ASD_EINVAL, "bytes is NULL");
+    *bytes = plan_ws(desc).total;
+    return ASD_OK;
+}
+
+// ------------------------------------------------------------------ grid
+
+extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes, void* stream,
+                             asd_grid* out) {
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    if (!out) return asd_fail(ASD_EINVAL, "out is NULL");
+    WsPlan p = plan_ws(desc);
+    if (!dev_ws) return asd_fail(ASD_EWORKSPACE, "workspace is NULL");
+    if ((uintptr_t)dev_ws & 255) return asd_fail(ASD_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < p.total)
+        return asd_fail(ASD_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, p.total);
+    asd_grid_s* g = new (std::nothrow) asd_grid_s();
+    if (!g) return asd_fail(ASD_EINVAL, "out of host memory");
+    g->d = *desc;
+    g->st = (hipStream_t)stream;
+    g->ws = (char*)dev_ws;
+    g->ws_bytes = ws_bytes;
+    g->N = cells(desc);
+    g->es = desc->dtype == ASD_F64 ? 8 : 4;
+    for (int i = 0; i < 2; ++i) g->tmp[i] = p.tmp[i] == (size_t)-1 ? nullptr : g->ws + p.tmp[i];
+    for (int L = 0; L < 3; ++L) {
+        for (int q = 0; q < 3; ++q) g->bl[L][q] = p.bl[L][q] == (size_t)-1 ? nullptr : g->ws + p.bl[L][q];
+        g->chil[L] = p.chil[L] == (size_t)-1 ? nullptr : g->ws + p.chil[L];
+    }
+    g->partials = (double*)(g->ws + p.partials);
+    g->max_blocks = p.max_blocks;
+    char* sm = g->ws + p.small;
+    g->ticket = (unsigned*)sm;
+    g->flags = (unsigned*)(sm + 4);
+    g->stats = (double*)(sm + 8);   // 3 doubles
+    g->e0 = (double*)(sm + 32);
+    for (int q = 0; q < desc->ndim; ++q) {
+        if (!choose_sweep_cfg((int)g->es, desc->ndim, (int)desc->n[q],
+                              (desc->flags & ASD_FLAG_PER_CELL_CHI) != 0, 0, 0, &g->cfg[q])) {
+            delete g;
+            return asd_fail(ASD_EUNSUPPORTED, "no sweep configuration for axis %d", q);
+        }
+    }
+    *out = g;
+    return ASD_OK;
+}
+
+extern "C" int asd_destroy(asd_grid g) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    delete g;
+    return ASD_OK;
+}
+
+extern "C" int asd_set_field(asd_grid g, int32_t field, void* dev_ptr, int64_t nelem, int32_t dtype) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (!dev_ptr) return asd_fail(ASD_EINVAL, "field pointer is NULL");
+    if (dtype != g->d.dtype) return asd_fail(ASD_EDTYPE, "dtype %d does not match the grid (%d)", dtype, g->d.dtype);
+    if (nelem != g->N)
+        return asd_fail(ASD_ESHAPE, "nelem %lld does not match the grid (%lld cells)", (long long)nelem,
+                        (long long)g->N);
+    switch (field) {
+        case ASD_FIELD_T: g->T = dev_ptr; break;
+        case ASD_FIELD_BX: g->b[0] = dev_ptr; g->layouts_dirty = true; break;
+        case ASD_FIELD_BY: g->b[1] = dev_ptr; g->layouts_dirty = true; break;
+        case ASD_FIELD_BZ:
+            if (g->d.ndim != 3) return asd_fail(ASD_EINVAL, "BZ set on a 2-D grid");
+            g->b[2] = dev_ptr;
+            g->layouts_dirty = true;
+            break;
+        case ASD_FIELD_CHI:
+            if (!(g->d.flags & ASD_FLAG_PER_CELL_CHI))
+                return asd_fail(ASD_EINVAL, "CHI set without ASD_FLAG_PER_CELL_CHI");
+            g->chi = dev_ptr;
+            g->layouts_dirty = true;
+            break;
+        default: return asd_fail(ASD_EINVAL, "unknown field %d", field);
+    }
+    g->graph_valid = false;
+    return ASD_OK;
+}
+
+int check_fields(asd_grid g, bool need_T) {
+    if (need_T && !g->T) return asd_fail(ASD_ENOTSET, "field T is not set");
+    for (int q = 0; q < g->d.ndim; ++q)
+        if (!g->b[q]) return asd_fail(ASD_ENOTSET, "field b%c is not set", "xyz"[q]);
+    if ((g->d.flags & ASD_FLAG_PER_CELL_CHI) && !g->chi) return asd_fail(ASD_ENOTSET, "field CHI is not set");
+    return ASD_OK;
+}
+
+// ------------------------------------------------------------- layouts
+
+// stride of axis a (0=x,1=y,2=z) in layout L
+int64_t layout_stride(const asd_grid g, int L, int a) {
+    const int64_t nx = g->d.n[0], ny = g->d.n[1], nz = g->d.ndim == 3 ? g->d.n[2] : 1;
+    if (L == 0) { const int64_t s[3] = {1, nx, nx * ny}; return s[a]; }
+    if (L == 1) { const int64_t s[3] = {ny, 1, nx * ny}; return s[a]; }  // [z][x][y]
+    const int64_t s[3] = {nz, nx * nz, 1};                               // [y][x][z]
+    return s[a];
+}
+
+const void* field_in_layout(const asd_grid g, int L, int q) {
+    return L == 0 ? g->b[q] : g->bl[L][q];
+}
+const void* chi_in_layout(const asd_grid g, int L) { return L == 0 ? g->chi : g->chil[L]; }
+
+static std::once_flag g_attr_once;
+static hipError_t g_attr_err = hipSuccess;
+
+template <typename T>
+static int do_prepare(asd_grid g) {
+    std::call_once(g_attr_once, [] { g_attr_err = sweep_set_lds_limits((int)kLdsLimit); });
+    if (g_attr_err != hipSuccess) return hip_check(g_attr_err, "kernel attributes");
+    if (!g->ws_inited) {
+        int rc = hip_check(launch_fill_u32(g->ticket, 0u, 2, g->st), "fill");
+        if (rc) return rc;
+        g->ws_inited = true;
+    }
+    if (g->layouts_dirty) {
+        const int n[3] = {(int)g->d.n[0], (int)g->d.n[1], g->d.ndim == 3 ? (int)g->d.n[2] : 1};
+        const int nlay = g->d.ndim == 3 ? 3 : 2;
+        for (int L = 1; L < nlay; ++L) {
+            const int64_t ds[3] = {layout_stride(g, L, 0), layout_stride(g, L, 1), layout_stride(g, L, 2)};
+            for (int q = 0; q < g->d.ndim; ++q) {
+                int rc = hip_check(launch_permute<T>((const T*)g->b[q], (T*)g->bl[L][q], n, ds, g->st), "permute b");
+                if (rc) return rc;
+            }
+            if (g->chi) {
+                int rc = hip_check(launch_permute<T>((const T*)g->chi, (T*)g->chil[L], n, ds, g->st), "permute chi");
+                if (rc) return rc;
+            }
+        }
+        g->layouts_dirty = false;
+    }
+    return ASD_OK;
+}
+
+int prepare(asd_grid g) { return g->es == 8 ? do_prepare<double>(g) : do_prepare<float>(g); }
+
+// --------------------------------------------------------------- sweeps
+
+// the three sweeps: axis, input layout, output layout, t1 (fastest of out), t2
+struct SweepGeom { int d, Lin, Lout, t1, t2; };
+static SweepGeom sweep_geom(int ndim, int d) {
+    if (ndim == 2) {
+        if (d == 0) return {0, 0, 1, 1, 2};
+        return {1, 1, 0, 0, 2};
+    }
+    if (d == 0) return {0, 0, 1, 1, 2};
+    if (d == 1) return {1, 1, 2, 2, 0};
+    return {2, 2, 0, 0, 1};
+}
+
+ReduceParams no_reduce() {
+    ReduceParams r{};
+    return r;
+}
+
+ReduceParams make_reduce(asd_grid g, double* energy_out, const double* e0) {
+    ReduceParams r{};
+    r.partials = g->partials;
+    r.ticket = g->ticket;
+    r.energy_out = energy_out;
+    r.stats_out = g->stats;
+    r.flags = g->flags;
+    r.e0 = e0;
+    double dv = 1.0;
+    for (int q = 0; q < g->d.ndim; ++q) dv *= g->d.h[q];
+    r.dV = dv;
+    return r;
+}
+
+template <typename T>
+static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
+                           const ReduceParams& red, const SweepCfg* override_cfg) {
+    const SweepGeom G = sweep_geom(g->d.ndim, d);
+    const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
+    SweepParams<T> P{};
+    P.U = (const T*)in;
+    P.out = (T*)out;
+    P.bn = (const T*)field_in_layout(g, G.Lin, G.d);
+    P.bt1 = (const T*)field_in_layout(g, G.Lin, G.t1);
+    P.bt2 = g->d.ndim == 3 ? (const T*)field_in_layout(g, G.Lin, G.t2) : nullptr;
+    P.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)chi_in_layout(g, G.Lin) : nullptr;
+    const int64_t nz = g->d.ndim == 3 ? g->d.n[2] : 1;
+    const int64_t nax[3] = {g->d.n[0], g->d.n[1], nz};
+    P.n = (int)nax[G.d];
+    P.nt1 = (int)nax[G.t1];
+    P.nt2 = (int)nax[G.t2];
+    P.si_n = layout_stride(g, G.Lin, G.d);
+    P.si_t1 = layout_stride(g, G.Lin, G.t1);
+    P.si_t2 = layout_stride(g, G.Lin, G.t2);
+    P.so_n = layout_stride(g, G.Lout, G.d);
+    P.so_t1 = layout_stride(g, G.Lout, G.t1);
+    P.so_t2 = layout_stride(g, G.Lout, G.t2);
+    const double hn = g->d.h[G.d];
+    const double h1 = g->d.h[G.t1 < g->d.ndim ? G.t1 : 0];
+    const double h2 = g->d.ndim == 3 ? g->d.h[G.t2] : 1.0;
+    P.cnn = (T)(dt / (hn * hn));
+    P.cnt1 = (T)(dt / (hn * h1));
+    P.cnt2 = (T)(dt / (hn * h2));
+    P.chi_par = (T)g->d.chi_par;
+    P.chi_perp = (T)g->d.chi_perp;
+    P.periodic = g->d.bc == ASD_BC_PERIODIC;
+    P.limiter = g->d.limiter;
+    P.wpl = c.wpl;
+    P.lpw = c.lpw;
+    P.P = c.P;
+    P.rhs_mode = rhs_mode;
+    P.red = red;
+    const int nb1 = (P.nt1 + c.lpw - 1) / c.lpw;
+    const int64_t nblocks = (int64_t)nb1 * P.nt2;
+    if (red.partials && nblocks > g->max_blocks)
+        return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
+    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), P.chi != nullptr);
+    return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st),
+                     "sweep launch");
+}
+
+int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode, const ReduceParams& red,
+                  const SweepCfg* cfg) {
+    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, cfg)
+                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, cfg);
+}
+
+int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0) {
+    const int nb = reduce_num_blocks(g->N);
+    ReduceParams r = make_reduce(g, energy_out, e0);
+    hipError_t e = g->es == 8 ? launch_reduce<double>((const double*)x, g->N, r, nb, g->st)
+                              : launch_reduce<float>((const float*)x, g->N, r, nb, g->st);
+    return hip_check(e, "reduce launch");
+}
+
+// One semi-implicit step from `src` (layout A) into `dst` (layout A); the
+// last sweep may carry the fused reduction.
+int enqueue_si_step(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red) {
+    const int nd = g->d.ndim;
+    const void* in = src;
+    for (int d = 0; d < nd; ++d) {
+        void* out = (d == nd - 1) ? dst : g->tmp[d];
+        int rc = enqueue_sweep(g, d, dt, in, out, 0, d == nd - 1 ? red : no_reduce(), nullptr);
+        if (rc) return rc;
+        in = out;
+    }
+    return ASD_OK;
+}
+
+static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
+    if (!finite_pos(dt)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
+    if (g->d.flags & ASD_FLAG_ALLOW_UNSTABLE) return ASD_OK;
+    const double chi = g->d.chi_par;
+    double hmin2 = g->d.h[0] * g->d.h[0], sum_inv = 0.0;
+    for (int q = 0; q < g->d.ndim; ++q) {
+        hmin2 = std::min(hmin2, g->d.h[q] * g->d.h[q]);
+        sum_inv += 1.0 / (g->d.h[q] * g->d.h[q]);
+    }
+    if (explicit_scheme) {
+        if (g->d.ndim == 2 && chi * dt * sum_inv > 1.0)
+            return asd_fail(ASD_EUNSTABLE, "explicit dt above the 2-D limit (chi dt sum 1/h^2 = %g > 1)", chi * dt * sum_inv);
+        if (g->d.ndim == 3 && chi * dt / hmin2 > 0.444)
+            return asd_fail(ASD_EUNSTABLE, "explicit dt above the 3-D limit (chi dt/h^2 = %g > 0.444)", chi * dt / hmin2);
+    } else if (g->d.ndim == 3 && chi * dt / hmin2 > 8.25) {
+        return asd_fail(ASD_EUNSTABLE, "3-D semi-implicit dt above the limit (chi dt/h^2 = %g > 8.25)", chi * dt / hmin2);
+    }
+    return ASD_OK;
+}
+
+extern "C" int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, double* dev_energy) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
+    int rc = check_dt(g, dt, false);
+    if (rc) return rc;
+    rc = check_fields(g, true);
+    if (rc) return rc;
+    rc = prepare(g);
+    if (rc) return rc;
+    if (dev_energy) {
+        rc = enqueue_reduce(g, g->T, dev_energy, nullptr);
+        if (rc) return rc;
+    }
+    if (nsteps == 0) return ASD_OK;
+    if (g->use_graphs && nsteps >= 2) return run_si_graph(g, dt, nsteps, dev_energy);
+    for (int s = 0; s < nsteps; ++s) {
+        ReduceParams red = dev_energy ? make_reduce(g, dev_energy + s + 1, dev_energy) : no_reduce();
+        rc = enqueue_si_step(g, dt, g->T, g->T, red);
+        if (rc) return rc;
+    }
+    return ASD_OK;
+}
+
+template <typename T>
+static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red) {
+    ExplicitParams<T> P{};
+    P.U = (const T*)src;
+    P.out = (T*)dst;
+    for (int q = 0; q < 3; ++q) P.b[q] = q < g->d.ndim ? (const T*)g->b[q] : nullptr;
+    P.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)g->chi : nullptr;
+    P.n[0] = (int)g->d.n[0];
+    P.n[1] = (int)g->d.n[1];
+    P.n[2] = g->d.ndim == 3 ? (int)g->d.n[2] : 1;
+    for (int d = 0; d < 3; ++d) {
+        const double hd = d < g->d.ndim ? g->d.h[d] : 1.0;
+        P.cn[d] = (T)(dt / (hd * hd));
+        for (int t = 0; t < 3; ++t) {
+            const double ht = t < g->d.ndim ? g->d.h[t] : 1.0;
+            P.ct[d][t] = (T)(dt / (hd * ht));
+        }
+    }
+    P.chi_par = (T)g->d.chi_par;
+    P.chi_perp = (T)g->d.chi_perp;
+    P.periodic = g->d.bc == ASD_BC_PERIODIC;
+    P.limiter = g->d.limiter;
+    P.red = red;
+    return hip_check(launch_explicit<T>(P, g->d.ndim, g->st, nullptr), "explicit launch");
+}
+
+int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red) {
+    return g->es == 8 ? enqueue_explicit_t<double>(g, dt, src, dst, red)
+                      : enqueue_explicit_t<float>(g, dt, src, dst, red);
+}
+
+int enqueue_copy(asd_grid g, const void* src, void* dst) {
+    hipError_t e = g->es == 8 ? launch_copy<double>((const double*)src, (double*)dst, g->N, g->st)
+                              : launch_copy<float>((const float*)src, (float*)dst, g->N, g->st);
+    return hip_check(e, "copy launch");
+}
+
+extern "C" int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, double* dev_energy) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
+    int rc = check_dt(g, dt, true);
+    if (rc) return rc;
+    rc = check_fields(g, true);
+    if (rc) return rc;
+    rc = prepare(g);
+    if (rc) return rc;
+    if (dev_energy) {
+        rc = enqueue_reduce(g, g->T, dev_energy, nullptr);
+        if (rc) return rc;
+    }
+    if (nsteps == 0) return ASD_OK;
+    if (g->use_graphs && nsteps >= 2) return run_explicit_graph(g, dt, nsteps, dev_energy);
+    void* a = g->T;
+    void* b = g->tmp[0];
+    for (int s = 0; s < nsteps; ++s) {
+        ReduceParams red = dev_energy ? make_reduce(g, dev_energy + s + 1, dev_energy) : no_reduce();
+        rc = enqueue_explicit(g, dt, a, b, red);
+        if (rc) return rc;
+        std::swap(a, b);
+    }
+    if (a != g->T) return enqueue_copy(g, a, g->T);
+    return ASD_OK;
+}
+
+extern "C" int asd_status(asd_grid g, uint32_t* flags, double* stats) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (!flags) return asd_fail(ASD_EINVAL, "flags is NULL");
+    int rc = check_fields(g, true);
+    if (rc) return rc;
+    rc = prepare(g);
+    if (rc) return rc;
+    rc = enqueue_reduce(g, g->T, nullptr, nullptr);
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(g->st), "stream synchronize");
+    if (rc) return rc;
+    unsigned f = 0;
+    double st[3];
+    rc = hip_check(hipMemcpy(&f, g->flags, sizeof f, hipMemcpyDeviceToHost), "flags copy");
+    if (rc) return rc;
+    rc = hip_check(hipMemcpy(st, g->stats, sizeof st, hipMemcpyDeviceToHost), "stats copy");
+    if (rc) return rc;
+    *flags = f;
+    if (stats) memcpy(stats, st, sizeof st);
+    // flags are sticky between status calls: clear them now they are reported
+    return hip_check(launch_fill_u32(g->flags, 0u, 1, g->st), "flags reset");
+}

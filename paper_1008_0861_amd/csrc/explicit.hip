@@ -1,0 +1,146 @@
+// Explicit limited step (the time-step-limited baseline of sections 1 and
+// 3): forward Euler of the same conservative operator, every face from T^n:
+//
+//   T^{n+1}_c = T^n_c + sum_d [ alpha_{c+1/2}(T_{c+e} - T_c) - alpha_{c-1/2}(T_c - T_{c-e})
+//                               + F_{c+1/2} - F_{c-1/2} ]
+//
+// with alpha_f and F_f defined exactly as in the semi-implicit sweep.
+//
+// gfx950 mapping: one workgroup per tile of TX x TY x TZ cells.  The tile
+// plus a one-cell halo of U, b (and chi) is staged through LDS with
+// coalesced loads; the limited cell slopes along every axis are computed
+// once per staged cell; each thread then updates one cell.
+#include "asd_device.h"
+#include "asd_launch.h"
+
+namespace asd {
+
+template <int NDIM>
+struct ExTile {
+    static constexpr int TX = NDIM == 2 ? 64 : 32;
+    static constexpr int TY = NDIM == 2 ? 4 : 4;
+    static constexpr int TZ = NDIM == 2 ? 1 : 2;
+    static constexpr int BX = TX + 2, BY = TY + 2, BZ = NDIM == 2 ? 1 : TZ + 2;
+    static constexpr int NB = BX * BY * BZ;
+    static constexpr int NT = TX * TY * TZ;
+};
+
+template <typename T, int NDIM>
+__global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
+    using TL = ExTile<NDIM>;
+    __shared__ T sU[TL::NB];
+    __shared__ T sB[NDIM][TL::NB];
+    __shared__ T sS[NDIM][TL::NB];  // limited slope along each axis
+    __shared__ T sChi[TL::NB];
+
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int gx = (nx + TL::TX - 1) / TL::TX, gy = (ny + TL::TY - 1) / TL::TY;
+    int blk = blockIdx.x;
+    const int x0 = (blk % gx) * TL::TX;
+    blk /= gx;
+    const int y0 = (blk % gy) * TL::TY;
+    const int z0 = (blk / gy) * TL::TZ;
+    const bool periodic = P.periodic != 0;
+    const int lim = P.limiter;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+
+    // stage the box [x0-1, x0+TX] x [y0-1, y0+TY] (x [z0-1, z0+TZ])
+    for (int i = threadIdx.x; i < TL::NB; i += blockDim.x) {
+        const int bx = i % TL::BX, by = (i / TL::BX) % TL::BY, bz = i / (TL::BX * TL::BY);
+        const int64_t x = nb_coord(x0 - 1 + bx, nx, periodic);
+        const int64_t y = nb_coord(y0 - 1 + by, ny, periodic);
+        const int64_t z = NDIM == 3 ? nb_coord(z0 - 1 + bz, nz, periodic) : 0;
+        // cells beyond the far edge of a partial tile are clamped (never used)
+        const int64_t xc = x < nx ? x : nx - 1, yc = y < ny ? y : ny - 1, zc = z < nz ? z : nz - 1;
+        const int64_t c = xc + yc * sy + zc * sz;
+        sU[i] = P.U[c];
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) sB[d][i] = P.b[d][c];
+        if (P.chi) sChi[i] = P.chi[c];
+    }
+    __syncthreads();
+    const int bstr[3] = {1, TL::BX, TL::BX * TL::BY};
+    const int bdim[3] = {TL::BX, TL::BY, TL::BZ};
+    for (int i = threadIdx.x; i < TL::NB; i += blockDim.x) {
+        const int bc[3] = {i % TL::BX, (i / TL::BX) % TL::BY, i / (TL::BX * TL::BY)};
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+            T s = T(0);
+            if (bc[d] > 0 && bc[d] < bdim[d] - 1)
+                s = cell_slope<T>(lim, sU[i - bstr[d]], sU[i], sU[i + bstr[d]]);
+            sS[d][i] = s;
+        }
+    }
+    __syncthreads();
+
+    const int tx = threadIdx.x % TL::TX, ty = (threadIdx.x / TL::TX) % TL::TY,
+              tz = threadIdx.x / (TL::TX * TL::TY);
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool inside = x < nx && y < ny && (NDIM == 2 || z < nz);
+    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
+    if (inside) {
+        const int bi = (tx + 1) + (ty + 1) * TL::BX + (NDIM == 3 ? (tz + 1) * TL::BX * TL::BY : 0);
+        const int gc[3] = {x, y, z};
+        const T uc = sU[bi];
+        T acc = T(0);
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                // face between cells c0 = (side ? c : c - e_d) and c1 = c0 + e_d
+                const int i0 = side ? bi : bi - bstr[d];
+                const int i1 = i0 + bstr[d];
+                const int g0 = side ? gc[d] : gc[d] - 1;
+                const bool wall = !periodic && (g0 < 0 || g0 + 1 > P.n[d] - 1);
+                if (wall) continue;
+                const T bnf = T(0.5) * (sB[d][i0] + sB[d][i1]);
+                T chif = P.chi_par;
+                if (P.chi) chif = harmonic<T>(sChi[i0], sChi[i1]);
+                const T dpar = chif - P.chi_perp;
+                const T alpha = P.cn[d] * (P.chi_perp + dpar * bnf * bnf);
+                T tr = T(0);
+#pragma unroll
+                for (int t = 0; t < NDIM; ++t) {
+                    if (t == d) continue;
+                    const T btf = T(0.5) * (sB[t][i0] + sB[t][i1]);
+                    tr += P.ct[d][t] * btf * limit2<T>(lim, sS[t][i1], sS[t][i0]);
+                }
+                const T flux = dpar * bnf * tr;
+                const T diff = sU[i1] - sU[i0];
+                // the face adds +(alpha diff + F) to c0 and -(..) to c1
+                acc += side ? (alpha * diff + flux) : -(alpha * diff + flux);
+            }
+        }
+        const T un = uc + acc;
+        P.out[(int64_t)x + y * sy + (int64_t)z * sz] = un;
+        lsum = (double)un;
+        lmin = lmax = (double)un;
+    }
+    if (P.red.partials) block_reduce_and_finish(P.red, lsum, lmin, lmax);
+}
+
+int explicit_num_blocks(int ndim, const int n[3]) {
+    if (ndim == 2) {
+        using TL = ExTile<2>;
+        return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY);
+    }
+    using TL = ExTile<3>;
+    return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY) *
+           ((n[2] + TL::TZ - 1) / TL::TZ);
+}
+
+template <typename T>
+hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out) {
+    const int nb = explicit_num_blocks(ndim, P.n);
+    if (nblocks_out) *nblocks_out = nb;
+    if (ndim == 2)
+        hipLaunchKernelGGL((explicit_kernel<T, 2>), dim3(nb), dim3(ExTile<2>::NT), 0, st, P);
+    else
+        hipLaunchKernelGGL((explicit_kernel<T, 3>), dim3(nb), dim3(ExTile<3>::NT), 0, st, P);
+    return hipGetLastError();
+}
+
+template hipError_t launch_explicit<float>(const ExplicitParams<float>&, int, hipStream_t, int*);
+template hipError_t launch_explicit<double>(const ExplicitParams<double>&, int, hipStream_t, int*);
+
+}  // namespace asd

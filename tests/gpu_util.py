@@ -1,0 +1,65 @@
+"""Helpers for the GPU tests: run a synthetic problem through the C ABI and
+through the oracle on identical inputs."""
+import numpy as np
+import torch
+
+from oracle import oracle
+from paper_1008_0861_amd import binding as asd
+
+DT = {"f32": torch.float32, "f64": torch.float64}
+NP = {"f32": np.float32, "f64": np.float64}
+
+# parity bars (relative, per cell): FP64 state 1e-12; FP32 state 1e-5 against
+# the FP64 oracle fed the FP32-rounded inputs
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def rounded(p, prec):
+    """Inputs as the GPU sees them, back in float64 for the oracle."""
+    r = lambda a: None if a is None else a.astype(NP[prec]).astype(np.float64)  # noqa: E731
+    return [r(c) for c in p.b], r(p.T0), r(p.chi)
+
+
+def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False):
+    b, T0, chi = rounded(p, prec)
+    g = oracle.OracleGrid(b, p.h, bc=p.bc, limiter=p.limiter, chi_par=p.chi_par, chi_perp=p.chi_perp, chi=chi)
+    nsteps = p.nsteps if nsteps is None else nsteps
+    dt = p.dt if dt is None else dt
+    f = g.step_si if scheme == "si" else g.step_explicit
+    return f(T0, dt, nsteps, energy=energy)
+
+
+class GpuProblem:
+    """A problem resident on the GPU, advanced on a private stream."""
+
+    def __init__(self, p, prec, stream=None, allow_unstable=False):
+        self.p = p
+        self.prec = prec
+        self.stream = stream or torch.cuda.Stream()
+        dt = DT[prec]
+        chi_par = p.chi_par if p.chi is None else float(max(p.chi.max(), p.chi_par))
+        with torch.cuda.stream(self.stream):
+            self.g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=dt, limiter=p.limiter, chi_par=chi_par,
+                              chi_perp=p.chi_perp, per_cell_chi=p.chi is not None,
+                              allow_unstable=allow_unstable)
+            self.b = [torch.from_numpy(c).to(dt).cuda() for c in p.b]
+            self.T = torch.from_numpy(p.T0).to(dt).cuda()
+            self.g.set_b(*self.b)
+            self.g.set_field("T", self.T)
+            if p.chi is not None:
+                self.chi = torch.from_numpy(p.chi).to(dt).cuda()
+                self.g.set_field("chi", self.chi)
+
+    def run(self, nsteps=None, scheme="si", dt=None, energy=False):
+        nsteps = self.p.nsteps if nsteps is None else nsteps
+        dt = self.p.dt if dt is None else dt
+        with torch.cuda.stream(self.stream):
+            f = self.g.step_semi_implicit if scheme == "si" else self.g.step_explicit
+            e = f(dt, nsteps, energy=energy)
+        self.stream.synchronize()
+        out = self.T.double().cpu().numpy()
+        return (out, e.cpu().numpy()) if energy else out
+
+
+def max_rel_err(got, ref):
+    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)))

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical seeded inputs, cell by cell.  FP64 state: 1e-12 relative; FP32
+state: 1e-5 relative against the oracle fed the FP32-rounded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from synth.configs import Problem
+from tests.gpu_util import TOL, GpuProblem, max_rel_err, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_problem(shape, bc, limiter="vanleer", chi_perp=0.0, per_cell_chi=False, ncfl=20.0, nsteps=5,
+                    seed=0):
+    """Random smooth b field and blob temperature on an arbitrary grid."""
+    nd = len(shape)
+    if nd == 2:
+        ny, nx = shape
+        bx, by = synth.grf_unit_field_2d(nx, ny, seed, kmax2=16)
+        T0 = synth.blobs_2d(nx, ny, seed + 1, nblobs=4, rmin=0.1, rmax=0.3, width=0.05)
+        b = (bx, by)
+        h = (1.0 / nx, 1.3 / ny)
+    else:
+        nz, ny, nx = shape
+        rng = np.random.default_rng(seed)
+        v = [synth.smoothed_normal(shape, seed + q, 2.0) + 0.3 * rng.standard_normal() for q in range(3)]
+        m = np.sqrt(sum(c * c for c in v))
+        b = tuple(c / m for c in v)
+        T0 = np.exp(0.3 * synth.smoothed_normal(shape, seed + 7, 2.0))
+        h = (1.0 / nx, 1.1 / ny, 0.9 / nz)
+    chi = synth.chi_field_2d(shape[-1], shape[-2], seed + 3) if (per_cell_chi and nd == 2) else None
+    if per_cell_chi and nd == 3:
+        chi = np.exp(0.4 * synth.smoothed_normal(shape, seed + 3, 2.0))
+    chi_max = 1.0 if chi is None else float(chi.max())
+    dt = synth.ncfl_dt(ncfl, h, chi_max)
+    if nd == 3:
+        dt = min(dt, 6.0 * min(h) ** 2 / chi_max)
+    return Problem("rand", b, T0, h, bc=bc, limiter=limiter, chi_par=1.0, chi_perp=chi_perp, chi=chi, dt=dt,
+                   nsteps=nsteps)
+
+
+def test_ring_64_fp64_200_steps():
+    """The 64^2 ring (T = 12 in the patch, 10 elsewhere), insulating walls,
+    200 steps at 10x the explicit step, FP64: every cell and the energy
+    series within 1e-12 of the oracle."""
+    p = synth.ring_problem(n=64)
+    ref, eref = oracle_run(p, "f64", energy=True)
+    got, e = GpuProblem(p, "f64").run(energy=True)
+    assert max_rel_err(got, ref) <= TOL["f64"]
+    np.testing.assert_allclose(e, eref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(37, 200), (130, 67), (64, 64), (5, 1000), (300, 7)])
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+def test_si_2d_ragged_shapes(prec, shape, bc):
+    p = _random_problem(shape, bc, seed=sum(shape))
+    ref = oracle_run(p, prec)
+    got = GpuProblem(p, prec).run()
+    assert max_rel_err(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("limiter", ["vanleer", "minmod", "mc", "linear"])
+@pytest.mark.parametrize("variant", ["plain", "chi_perp", "per_cell_chi"])
+def test_si_2d_limiters_and_tensor_forms(limiter, variant):
+    p = _random_problem((72, 90), "periodic", limiter=limiter, chi_perp=1e-3 if variant == "chi_perp" else 0.0,
+                        per_cell_chi=variant == "per_cell_chi", seed=3)
+    for prec in ("f64", "f32"):
+        ref = oracle_run(p, prec)
+        got = GpuProblem(p, prec).run()
+        assert max_rel_err(got, ref) <= TOL[prec], (prec, max_rel_err(got, ref))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 31, 63, 64, 65, 127, 129, 1000, 1023, 1025, 2048, 4096])
+def test_si_line_lengths(n):
+    """Line lengths around every segment/lane boundary of the line solver,
+    on both axes (n x 6 and 6 x n), insulating for n = 2, else periodic."""
+    bc = "insulating" if n == 2 else "periodic"
+    for shape in ((6, n), (n, 6)):
+        p = _random_problem(shape, bc, seed=n, nsteps=3)
+        ref = oracle_run(p, "f64")
+        got = GpuProblem(p, "f64").run()
+        assert max_rel_err(got, ref) <= TOL["f64"], (shape, max_rel_err(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(9, 13, 21), (20, 24, 17), (3, 40, 5)])
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+def test_si_3d(prec, shape, bc):
+    p = _random_problem(shape, bc, ncfl=10.0, seed=len(shape) + shape[0], nsteps=4)
+    ref = oracle_run(p, prec)
+    got = GpuProblem(p, prec).run()
+    assert max_rel_err(got, ref) <= TOL[prec]
+
+
+def test_si_3d_per_cell_chi_and_chi_perp():
+    p = _random_problem((12, 14, 16), "periodic", chi_perp=1e-2, per_cell_chi=True, ncfl=8.0, seed=5)
+    ref = oracle_run(p, "f64")
+    got = GpuProblem(p, "f64").run()
+    assert max_rel_err(got, ref) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(37, 200), (64, 64), (9, 13, 21), (16, 16, 16)])
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+def test_explicit_parity(prec, shape, bc):
+    p = _random_problem(shape, bc, seed=11, nsteps=7)
+    dt = synth.ncfl_dt(1.0 if len(shape) == 2 else 0.8, p.h, 1.0)
+    ref = oracle_run(p, prec, scheme="ex", dt=dt)
+    got = GpuProblem(p, prec).run(scheme="ex", dt=dt)
+    assert max_rel_err(got, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("limiter", ["vanleer", "minmod", "mc", "linear"])
+def test_explicit_limiters_per_cell_chi(limiter):
+    p = _random_problem((50, 70), "insulating", limiter=limiter, per_cell_chi=True, chi_perp=1e-3, seed=2)
+    dt = synth.ncfl_dt(1.0, p.h, float(p.chi.max()))
+    ref = oracle_run(p, "f64", scheme="ex", dt=dt, nsteps=6)
+    got = GpuProblem(p, "f64").run(scheme="ex", dt=dt, nsteps=6)
+    assert max_rel_err(got, ref) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_grf_1024_full_size(prec):
+    """The 1024^2 periodic random-field workload at full size, in the launch
+    configuration the benchmark uses, against the oracle for 30 steps."""
+    p = synth.grf2d_problem(1024, nsteps=30)
+    ref = oracle_run(p, prec)
+    got = GpuProblem(p, prec).run()
+    assert max_rel_err(got, ref) <= TOL[prec]
+
+
+def test_grf_1024_chi_perp_fp32():
+    p = synth.grf2d_problem(1024, nsteps=10, chi_perp=1e-3)
+    ref = oracle_run(p, "f32")
+    got = GpuProblem(p, "f32").run()
+    assert max_rel_err(got, ref) <= TOL["f32"]
+
+
+def test_energy_conserved_and_deterministic_100_steps():
+    """FP32 state, 100 steps at 1024^2: the FP64 energy series stays at its
+    initial value to FP32 rounding, and two runs are bitwise equal."""
+    p = synth.grf2d_problem(1024, nsteps=100)
+    a, ea = GpuProblem(p, "f32").run(energy=True)
+    b, eb = GpuProblem(p, "f32").run(energy=True)
+    assert np.array_equal(a, b) and np.array_equal(ea, eb)
+    assert np.max(np.abs(ea - ea[0])) <= 2e-6 * abs(ea[0])
+
+
+def test_graph_and_eager_paths_agree():
+    p = synth.grf2d_problem(256, nsteps=12)
+    g1 = GpuProblem(p, "f32")
+    g2 = GpuProblem(p, "f32")
+    g2.g.set_graphs(False)
+    a = g1.run()
+    b = g2.run()
+    assert np.array_equal(a, b)
+    # replay the cached graph three more times, with eager work in between
+    for _ in range(3):
+        a = g1.run(nsteps=12)
+        b = g2.run(nsteps=12)
+        torch.cuda.synchronize()
+        assert np.array_equal(a, b)
+
+
+def test_launch_shapes_agree():
+    """Every admissible launch shape gives the oracle's result."""
+    p = _random_problem((40, 256), "periodic", seed=9, nsteps=3)
+    ref = oracle_run(p, "f64")
+    for wpl in (1, 2, 4):
+        for lpw in (1, 2, 4):
+            gp = GpuProblem(p, "f64")
+            try:
+                gp.g.set_sweep_config(0, wpl, lpw)
+            except Exception:
+                continue
+            got = gp.run()
+            assert max_rel_err(got, ref) <= TOL["f64"], (wpl, lpw)
+
+
+def test_tuner_keeps_results():
+    p = synth.grf2d_problem(512, nsteps=5)
+    ref = oracle_run(p, "f32")
+    gp = GpuProblem(p, "f32")
+    with torch.cuda.stream(gp.stream):
+        cfgs = gp.g.tune(p.dt, reps=3)
+    assert len(cfgs) == 2
+    got = gp.run()
+    assert max_rel_err(got, ref) <= TOL["f32"]
+
+
+def test_status_flags():
+    p = synth.ring_problem(n=64, nsteps=5)
+    gp = GpuProblem(p, "f64")
+    gp.run(energy=True)
+    with torch.cuda.stream(gp.stream):
+        flags, stats = gp.g.status()
+    assert flags == 0
+    assert stats[1] >= 10.0 - 1e-9 and stats[2] <= 12.0 + 1e-9
+    # a negative temperature is reported
+    with torch.cuda.stream(gp.stream):
+        gp.T[3, 3] = -1.0
+        flags, stats = gp.g.status()
+    assert flags & 2 and stats[1] == -1.0
