@@ -1,0 +1,259 @@
+"""Benchmark of the semi-implicit anisotropic diffusion hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 1024 x 1024 periodic random-field problem (b from a random
+vector potential A_z with |m|^2 <= 64, chi_par = 1, chi_perp = 0, blob
+initial T), FP32 state, dt = 20x the explicit Courant step.  A "step" is one
+full semi-implicit step: x sweep + y sweep (face coefficients, limited
+transverse fluxes, one tridiagonal solve per line) with the FP64 energy /
+min / max reduction fused into the second sweep.  Inputs are resident in
+HBM before timing; K steps are timed as one graph-captured call.
+
+Prints one JSON line with the throughput (Gcell-updates/s), the roofline
+of the dominant kernel (HBM bound, algorithmic bytes over its event-timed
+average duration), the FP64 oracle timed on the host, and secondary
+figures (FP64 state, explicit limited step, copy-kernel bandwidth).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+NX = 1024
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip secondary measurements")
+    ap.add_argument("--tune", type=int, default=1, help="run the launch-shape autotuner first")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run one plain copy of 64 MiB (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of sweep launch shapes: loaded if present (no tuning), else written")
+    return ap.parse_args()
+
+
+def timed(fn, stream, torch):
+    """Run fn() between two events on `stream`; returns milliseconds."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def make_grid(p, prec, stream, torch, asd):
+    dt = torch.float32 if prec == "f32" else torch.float64
+    with torch.cuda.stream(stream):
+        g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=dt, chi_par=p.chi_par, chi_perp=p.chi_perp)
+        b = [torch.from_numpy(c).to(dt).cuda() for c in p.b]
+        T = torch.from_numpy(p.T0).to(dt).cuda()
+        g.set_b(*b)
+        g.set_field("T", T)
+    g._keep = b
+    stream.synchronize()
+    return g
+
+
+def run_si(g, p, steps, warmup, stream, torch):
+    """Warm up (capturing the K-step graph when warmup >= steps), then time
+    exactly `steps` steps; returns ms per step."""
+    ebuf = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        left = warmup
+        while left > 0:
+            n = steps if left >= steps else left
+            g.step_semi_implicit(p.dt, n, out=ebuf)
+            left -= n
+        stream.synchronize()
+        ms = timed(lambda: g.step_semi_implicit(p.dt, steps, out=ebuf), stream, torch)
+    e = ebuf.cpu().numpy()
+    return ms / steps, e
+
+
+def kernel_durations(g, p, stream, torch, reps=200):
+    """Average duration of each sweep kernel, launched back to back on the
+    grid's stream between two events (T is not modified)."""
+    out = []
+    with torch.cuda.stream(stream):
+        g.bench_sweep(0, p.dt, 0)  # valid inputs for every sweep
+        for axis in range(len(p.shape)):
+            g.bench_sweep(axis, p.dt, 5)
+            ms = timed(lambda: g.bench_sweep(axis, p.dt, reps), stream, torch)
+            out.append(ms / reps)
+    return out
+
+
+def copy_bandwidth(stream, torch, asd, nbytes=1 << 30):
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            asd.bench_copy(src, dst, stream)
+        reps = 20
+        ms = timed(lambda: [asd.bench_copy(src, dst, stream) for _ in range(reps)], stream, torch)
+    return 2 * nbytes * reps / (ms * 1e-3) / 1e9
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_grf2d1024_fp32.json")
+
+
+def kernel_source_digest():
+    """Digest of the sources that define the timed sweep kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "asd_device.h", "asd_launch.h"):
+        h.update(open(os.path.join(ROOT, "paper_1008_0861_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cfg):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs,
+    or None if they were taken on other kernel sources or launch shapes."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("kernel_digest") != kernel_source_digest() or t.get("sweep_config") != cfg:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s=12.0):
+    """The FP64 oracle, serial on one host core, on the same 1024^2 workload:
+    as many whole steps as fit in about budget_s seconds (at least 2)."""
+    import synth
+    from oracle import oracle
+
+    p = synth.grf2d_problem(NX, nsteps=1)
+    g = oracle.OracleGrid(p.b, p.h, bc=p.bc, chi_par=p.chi_par, chi_perp=p.chi_perp)
+    T = p.T0
+    t0 = time.perf_counter()
+    T = g.step_si(T, p.dt, 1)
+    one = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    T = g.step_si(T, p.dt, n)
+    el = time.perf_counter() - t0
+    steps = n + 1
+    total = el + one
+    return {
+        "value": round(p.ncells * steps / total / 1e9, 6),
+        "unit": "Gcell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} semi-implicit steps of the 1024^2 periodic random-field problem, FP64, "
+                  f"serial C oracle, {total:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "see DESIGN.md for how the path would shard", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_1008_0861_amd import binding as asd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    asd.lib()
+    stream = torch.cuda.Stream()
+    p = synth.grf2d_problem(NX, nsteps=args.steps)
+    g = make_grid(p, "f32", stream, torch, asd)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        for a, c in enumerate(json.load(open(args.tune_cache))):
+            g.set_sweep_config(a, c["wpl"], c["lpw"])
+    elif args.tune:
+        with torch.cuda.stream(stream):
+            g.tune(p.dt, reps=20)
+    cfgs = [g.sweep_config(a) for a in range(2)]
+    if args.tune_cache and not os.path.exists(args.tune_cache):
+        json.dump(cfgs, open(args.tune_cache, "w"))
+    ms_step, e = run_si(g, p, args.steps, args.warmup, stream, torch)
+    N = p.ncells
+    value = N / (ms_step * 1e-3) / 1e9
+    drift = float(abs(e[-1] - e[0]) / abs(e[0]))
+
+    if args.calib:
+        src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            asd.bench_copy(src, dst, stream)
+        stream.synchronize()
+
+    durs = kernel_durations(g, p, stream, torch)
+    dom = max(range(len(durs)), key=lambda a: durs[a])
+    bytes_per_launch = N * (4 + 4 + 8)  # T in, T out, (b_n, b_t) per cell, FP32
+    achieved = bytes_per_launch / (durs[dom] * 1e-3) / 1e9
+    step_gbs = N * 32 / (ms_step * 1e-3) / 1e9
+
+    result = {
+        "metric": "Gcell-updates/s per semi-implicit step + %HBM peak; speedup vs explicit at equal L1 error",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grf2d-1024x1024-periodic-fp32-ncfl20-vanleer", "nx": NX, "ny": NX,
+                   "chi_par": 1.0, "chi_perp": 0.0, "fused_fp64_energy": True, "sweep_configs": cfgs},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"sweep_kernel axis {'xy'[dom]}",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(cfgs[dom]),
+            "kernel_ms": [round(d, 6) for d in durs],
+            "step_algorithmic_GBs": round(step_gbs, 1),
+            "kernel_digest": kernel_source_digest(),
+        },
+        "energy_rel_drift": drift,
+    }
+    if not args.no_extra:
+        extra = {}
+        extra["copy_kernel_GBs"] = round(copy_bandwidth(stream, torch, asd), 1)
+        p64 = synth.grf2d_problem(NX, nsteps=200)
+        g64 = make_grid(p64, "f64", stream, torch, asd)
+        with torch.cuda.stream(stream):
+            g64.tune(p64.dt, reps=10)
+        ms64, _ = run_si(g64, p64, 200, 200, stream, torch)
+        extra["fp64_si_Gcells"] = round(N / (ms64 * 1e-3) / 1e9, 3)
+        gx = make_grid(p, "f32", stream, torch, asd)
+        dtx = synth.ncfl_dt(1.0, p.h, 1.0)
+        ebx = torch.empty(2001, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(stream):
+            gx.step_explicit(dtx, 2000, out=ebx)
+            msx = timed(lambda: gx.step_explicit(dtx, 2000, out=ebx), stream, torch) / 2000
+        extra["explicit_fp32_Gcells"] = round(N / (msx * 1e-3) / 1e9, 3)
+        extra["explicit_ms_per_step"] = round(msx, 6)
+        result["extra"] = extra
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

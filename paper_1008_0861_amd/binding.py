@@ -202,14 +202,26 @@ class Grid:
     def T(self):
         return self.fields["T"]
 
-    def step_semi_implicit(self, dt, nsteps=1, energy=False):
-        e = torch.empty(nsteps + 1, dtype=torch.float64, device=self.device) if energy else None
+    def _energy_buf(self, nsteps, energy, out):
+        if out is not None:
+            if out.dtype != torch.float64 or out.device.type != "cuda" or out.numel() < nsteps + 1:
+                raise ValueError("out must be a CUDA float64 tensor of at least nsteps+1 entries")
+            return out
+        if energy:
+            return torch.empty(nsteps + 1, dtype=torch.float64, device=self.device)
+        return None
+
+    def step_semi_implicit(self, dt, nsteps=1, energy=False, out=None):
+        """nsteps semi-implicit steps of T in place.  With energy=True (or an
+        FP64 buffer `out` of nsteps+1 entries, reused across calls so that the
+        captured step graph is replayed) returns sum T dV per step."""
+        e = self._energy_buf(nsteps, energy, out)
         check(lib().asd_step_semi_implicit(self.handle, float(dt), int(nsteps),
                                            ctypes.c_void_p(e.data_ptr()) if e is not None else None))
         return e
 
-    def step_explicit(self, dt, nsteps=1, energy=False):
-        e = torch.empty(nsteps + 1, dtype=torch.float64, device=self.device) if energy else None
+    def step_explicit(self, dt, nsteps=1, energy=False, out=None):
+        e = self._energy_buf(nsteps, energy, out)
         check(lib().asd_step_explicit_limited(self.handle, float(dt), int(nsteps),
                                               ctypes.c_void_p(e.data_ptr()) if e is not None else None))
         return e

@@ -13,6 +13,38 @@ namespace asd {
 
 enum Limiter : int { LIM_VANLEER = 0, LIM_MINMOD = 1, LIM_MC = 2, LIM_LINEAR = 3 };
 
+// Reciprocals from the hardware approximation.  approx_rcp: FP32
+// v_rcp_f32 as is (1 ulp, used inside the limiter, whose rounding cannot
+// affect conservation).  fast_rcp: refined by Newton steps
+// x <- x + x (1 - d x) (one in FP32, two in FP64), used by the line solves,
+// where a biased reciprocal would bias the column sums of the inverse and
+// make the total energy drift.
+template <typename T>
+__device__ __forceinline__ T approx_rcp(T d);
+template <>
+__device__ __forceinline__ float approx_rcp<float>(float d) {
+    return __builtin_amdgcn_rcpf(d);
+}
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T d);
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float d) {
+    const float x = __builtin_amdgcn_rcpf(d);
+    return fmaf(x, fmaf(-d, x, 1.0f), x);
+}
+template <>
+__device__ __forceinline__ double fast_rcp<double>(double d) {
+    double x = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-d, x, 1.0);
+    return fma(x, e, x);
+}
+template <>
+__device__ __forceinline__ double approx_rcp<double>(double d) {
+    return fast_rcp<double>(d);
+}
+
 // Two-argument limiters of section 2: van Leer (Eq. vanLeer), minmod, and
 // monotonised central (minmod of 2a, 2b, (a+b)/2); LINEAR is the plain mean
 // used in the linear stability analysis (section 2.1).
@@ -21,7 +53,7 @@ __device__ __forceinline__ T limit2(int lim, T a, T b) {
     const T ab = a * b;
     if (lim == LIM_LINEAR) return T(0.5) * (a + b);
     if (!(ab > T(0))) return T(0);
-    if (lim == LIM_VANLEER) return T(2) * ab / (a + b);
+    if (lim == LIM_VANLEER) return T(2) * ab * approx_rcp<T>(a + b);
     const T aa = fabs(a), bb = fabs(b);
     T m;
     if (lim == LIM_MINMOD) {

@@ -26,10 +26,12 @@ inline int pow2_floor(int v) {
     return p;
 }
 
-inline size_t sweep_lds(int es, int ndim, int n, int lpw, int nthreads, bool chi) {
+// LDS of a sweep launch: U, alpha, slope and beta per transverse axis for
+// each line, and three reduction arrays per thread.
+inline size_t sweep_lds(int es, int ndim, int n, int lpw, int nthreads) {
     const int LS = es == 8 ? asd::lds_line_stride<double>(n) : asd::lds_line_stride<float>(n);
-    const int narr = (ndim == 2 ? 4 : 6) + (chi ? 1 : 0);
-    return (size_t)es * ((size_t)narr * lpw * LS + 4 * (size_t)nthreads);
+    const int narr = ndim == 2 ? 4 : 6;
+    return (size_t)es * ((size_t)narr * lpw * LS + 3 * (size_t)nthreads);
 }
 
 inline int sweep_threads_cap(int es, int mmax) {
@@ -39,17 +41,32 @@ inline int sweep_threads_cap(int es, int mmax) {
 
 // Fill *out for a line of n cells.  want_wpl / want_lpw: 0 = heuristic.
 // Returns false if no configuration fits.
+inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out);
+
 inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, int want_lpw, SweepCfg* out) {
+    if (want_wpl > 0) return choose_sweep_cfg_wpl(es, ndim, n, chi, want_wpl, want_lpw, out);
+    // heuristic: the fewest waves per line that keep <= pref cells per lane;
+    // otherwise the feasible shape with the fewest cells per lane
     const int pref = es == 8 ? 8 : 16;
-    int wpl = want_wpl;
-    if (wpl <= 0) {
-        wpl = 1;
-        while (wpl < 16) {
-            const int P = std::min(64 * wpl, pow2_floor(n));
-            if ((n + P - 1) / P <= pref) break;
-            wpl *= 2;
+    SweepCfg best;
+    bool found = false;
+    for (int wpl = 1; wpl <= 16; wpl *= 2) {
+        SweepCfg c;
+        if (!choose_sweep_cfg_wpl(es, ndim, n, chi, wpl, want_lpw, &c)) continue;
+        if (c.mmax <= pref) {
+            *out = c;
+            return true;
+        }
+        if (!found || c.mmax < best.mmax) {
+            best = c;
+            found = true;
         }
     }
+    if (found) *out = best;
+    return found;
+}
+
+inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out) {
     if (wpl < 1 || wpl > 16 || (wpl & (wpl - 1))) return false;
     const int P = std::min(64 * wpl, pow2_floor(n));
     const int m = (n + P - 1) / P;
@@ -60,10 +77,10 @@ inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, in
     if (64 * wpl > cap) return false;
     int lpw = want_lpw;
     if (lpw <= 0) lpw = std::max(1, 256 / (64 * wpl));
-    while (lpw > 1 && (64 * wpl * lpw > cap || sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw, chi) > kLdsLimit))
+    while (lpw > 1 && (64 * wpl * lpw > cap || sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw) > kLdsLimit))
         lpw /= 2;
     if (64 * wpl * lpw > cap) return false;
-    if (sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw, chi) > kLdsLimit) return false;
+    if (sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw) > kLdsLimit) return false;
     out->wpl = wpl;
     out->lpw = lpw;
     out->P = P;
@@ -81,17 +98,15 @@ struct asd_grid_s {
     void* T = nullptr;
     void* b[3] = {nullptr, nullptr, nullptr};
     void* chi = nullptr;
-    bool layouts_dirty = true;
     bool ws_inited = false;
+    bool coef_valid = false;   // face coefficients computed for coef_dt
+    double coef_dt = 0.0;
     void* tmp[2] = {nullptr, nullptr};
-    char* bl[3][3] = {};
-    char* chil[3] = {};
-    double* partials = nullptr;
+    char* coef[3][3] = {};     // [sweep][alpha, beta_t1, beta_t2], sweep's input layout
+    double* partials[2] = {nullptr, nullptr};  // per-block (sum, min, max) of reducing launches
     int64_t max_blocks = 0;
-    unsigned* ticket = nullptr;
     unsigned* flags = nullptr;
     double* stats = nullptr;
-    double* e0 = nullptr;
     SweepCfg cfg[3];
     // graph cache of the step loop
     bool use_graphs = true;
@@ -106,16 +121,21 @@ struct asd_grid_s {
 // capi.cpp
 int asd_fail(int code, const char* fmt, ...);
 int check_fields(asd_grid g, bool need_T);
-int prepare(asd_grid g);
+int prepare(asd_grid g, double dt);  // dt > 0: face coefficients for dt
 int64_t layout_stride(const asd_grid g, int L, int a);
 asd::ReduceParams no_reduce();
-asd::ReduceParams make_reduce(asd_grid g, double* energy_out, const double* e0);
+asd::FoldParams no_fold();
+asd::FoldParams make_fold(asd_grid g, const double* partials, int nblocks, double* energy_out, const double* e0);
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
-                  const asd::ReduceParams& red, const SweepCfg* cfg);
-int enqueue_si_step(asd_grid g, double dt, const void* src, void* dst, const asd::ReduceParams& red);
-int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const asd::ReduceParams& red);
+                  const asd::ReduceParams& red, const asd::FoldParams& fold, const SweepCfg* cfg,
+                  int* nblocks_out);
+int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy);
+int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy);
+int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const asd::ReduceParams& red,
+                     const asd::FoldParams& fold, int* nblocks_out);
 int enqueue_copy(asd_grid g, const void* src, void* dst);
-int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0);
+int enqueue_reduce(asd_grid g, const void* x, int buf, double* energy_out, const double* e0, asd::FoldParams* fold);
+int enqueue_fold(asd_grid g, const asd::FoldParams& f);
 // graph.cpp
 int run_si_graph(asd_grid g, double dt, int nsteps, double* energy);
 int run_explicit_graph(asd_grid g, double dt, int nsteps, double* energy);

@@ -6,12 +6,17 @@
 
 namespace asd {
 
-// Fused FP64 reduction of a state: per-block partials (sum, min, max), then
-// the last block to finish (atomic ticket) folds them in a fixed order, so
-// the result does not depend on block scheduling.
+// Fused FP64 reduction of a state, without any cross-block fence: the
+// producing launch writes one (sum, min, max) partial per block; a later
+// launch on the same stream (block 0 of the next kernel, or fold_kernel)
+// folds them in a fixed order, so the result is deterministic and the
+// kernel boundary makes the partials visible.
 struct ReduceParams {
     double* partials;    // 3 doubles per block; nullptr disables the reduction
-    unsigned* ticket;    // zero before the launch; reset to zero by the last block
+};
+struct FoldParams {
+    const double* partials;  // nullptr: nothing to fold
+    int nblocks;
     double* energy_out;  // nullable: receives sum * dV
     double* stats_out;   // nullable: {sum * dV, min, max}
     unsigned* flags;     // nullable: ORed with status bits
@@ -21,27 +26,47 @@ struct ReduceParams {
 
 template <typename T>
 struct SweepParams {
-    const T* U;     // input state
-    T* out;         // output state (never aliases U)
-    const T* bn;    // b along the sweep axis, in U's layout
-    const T* bt1;   // b along transverse axis 1
-    const T* bt2;   // b along transverse axis 2 (3-D)
-    const T* chi;   // per-cell chi in U's layout, or nullptr
-    int n;          // line length
-    int nt1, nt2;   // lines along transverse axes 1, 2 (nt2 = 1 in 2-D)
-    int64_t si_n, si_t1, si_t2;  // input strides, elements
-    int64_t so_n, so_t1, so_t2;  // output strides, elements
-    T cnn;          // dt / h_n^2
-    T cnt1, cnt2;   // dt / (h_n h_t1), dt / (h_n h_t2)
-    T chi_par, chi_perp;
+    const T* U;       // input state
+    T* out;           // output state (never aliases U)
+    const T* alpha;   // normal coefficient of the face after each cell, in U's layout
+    const T* beta1;   // transverse coefficient (axis t1) of that face
+    const T* beta2;   // transverse coefficient (axis t2), 3-D only
+    int n;            // line length (input is contiguous along the line)
+    int nt1, nt2;     // lines along transverse axes 1, 2 (nt2 = 1 in 2-D)
+    int si_n, si_t1, si_t2;  // input strides, elements
+    int so_n, so_t1, so_t2;  // output strides, elements
     int periodic;
     int limiter;
-    int wpl;        // waves per line
-    int lpw;        // lines per workgroup
-    int P;          // segments per line: power of two, <= 64*wpl, <= n
-    int rhs_mode;   // 0: full sweep; 1: solve only (right-hand side = U)
+    int wpl;          // waves per line
+    int lpw;          // lines per workgroup
+    int P;            // segments per line: power of two, <= 64*wpl, <= n
+    int nseg_log2;    // log2(P)
+    int spl_log2;     // log2(64*wpl)
+    int lpw_log2;     // log2(lpw)
+    int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)
     ReduceParams red;
+    FoldParams fold;
 };
+
+// Face coefficients of the sweep along axis d, written in that sweep's
+// input layout (out strides): for every cell c, the face between c and
+// c + e_d (wrapping when periodic; zero for a wall face).
+template <typename T>
+struct CoefParams {
+    const T* b[3];       // cell-centred b, x-fastest
+    const T* chi;        // per-cell chi or nullptr
+    T* alpha;
+    T* beta1;
+    T* beta2;            // 3-D only
+    int n[3];
+    int d, t1, t2;       // sweep axis and the two transverse axes
+    int so[3];           // output stride of axes x, y, z
+    double cnn, ct1, ct2;  // dt/h_d^2, dt/(h_d h_t1), dt/(h_d h_t2)
+    double chi_par, chi_perp;
+    int periodic, ndim;
+};
+template <typename T>
+hipError_t launch_coef(const CoefParams<T>& C, hipStream_t st);
 
 // Largest workgroup a sweep instantiation is compiled for (register budget
 // of the per-lane segment arrays: seven arrays of MMAX values).
@@ -69,6 +94,7 @@ struct ExplicitParams {
     int periodic;
     int limiter;
     ReduceParams red;
+    FoldParams fold;
 };
 template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out);
@@ -80,9 +106,11 @@ int explicit_num_blocks(int ndim, const int n[3]);
 template <typename T>
 hipError_t launch_permute(const T* in, T* out, const int n[3], const int64_t dst_stride[3],
                           hipStream_t st);
-// Standalone FP64 reduction of a dense array of N elements.
+// Standalone FP64 reduction of a dense array of N elements (partials only).
 template <typename T>
 hipError_t launch_reduce(const T* x, int64_t N, const ReduceParams& red, int nblocks, hipStream_t st);
+// One block folding the partials of an earlier launch.
+hipError_t launch_fold(const FoldParams& f, hipStream_t st);
 int reduce_num_blocks(int64_t N);
 hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t count, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
@@ -92,10 +120,10 @@ template <typename T>
 hipError_t launch_axpy(T* y, const T* x, T a, int64_t N, hipStream_t st);
 
 // ------------------------------------------------- block reduction epilogue
-__device__ __forceinline__ void block_reduce_and_finish(const ReduceParams& R, double s, double mn,
-                                                        double mx) {
+// Block-wide (sum, min, max); every thread must call it.  Writes the
+// block's partial.
+__device__ __forceinline__ void block_partials(double* partials, double s, double mn, double mx) {
     __shared__ double red_s[16], red_mn[16], red_mx[16];
-    __shared__ int last;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
     for (int off = 32; off > 0; off >>= 1) {
@@ -112,21 +140,22 @@ __device__ __forceinline__ void block_reduce_and_finish(const ReduceParams& R, d
             tmn = fmin(tmn, red_mn[w]);
             tmx = fmax(tmx, red_mx[w]);
         }
-        double* pp = R.partials + 3 * (size_t)blockIdx.x;
+        double* pp = partials + 3 * (size_t)blockIdx.x;
         pp[0] = ts;
         pp[1] = tmn;
         pp[2] = tmx;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned t = atomicAdd(R.ticket, 1u);
-        last = (t == gridDim.x - 1) ? 1 : 0;
     }
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // fixed-order fold: thread i takes partials i, i+nthreads, ...
+}
+
+// Fold f.nblocks partials in a fixed order (thread i takes i, i+nthreads,
+// ..., then a fixed tree); every thread of the calling block must call it.
+__device__ __forceinline__ void fold_partials(const FoldParams& f) {
+    __shared__ double fs[16], fmn[16], fmx[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
     double ts = 0.0, tmn = __builtin_huge_val(), tmx = -__builtin_huge_val();
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-        const volatile double* pp = R.partials + 3 * (size_t)b;
+    for (int b = threadIdx.x; b < f.nblocks; b += blockDim.x) {
+        const double* pp = f.partials + 3 * (size_t)b;
         ts += pp[0];
         tmn = fmin(tmn, pp[1]);
         tmx = fmax(tmx, pp[2]);
@@ -136,30 +165,28 @@ __device__ __forceinline__ void block_reduce_and_finish(const ReduceParams& R, d
         tmn = fmin(tmn, __shfl_xor(tmn, off, 64));
         tmx = fmax(tmx, __shfl_xor(tmx, off, 64));
     }
-    __syncthreads();
-    if (lane == 0) { red_s[wid] = ts; red_mn[wid] = tmn; red_mx[wid] = tmx; }
+    if (lane == 0) { fs[wid] = ts; fmn[wid] = tmn; fmx[wid] = tmx; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double S = 0.0, MN = red_mn[0], MX = red_mx[0];
+        double S = 0.0, MN = fmn[0], MX = fmx[0];
         for (int w = 0; w < nw; ++w) {
-            S += red_s[w];
-            MN = fmin(MN, red_mn[w]);
-            MX = fmax(MX, red_mx[w]);
+            S += fs[w];
+            MN = fmin(MN, fmn[w]);
+            MX = fmax(MX, fmx[w]);
         }
-        const double E = S * R.dV;
-        if (R.energy_out) *R.energy_out = E;
-        if (R.stats_out) { R.stats_out[0] = E; R.stats_out[1] = MN; R.stats_out[2] = MX; }
-        if (R.flags) {
-            unsigned f = 0;
-            if (!(E == E) || E - E != 0.0 || !(MN == MN) || !(MX == MX) || MX - MX != 0.0) f |= 1u;
-            if (MN < 0.0) f |= 2u;
-            if (R.e0) {
-                const double e0 = *R.e0;
-                if (fabs(E - e0) > 1e-6 * fabs(e0)) f |= 4u;
+        const double E = S * f.dV;
+        if (f.energy_out) *f.energy_out = E;
+        if (f.stats_out) { f.stats_out[0] = E; f.stats_out[1] = MN; f.stats_out[2] = MX; }
+        if (f.flags) {
+            unsigned fl = 0;
+            if (!(E == E) || E - E != 0.0 || !(MN == MN) || !(MX == MX) || MX - MX != 0.0) fl |= 1u;
+            if (MN < 0.0) fl |= 2u;
+            if (f.e0) {
+                const double e0 = *f.e0;
+                if (fabs(E - e0) > 1e-6 * fabs(e0)) fl |= 4u;
             }
-            if (f) atomicOr(R.flags, f);
+            if (fl) *f.flags |= fl;
         }
-        *R.ticket = 0u;
     }
 }
 

@@ -65,7 +65,7 @@ static void bench_buffers(asd_grid g, int axis, const void** in, void** out) {
 static int bench_prepare_inputs(asd_grid g, double dt) {
     for (int axis = 0; axis + 1 < g->d.ndim; ++axis) {
         const void* in = axis == 0 ? g->T : g->tmp[axis - 1];
-        int rc = enqueue_sweep(g, axis, dt, in, g->tmp[axis], 0, no_reduce(), nullptr);
+        int rc = enqueue_sweep(g, axis, dt, in, g->tmp[axis], 0, no_reduce(), no_fold(), nullptr, nullptr);
         if (rc) return rc;
     }
     return ASD_OK;
@@ -78,14 +78,14 @@ extern "C" int asd_bench_sweep(asd_grid g, int32_t axis, double dt, int32_t reps
     if (reps < 0) return asd_fail(ASD_EINVAL, "reps must be >= 0");
     int rc = check_fields(g, true);
     if (rc) return rc;
-    rc = prepare(g);
+    rc = prepare(g, dt);
     if (rc) return rc;
     if (reps == 0) return bench_prepare_inputs(g, dt);
     const void* in;
     void* out;
     bench_buffers(g, axis, &in, &out);
     for (int r = 0; r < reps; ++r) {
-        rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), nullptr);
+        rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), no_fold(), nullptr, nullptr);
         if (rc) return rc;
     }
     return ASD_OK;
@@ -111,9 +111,9 @@ static int time_cfg(asd_grid g, int axis, double dt, int reps, const SweepCfg& c
         (void)hipEventDestroy(e0);
         return asd_fail(ASD_EHIP, "event create");
     }
-    int rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), &c);  // warm-up
+    int rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), no_fold(), &c, nullptr);  // warm-up
     if (!rc && hipEventRecord(e0, g->st) != hipSuccess) rc = asd_fail(ASD_EHIP, "event record");
-    for (int r = 0; !rc && r < reps; ++r) rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), &c);
+    for (int r = 0; !rc && r < reps; ++r) rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), no_fold(), &c, nullptr);
     if (!rc && hipEventRecord(e1, g->st) != hipSuccess) rc = asd_fail(ASD_EHIP, "event record");
     if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = asd_fail(ASD_EHIP, "event sync");
     if (!rc && hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = asd_fail(ASD_EHIP, "elapsed");
@@ -128,7 +128,7 @@ extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
     if (reps < 1) return asd_fail(ASD_EINVAL, "reps must be >= 1");
     int rc = check_fields(g, true);
     if (rc) return rc;
-    rc = prepare(g);
+    rc = prepare(g, dt);
     if (rc) return rc;
     const bool chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) != 0;
     rc = bench_prepare_inputs(g, dt);  // T itself is untouched

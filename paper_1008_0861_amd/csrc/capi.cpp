@@ -7,8 +7,9 @@
 //   2-D:  x-sweep  A=[y][x] -> B=[x][y];  y-sweep B -> A
 //   3-D:  x-sweep  A=[z][y][x] -> B=[z][x][y];  y-sweep B -> C=[y][x][z];
 //         z-sweep  C -> A
-// b (and a per-cell chi) are static, so their B and C copies are made once
-// per asd_set_field, in the caller's workspace.
+// The face coefficients of each sweep (alpha, beta_t) depend only on dt, b
+// and chi: they are computed once per dt in that sweep's input layout, in
+// the caller's workspace, and the sweeps read them instead of b.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -72,7 +73,7 @@ static int validate_desc(const asd_desc* d) {
     if (!std::isfinite(d->chi_perp) || d->chi_perp < 0.0 || d->chi_perp > d->chi_par)
         return asd_fail(ASD_EINVAL, "chi_perp must be in [0, chi_par]");
     const int64_t N = d->n[0] * d->n[1] * (d->ndim == 3 ? d->n[2] : 1);
-    if (N > (int64_t)1 << 34) return asd_fail(ASD_EUNSUPPORTED, "grid too large");
+    if (N > (int64_t)INT32_MAX) return asd_fail(ASD_EUNSUPPORTED, "grid too large (more than 2^31-1 cells)");
     for (int q = 0; q < d->ndim; ++q) {
         SweepCfg c;
         if (!choose_sweep_cfg(d->dtype == ASD_F64 ? 8 : 4, d->ndim, (int)d->n[q],
@@ -89,7 +90,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace plan: offsets of each region.
 struct WsPlan {
-    size_t tmp[2], bl[3][3], chil[3], partials, small, total;
+    size_t tmp[2], coef[3][3], partials, small, total;
     int64_t max_blocks;
 };
 
@@ -110,18 +111,14 @@ static WsPlan plan_ws(const asd_desc* d) {
     const int ntmp = 2;  // sweep intermediates / explicit ping-pong / benchmark outputs
     for (int i = 0; i < 2; ++i) p.tmp[i] = (size_t)-1;
     for (int i = 0; i < ntmp; ++i) { p.tmp[i] = off; off += fb; }
-    for (int L = 0; L < 3; ++L) {
-        for (int q = 0; q < 3; ++q) p.bl[L][q] = (size_t)-1;
-        p.chil[L] = (size_t)-1;
-    }
-    const int nlay = d->ndim == 3 ? 3 : 2;  // layout 0 is the user's
-    for (int L = 1; L < nlay; ++L) {
-        for (int q = 0; q < d->ndim; ++q) { p.bl[L][q] = off; off += fb; }
-        if (d->flags & ASD_FLAG_PER_CELL_CHI) { p.chil[L] = off; off += fb; }
-    }
+    // face coefficients: per sweep direction alpha and one beta per transverse axis
+    for (int dd = 0; dd < 3; ++dd)
+        for (int q = 0; q < 3; ++q) p.coef[dd][q] = (size_t)-1;
+    for (int dd = 0; dd < d->ndim; ++dd)
+        for (int q = 0; q < d->ndim; ++q) { p.coef[dd][q] = off; off += fb; }
     p.max_blocks = max_reduce_blocks(d);
-    p.partials = off;
-    off += align256((size_t)p.max_blocks * 3 * sizeof(double));
+    p.partials = off;  // two buffers, alternated by successive producers
+    off += 2 * align256((size_t)p.max_blocks * 3 * sizeof(double));
     p.small = off;
     off += 256;
     p.total = off;
@@ -157,17 +154,14 @@ extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes
     g->N = cells(desc);
     g->es = desc->dtype == ASD_F64 ? 8 : 4;
     for (int i = 0; i < 2; ++i) g->tmp[i] = p.tmp[i] == (size_t)-1 ? nullptr : g->ws + p.tmp[i];
-    for (int L = 0; L < 3; ++L) {
-        for (int q = 0; q < 3; ++q) g->bl[L][q] = p.bl[L][q] == (size_t)-1 ? nullptr : g->ws + p.bl[L][q];
-        g->chil[L] = p.chil[L] == (size_t)-1 ? nullptr : g->ws + p.chil[L];
-    }
-    g->partials = (double*)(g->ws + p.partials);
+    for (int dd = 0; dd < 3; ++dd)
+        for (int q = 0; q < 3; ++q) g->coef[dd][q] = p.coef[dd][q] == (size_t)-1 ? nullptr : g->ws + p.coef[dd][q];
+    g->partials[0] = (double*)(g->ws + p.partials);
+    g->partials[1] = (double*)(g->ws + p.partials + align256((size_t)p.max_blocks * 3 * sizeof(double)));
     g->max_blocks = p.max_blocks;
     char* sm = g->ws + p.small;
-    g->ticket = (unsigned*)sm;
-    g->flags = (unsigned*)(sm + 4);
+    g->flags = (unsigned*)sm;
     g->stats = (double*)(sm + 8);   // 3 doubles
-    g->e0 = (double*)(sm + 32);
     for (int q = 0; q < desc->ndim; ++q) {
         if (!choose_sweep_cfg((int)g->es, desc->ndim, (int)desc->n[q],
                               (desc->flags & ASD_FLAG_PER_CELL_CHI) != 0, 0, 0, &g->cfg[q])) {
@@ -195,18 +189,18 @@ extern "C" int asd_set_field(asd_grid g, int32_t field, void* dev_ptr, int64_t n
                         (long long)g->N);
     switch (field) {
         case ASD_FIELD_T: g->T = dev_ptr; break;
-        case ASD_FIELD_BX: g->b[0] = dev_ptr; g->layouts_dirty = true; break;
-        case ASD_FIELD_BY: g->b[1] = dev_ptr; g->layouts_dirty = true; break;
+        case ASD_FIELD_BX: g->b[0] = dev_ptr; g->coef_valid = false; break;
+        case ASD_FIELD_BY: g->b[1] = dev_ptr; g->coef_valid = false; break;
         case ASD_FIELD_BZ:
             if (g->d.ndim != 3) return asd_fail(ASD_EINVAL, "BZ set on a 2-D grid");
             g->b[2] = dev_ptr;
-            g->layouts_dirty = true;
+            g->coef_valid = false;
             break;
         case ASD_FIELD_CHI:
             if (!(g->d.flags & ASD_FLAG_PER_CELL_CHI))
                 return asd_fail(ASD_EINVAL, "CHI set without ASD_FLAG_PER_CELL_CHI");
             g->chi = dev_ptr;
-            g->layouts_dirty = true;
+            g->coef_valid = false;
             break;
         default: return asd_fail(ASD_EINVAL, "unknown field %d", field);
     }
@@ -233,46 +227,6 @@ int64_t layout_stride(const asd_grid g, int L, int a) {
     return s[a];
 }
 
-const void* field_in_layout(const asd_grid g, int L, int q) {
-    return L == 0 ? g->b[q] : g->bl[L][q];
-}
-const void* chi_in_layout(const asd_grid g, int L) { return L == 0 ? g->chi : g->chil[L]; }
-
-static std::once_flag g_attr_once;
-static hipError_t g_attr_err = hipSuccess;
-
-template <typename T>
-static int do_prepare(asd_grid g) {
-    std::call_once(g_attr_once, [] { g_attr_err = sweep_set_lds_limits((int)kLdsLimit); });
-    if (g_attr_err != hipSuccess) return hip_check(g_attr_err, "kernel attributes");
-    if (!g->ws_inited) {
-        int rc = hip_check(launch_fill_u32(g->ticket, 0u, 2, g->st), "fill");
-        if (rc) return rc;
-        g->ws_inited = true;
-    }
-    if (g->layouts_dirty) {
-        const int n[3] = {(int)g->d.n[0], (int)g->d.n[1], g->d.ndim == 3 ? (int)g->d.n[2] : 1};
-        const int nlay = g->d.ndim == 3 ? 3 : 2;
-        for (int L = 1; L < nlay; ++L) {
-            const int64_t ds[3] = {layout_stride(g, L, 0), layout_stride(g, L, 1), layout_stride(g, L, 2)};
-            for (int q = 0; q < g->d.ndim; ++q) {
-                int rc = hip_check(launch_permute<T>((const T*)g->b[q], (T*)g->bl[L][q], n, ds, g->st), "permute b");
-                if (rc) return rc;
-            }
-            if (g->chi) {
-                int rc = hip_check(launch_permute<T>((const T*)g->chi, (T*)g->chil[L], n, ds, g->st), "permute chi");
-                if (rc) return rc;
-            }
-        }
-        g->layouts_dirty = false;
-    }
-    return ASD_OK;
-}
-
-int prepare(asd_grid g) { return g->es == 8 ? do_prepare<double>(g) : do_prepare<float>(g); }
-
-// --------------------------------------------------------------- sweeps
-
 // the three sweeps: axis, input layout, output layout, t1 (fastest of out), t2
 struct SweepGeom { int d, Lin, Lout, t1, t2; };
 static SweepGeom sweep_geom(int ndim, int d) {
@@ -285,98 +239,153 @@ static SweepGeom sweep_geom(int ndim, int d) {
     return {2, 2, 0, 0, 1};
 }
 
+static std::once_flag g_attr_once;
+static hipError_t g_attr_err = hipSuccess;
+
+template <typename T>
+static int do_prepare(asd_grid g, double dt) {
+    std::call_once(g_attr_once, [] { g_attr_err = sweep_set_lds_limits((int)kLdsLimit); });
+    if (g_attr_err != hipSuccess) return hip_check(g_attr_err, "kernel attributes");
+    if (!g->ws_inited) {
+        int rc = hip_check(launch_fill_u32(g->flags, 0u, 1, g->st), "fill");
+        if (rc) return rc;
+        g->ws_inited = true;
+    }
+    if (dt > 0.0 && !(g->coef_valid && g->coef_dt == dt)) {
+        const int nd = g->d.ndim;
+        for (int d = 0; d < nd; ++d) {
+            const SweepGeom G = sweep_geom(nd, d);
+            CoefParams<T> C{};
+            for (int q = 0; q < 3; ++q) C.b[q] = q < nd ? (const T*)g->b[q] : nullptr;
+            C.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)g->chi : nullptr;
+            C.alpha = (T*)g->coef[d][0];
+            C.beta1 = (T*)g->coef[d][1];
+            C.beta2 = nd == 3 ? (T*)g->coef[d][2] : nullptr;
+            C.n[0] = (int)g->d.n[0];
+            C.n[1] = (int)g->d.n[1];
+            C.n[2] = nd == 3 ? (int)g->d.n[2] : 1;
+            C.d = G.d;
+            C.t1 = G.t1;
+            C.t2 = G.t2;
+            for (int a = 0; a < 3; ++a) C.so[a] = (int)layout_stride(g, G.Lin, a);
+            const double hd = g->d.h[G.d];
+            const double h1 = g->d.h[G.t1];
+            const double h2 = nd == 3 ? g->d.h[G.t2] : 1.0;
+            C.cnn = dt / (hd * hd);
+            C.ct1 = dt / (hd * h1);
+            C.ct2 = dt / (hd * h2);
+            C.chi_par = g->d.chi_par;
+            C.chi_perp = g->d.chi_perp;
+            C.periodic = g->d.bc == ASD_BC_PERIODIC;
+            C.ndim = nd;
+            int rc = hip_check(launch_coef<T>(C, g->st), "coefficient launch");
+            if (rc) return rc;
+        }
+        g->coef_valid = true;
+        g->coef_dt = dt;
+        g->graph_valid = false;
+    }
+    return ASD_OK;
+}
+
+int prepare(asd_grid g, double dt) { return g->es == 8 ? do_prepare<double>(g, dt) : do_prepare<float>(g, dt); }
+
+// --------------------------------------------------------------- sweeps
+
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+
 ReduceParams no_reduce() {
     ReduceParams r{};
     return r;
 }
+FoldParams no_fold() {
+    FoldParams f{};
+    return f;
+}
 
-ReduceParams make_reduce(asd_grid g, double* energy_out, const double* e0) {
-    ReduceParams r{};
-    r.partials = g->partials;
-    r.ticket = g->ticket;
-    r.energy_out = energy_out;
-    r.stats_out = g->stats;
-    r.flags = g->flags;
-    r.e0 = e0;
+FoldParams make_fold(asd_grid g, const double* partials, int nblocks, double* energy_out, const double* e0) {
+    FoldParams f{};
+    f.partials = partials;
+    f.nblocks = nblocks;
+    f.energy_out = energy_out;
+    f.stats_out = g->stats;
+    f.flags = g->flags;
+    f.e0 = e0;
     double dv = 1.0;
     for (int q = 0; q < g->d.ndim; ++q) dv *= g->d.h[q];
-    r.dV = dv;
-    return r;
+    f.dV = dv;
+    return f;
 }
 
 template <typename T>
 static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
-                           const ReduceParams& red, const SweepCfg* override_cfg) {
+                           const ReduceParams& red, const FoldParams& fold, const SweepCfg* override_cfg,
+                           int* nblocks_out) {
     const SweepGeom G = sweep_geom(g->d.ndim, d);
     const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
     SweepParams<T> P{};
     P.U = (const T*)in;
     P.out = (T*)out;
-    P.bn = (const T*)field_in_layout(g, G.Lin, G.d);
-    P.bt1 = (const T*)field_in_layout(g, G.Lin, G.t1);
-    P.bt2 = g->d.ndim == 3 ? (const T*)field_in_layout(g, G.Lin, G.t2) : nullptr;
-    P.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)chi_in_layout(g, G.Lin) : nullptr;
+    P.alpha = (const T*)g->coef[d][0];
+    P.beta1 = (const T*)g->coef[d][1];
+    P.beta2 = g->d.ndim == 3 ? (const T*)g->coef[d][2] : nullptr;
     const int64_t nz = g->d.ndim == 3 ? g->d.n[2] : 1;
     const int64_t nax[3] = {g->d.n[0], g->d.n[1], nz};
     P.n = (int)nax[G.d];
     P.nt1 = (int)nax[G.t1];
     P.nt2 = (int)nax[G.t2];
-    P.si_n = layout_stride(g, G.Lin, G.d);
-    P.si_t1 = layout_stride(g, G.Lin, G.t1);
-    P.si_t2 = layout_stride(g, G.Lin, G.t2);
-    P.so_n = layout_stride(g, G.Lout, G.d);
-    P.so_t1 = layout_stride(g, G.Lout, G.t1);
-    P.so_t2 = layout_stride(g, G.Lout, G.t2);
-    const double hn = g->d.h[G.d];
-    const double h1 = g->d.h[G.t1 < g->d.ndim ? G.t1 : 0];
-    const double h2 = g->d.ndim == 3 ? g->d.h[G.t2] : 1.0;
-    P.cnn = (T)(dt / (hn * hn));
-    P.cnt1 = (T)(dt / (hn * h1));
-    P.cnt2 = (T)(dt / (hn * h2));
-    P.chi_par = (T)g->d.chi_par;
-    P.chi_perp = (T)g->d.chi_perp;
+    P.si_n = (int)layout_stride(g, G.Lin, G.d);
+    P.si_t1 = (int)layout_stride(g, G.Lin, G.t1);
+    P.si_t2 = (int)layout_stride(g, G.Lin, G.t2);
+    P.so_n = (int)layout_stride(g, G.Lout, G.d);
+    P.so_t1 = (int)layout_stride(g, G.Lout, G.t1);
+    P.so_t2 = (int)layout_stride(g, G.Lout, G.t2);
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
     P.limiter = g->d.limiter;
     P.wpl = c.wpl;
     P.lpw = c.lpw;
     P.P = c.P;
+    P.nseg_log2 = ilog2(c.P);
+    P.spl_log2 = ilog2(64 * c.wpl);
+    P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode;
+    if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
     P.red = red;
+    P.fold = fold;
     const int nb1 = (P.nt1 + c.lpw - 1) / c.lpw;
     const int64_t nblocks = (int64_t)nb1 * P.nt2;
+    if (nblocks_out) *nblocks_out = (int)nblocks;
     if (red.partials && nblocks > g->max_blocks)
         return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
-    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), P.chi != nullptr);
+    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads());
     return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st),
                      "sweep launch");
 }
 
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode, const ReduceParams& red,
-                  const SweepCfg* cfg) {
-    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, cfg)
-                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, cfg);
+                  const FoldParams& fold, const SweepCfg* cfg, int* nblocks_out) {
+    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, fold, cfg, nblocks_out)
+                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, fold, cfg, nblocks_out);
 }
 
-int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0) {
+// Reduce a state into partial buffer `buf`; returns the fold that finishes it.
+int enqueue_reduce(asd_grid g, const void* x, int buf, double* energy_out, const double* e0, FoldParams* fold) {
     const int nb = reduce_num_blocks(g->N);
-    ReduceParams r = make_reduce(g, energy_out, e0);
+    ReduceParams r{};
+    r.partials = g->partials[buf];
     hipError_t e = g->es == 8 ? launch_reduce<double>((const double*)x, g->N, r, nb, g->st)
                               : launch_reduce<float>((const float*)x, g->N, r, nb, g->st);
+    *fold = make_fold(g, g->partials[buf], nb, energy_out, e0);
     return hip_check(e, "reduce launch");
 }
 
-// One semi-implicit step from `src` (layout A) into `dst` (layout A); the
-// last sweep may carry the fused reduction.
-int enqueue_si_step(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red) {
-    const int nd = g->d.ndim;
-    const void* in = src;
-    for (int d = 0; d < nd; ++d) {
-        void* out = (d == nd - 1) ? dst : g->tmp[d];
-        int rc = enqueue_sweep(g, d, dt, in, out, 0, d == nd - 1 ? red : no_reduce(), nullptr);
-        if (rc) return rc;
-        in = out;
-    }
-    return ASD_OK;
+int enqueue_fold(asd_grid g, const FoldParams& f) {
+    if (!f.partials) return ASD_OK;
+    return hip_check(launch_fold(f, g->st), "fold launch");
 }
 
 static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
@@ -399,6 +408,40 @@ static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
     return ASD_OK;
 }
 
+// The whole multi-step call as a kernel sequence (used eagerly and under
+// graph capture).  Energy: the initial state is reduced first; every step's
+// last kernel writes per-block partials that the next kernel (or a final
+// fold) folds into energy[s+1].
+int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy) {
+    const int nd = g->d.ndim;
+    int buf = 0;
+    FoldParams pending = no_fold();
+    int rc = ASD_OK;
+    if (energy) {
+        rc = enqueue_reduce(g, g->T, buf, energy, nullptr, &pending);
+        buf ^= 1;
+    }
+    for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
+        const void* in = g->T;
+        for (int d = 0; d < nd && rc == ASD_OK; ++d) {
+            void* out = (d == nd - 1) ? g->T : g->tmp[d];
+            const bool produce = energy && d == nd - 1;
+            ReduceParams red = no_reduce();
+            if (produce) red.partials = g->partials[buf];
+            int nb = 0;
+            rc = enqueue_sweep(g, d, dt, in, out, 0, red, d == 0 ? pending : no_fold(), nullptr, &nb);
+            if (d == 0) pending = no_fold();
+            if (produce) {
+                pending = make_fold(g, g->partials[buf], nb, energy + s + 1, energy);
+                buf ^= 1;
+            }
+            in = out;
+        }
+    }
+    if (rc == ASD_OK) rc = enqueue_fold(g, pending);
+    return rc;
+}
+
 extern "C" int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, double* dev_energy) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
     if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
@@ -406,24 +449,16 @@ extern "C" int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, dou
     if (rc) return rc;
     rc = check_fields(g, true);
     if (rc) return rc;
-    rc = prepare(g);
+    rc = prepare(g, dt);
     if (rc) return rc;
-    if (dev_energy) {
-        rc = enqueue_reduce(g, g->T, dev_energy, nullptr);
-        if (rc) return rc;
-    }
-    if (nsteps == 0) return ASD_OK;
-    if (g->use_graphs && nsteps >= 2) return run_si_graph(g, dt, nsteps, dev_energy);
-    for (int s = 0; s < nsteps; ++s) {
-        ReduceParams red = dev_energy ? make_reduce(g, dev_energy + s + 1, dev_energy) : no_reduce();
-        rc = enqueue_si_step(g, dt, g->T, g->T, red);
-        if (rc) return rc;
-    }
-    return ASD_OK;
+    // the legacy default stream cannot be captured: launch eagerly there
+    if (g->use_graphs && g->st && nsteps >= 2) return run_si_graph(g, dt, nsteps, dev_energy);
+    return enqueue_si_loop(g, dt, nsteps, dev_energy);
 }
 
 template <typename T>
-static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red) {
+static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red,
+                              const FoldParams& fold, int* nblocks_out) {
     ExplicitParams<T> P{};
     P.U = (const T*)src;
     P.out = (T*)dst;
@@ -445,18 +480,45 @@ static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst,
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
     P.limiter = g->d.limiter;
     P.red = red;
-    return hip_check(launch_explicit<T>(P, g->d.ndim, g->st, nullptr), "explicit launch");
+    P.fold = fold;
+    return hip_check(launch_explicit<T>(P, g->d.ndim, g->st, nblocks_out), "explicit launch");
 }
 
-int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red) {
-    return g->es == 8 ? enqueue_explicit_t<double>(g, dt, src, dst, red)
-                      : enqueue_explicit_t<float>(g, dt, src, dst, red);
+int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red,
+                     const FoldParams& fold, int* nblocks_out) {
+    return g->es == 8 ? enqueue_explicit_t<double>(g, dt, src, dst, red, fold, nblocks_out)
+                      : enqueue_explicit_t<float>(g, dt, src, dst, red, fold, nblocks_out);
 }
 
 int enqueue_copy(asd_grid g, const void* src, void* dst) {
     hipError_t e = g->es == 8 ? launch_copy<double>((const double*)src, (double*)dst, g->N, g->st)
                               : launch_copy<float>((const float*)src, (float*)dst, g->N, g->st);
     return hip_check(e, "copy launch");
+}
+
+// Explicit steps ping-pong between T and tmp[0]; an odd count ends with a copy.
+int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy) {
+    int buf = 0;
+    FoldParams pending = no_fold();
+    int rc = ASD_OK;
+    if (energy) {
+        rc = enqueue_reduce(g, g->T, buf, energy, nullptr, &pending);
+        buf ^= 1;
+    }
+    void* a = g->T;
+    void* b = g->tmp[0];
+    for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
+        ReduceParams red = no_reduce();
+        if (energy) red.partials = g->partials[buf];
+        int nb = 0;
+        rc = enqueue_explicit(g, dt, a, b, red, pending, &nb);
+        pending = energy ? make_fold(g, g->partials[buf], nb, energy + s + 1, energy) : no_fold();
+        buf ^= 1;
+        std::swap(a, b);
+    }
+    if (rc == ASD_OK) rc = enqueue_fold(g, pending);
+    if (rc == ASD_OK && a != g->T) rc = enqueue_copy(g, a, g->T);
+    return rc;
 }
 
 extern "C" int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, double* dev_energy) {
@@ -466,24 +528,10 @@ extern "C" int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, 
     if (rc) return rc;
     rc = check_fields(g, true);
     if (rc) return rc;
-    rc = prepare(g);
+    rc = prepare(g, 0.0);
     if (rc) return rc;
-    if (dev_energy) {
-        rc = enqueue_reduce(g, g->T, dev_energy, nullptr);
-        if (rc) return rc;
-    }
-    if (nsteps == 0) return ASD_OK;
-    if (g->use_graphs && nsteps >= 2) return run_explicit_graph(g, dt, nsteps, dev_energy);
-    void* a = g->T;
-    void* b = g->tmp[0];
-    for (int s = 0; s < nsteps; ++s) {
-        ReduceParams red = dev_energy ? make_reduce(g, dev_energy + s + 1, dev_energy) : no_reduce();
-        rc = enqueue_explicit(g, dt, a, b, red);
-        if (rc) return rc;
-        std::swap(a, b);
-    }
-    if (a != g->T) return enqueue_copy(g, a, g->T);
-    return ASD_OK;
+    if (g->use_graphs && g->st && nsteps >= 2) return run_explicit_graph(g, dt, nsteps, dev_energy);
+    return enqueue_explicit_loop(g, dt, nsteps, dev_energy);
 }
 
 extern "C" int asd_status(asd_grid g, uint32_t* flags, double* stats) {
@@ -491,19 +539,22 @@ extern "C" int asd_status(asd_grid g, uint32_t* flags, double* stats) {
     if (!flags) return asd_fail(ASD_EINVAL, "flags is NULL");
     int rc = check_fields(g, true);
     if (rc) return rc;
-    rc = prepare(g);
+    rc = prepare(g, 0.0);
     if (rc) return rc;
-    rc = enqueue_reduce(g, g->T, nullptr, nullptr);
+    FoldParams f;
+    rc = enqueue_reduce(g, g->T, 0, nullptr, nullptr, &f);
+    if (rc) return rc;
+    rc = enqueue_fold(g, f);
     if (rc) return rc;
     rc = hip_check(hipStreamSynchronize(g->st), "stream synchronize");
     if (rc) return rc;
-    unsigned f = 0;
+    unsigned fl = 0;
     double st[3];
-    rc = hip_check(hipMemcpy(&f, g->flags, sizeof f, hipMemcpyDeviceToHost), "flags copy");
+    rc = hip_check(hipMemcpy(&fl, g->flags, sizeof fl, hipMemcpyDeviceToHost), "flags copy");
     if (rc) return rc;
     rc = hip_check(hipMemcpy(st, g->stats, sizeof st, hipMemcpyDeviceToHost), "stats copy");
     if (rc) return rc;
-    *flags = f;
+    *flags = fl;
     if (stats) memcpy(stats, st, sizeof st);
     // flags are sticky between status calls: clear them now they are reported
     return hip_check(launch_fill_u32(g->flags, 0u, 1, g->st), "flags reset");

@@ -44,19 +44,35 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     const int lim = P.limiter;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
 
-    // stage the box [x0-1, x0+TX] x [y0-1, y0+TY] (x [z0-1, z0+TZ])
-    for (int i = threadIdx.x; i < TL::NB; i += blockDim.x) {
-        const int bx = i % TL::BX, by = (i / TL::BX) % TL::BY, bz = i / (TL::BX * TL::BY);
-        const int64_t x = nb_coord(x0 - 1 + bx, nx, periodic);
-        const int64_t y = nb_coord(y0 - 1 + by, ny, periodic);
-        const int64_t z = NDIM == 3 ? nb_coord(z0 - 1 + bz, nz, periodic) : 0;
-        // cells beyond the far edge of a partial tile are clamped (never used)
-        const int64_t xc = x < nx ? x : nx - 1, yc = y < ny ? y : ny - 1, zc = z < nz ? z : nz - 1;
-        const int64_t c = xc + yc * sy + zc * sz;
-        sU[i] = P.U[c];
+    // stage the box [x0-1, x0+TX] x [y0-1, y0+TY] (x [z0-1, z0+TZ]); all of a
+    // thread's loads are issued before any is stored to LDS
+    constexpr int IT = (TL::NB + TL::NT - 1) / TL::NT;
+    {
+        T vu[IT], vb[NDIM][IT], vc[IT];
 #pragma unroll
-        for (int d = 0; d < NDIM; ++d) sB[d][i] = P.b[d][c];
-        if (P.chi) sChi[i] = P.chi[c];
+        for (int j = 0; j < IT; ++j) {
+            const int i = threadIdx.x + j * TL::NT;
+            const int ii = i < TL::NB ? i : 0;
+            const int bx = ii % TL::BX, by = (ii / TL::BX) % TL::BY, bz = ii / (TL::BX * TL::BY);
+            // cells beyond the far edge of a partial tile map to valid cells (never used)
+            const int64_t x = nb_coord(x0 - 1 + bx, nx, periodic);
+            const int64_t y = nb_coord(y0 - 1 + by, ny, periodic);
+            const int64_t z = NDIM == 3 ? nb_coord(z0 - 1 + bz, nz, periodic) : 0;
+            const int64_t c = x + y * sy + z * sz;
+            vu[j] = P.U[c];
+#pragma unroll
+            for (int d = 0; d < NDIM; ++d) vb[d][j] = P.b[d][c];
+            if (P.chi) vc[j] = P.chi[c];
+        }
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int i = threadIdx.x + j * TL::NT;
+            if (i >= TL::NB) continue;
+            sU[i] = vu[j];
+#pragma unroll
+            for (int d = 0; d < NDIM; ++d) sB[d][i] = vb[d][j];
+            if (P.chi) sChi[i] = vc[j];
+        }
     }
     __syncthreads();
     const int bstr[3] = {1, TL::BX, TL::BX * TL::BY};
@@ -116,7 +132,8 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
         lsum = (double)un;
         lmin = lmax = (double)un;
     }
-    if (P.red.partials) block_reduce_and_finish(P.red, lsum, lmin, lmax);
+    if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
+    if (P.fold.partials && blockIdx.x == 0) fold_partials(P.fold);
 }
 
 int explicit_num_blocks(int ndim, const int n[3]) {

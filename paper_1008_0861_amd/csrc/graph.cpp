@@ -9,15 +9,7 @@
 using namespace asd;
 
 static int run_graph(asd_grid g, int kind, double dt, int nsteps, double* energy) {
-    if (!g->st) {
-        // the legacy default stream cannot be captured: launch directly
-        g->use_graphs = false;
-        int rc = kind == 1 ? asd_step_semi_implicit(g, dt, nsteps, nullptr)
-                           : asd_step_explicit_limited(g, dt, nsteps, nullptr);
-        g->use_graphs = true;
-        (void)energy;
-        return rc;
-    }
+    // callers only come here with a capturable (non-default) stream
     const bool hit = g->graph_valid && g->graph_kind == kind && g->graph_dt == dt &&
                      g->graph_nsteps == nsteps && g->graph_energy == energy && g->graph_exec;
     if (!hit) {
@@ -28,24 +20,7 @@ static int run_graph(asd_grid g, int kind, double dt, int nsteps, double* energy
         g->graph_valid = false;
         hipError_t e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return asd_fail(ASD_EHIP, "begin capture: %s", hipGetErrorString(e));
-        int rc = ASD_OK;
-        if (kind == 1) {
-            for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
-                ReduceParams red = energy ? make_reduce(g, energy + s + 1, energy) : no_reduce();
-                rc = enqueue_si_step(g, dt, g->T, g->T, red);
-            }
-        } else {
-            void* a = g->T;
-            void* b = g->tmp[0];
-            for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
-                ReduceParams red = energy ? make_reduce(g, energy + s + 1, energy) : no_reduce();
-                rc = enqueue_explicit(g, dt, a, b, red);
-                void* t = a;
-                a = b;
-                b = t;
-            }
-            if (rc == ASD_OK && a != g->T) rc = enqueue_copy(g, a, g->T);
-        }
+        const int rc = kind == 1 ? enqueue_si_loop(g, dt, nsteps, energy) : enqueue_explicit_loop(g, dt, nsteps, energy);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(g->st, &graph);
         if (rc != ASD_OK) {

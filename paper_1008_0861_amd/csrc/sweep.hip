@@ -4,25 +4,26 @@
 //     out = (1 + dt D_nn)^-1 ( U + F_{p+1/2} - F_{p-1/2} )      along each line
 //
 // with, at the face between line cells p and p+1,
-//     b_f     = (b_p + b_{p+1}) / 2                       (arithmetic mean)
-//     chi_f   = chi_par, or the harmonic mean of the two cells
-//     alpha_f = dt (chi_perp + (chi_f - chi_perp) bn_f^2) / h_n^2
-//     F_f     = dt (chi_f - chi_perp) bn_f sum_t bt_f L(s_t(p+1), s_t(p)) / (h_n h_t)
-//     s_t(c)  = L(U[c+e_t] - U[c], U[c] - U[c-e_t])       (limited cell slope)
-// and wall faces (insulating walls) carrying no flux.
+//     alpha_f = dt D_nn,f / h_n^2                  (precomputed, coef.hip)
+//     F_f     = sum_t beta_t,f L(s_t(p+1), s_t(p))  beta_t,f = dt D_nt,f/(h_n h_t)
+//     s_t(c)  = L(U[c+e_t] - U[c], U[c] - U[c-e_t])  (limited cell slope)
+// Wall faces (insulating walls) have alpha = beta = 0 in the coefficient
+// arrays, so every line is handled as a cyclic system.
 //
 // gfx950 mapping.  A workgroup owns `lpw` neighbouring lines; each line is
 // owned by `wpl` waves.  Phase 1 streams the lines (and the neighbouring
-// lines needed for the transverse slopes) from HBM with coalesced loads into
-// LDS.  Phase 2 splits each line into P contiguous segments, one per lane;
-// a lane eliminates its segment interior in registers, leaving one interface
-// unknown per segment (the segment's last cell).  The P interface unknowns
-// form a cyclic tridiagonal system (the Schur complement), solved by
-// parallel cyclic reduction in LDS in log2(P) steps; lanes then
-// back-substitute their interiors.  Phase 3 writes the line tile back,
-// optionally transposed (so the next sweep again reads contiguous lines).
-// All systems are symmetric, strictly diagonally dominant M-matrices, so no
-// pivoting is needed anywhere.
+// lines needed for the transverse slopes) from HBM into LDS with coalesced
+// loads, all issued before use.  Phase 2 splits each line into P contiguous
+// segments, one per lane; a lane eliminates its segment interior in
+// registers, leaving one interface unknown per segment (its last cell).
+// The P interface unknowns form a cyclic tridiagonal system (the Schur
+// complement), solved by parallel cyclic reduction in log2(P) steps: across
+// lanes with shuffles when a wave owns the line, through LDS otherwise.
+// Each equation is kept normalised (unit diagonal), so a reduction step
+// costs one reciprocal.  Phase 3 writes the tile back, transposed when the
+// output layout has the transverse axis fastest (the next sweep then reads
+// contiguous lines again).  The systems are symmetric, strictly diagonally
+// dominant M-matrices: no pivoting anywhere.
 #include "asd_device.h"
 #include "asd_launch.h"
 
@@ -38,24 +39,23 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
     const int seg_per_line = 64 * P.wpl;  // lanes per line
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
+    const bool solve_only = P.rhs_mode != 0;
 
     // LDS regions, each lpw * LS elements
     T* sU = smem;
-    T* sS1 = sU + lpw * LS;
-    T* sS2 = sS1 + lpw * LS;            // 3-D only
-    T* sBn = sS2 + (NDIM == 3 ? lpw * LS : 0);
-    T* sB1 = sBn + lpw * LS;
-    T* sB2 = sB1 + lpw * LS;            // 3-D only
-    T* sChi = sB2 + (NDIM == 3 ? lpw * LS : 0);  // only if per-cell chi
-    T* pcr = sChi + (P.chi ? lpw * LS : 0);       // 4 * nthreads elements
+    T* sA = sU + lpw * LS;
+    T* sS1 = sA + lpw * LS;
+    T* sB1 = sS1 + lpw * LS;
+    T* sS2 = sB1 + lpw * LS;                    // 3-D only
+    T* sB2 = sS2 + (NDIM == 3 ? lpw * LS : 0);  // 3-D only
+    T* pcr = sB2 + (NDIM == 3 ? lpw * LS : 0);  // 3 * nthreads elements
     T* pA = pcr;
-    T* pB = pA + nthreads;
-    T* pC = pB + nthreads;
+    T* pC = pA + nthreads;
     T* pD = pC + nthreads;
 
     // XCD-aware block order: consecutive logical blocks on the same XCD so
-    // that the halo lines and the partial lines of a transposed store are
-    // shared through that XCD's L2.
+    // that halo lines and the partial lines of a transposed store are shared
+    // through that XCD's L2.
     int blk = blockIdx.x;
     const int nblk = gridDim.x;
     if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
@@ -64,85 +64,104 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
     const int l1_0 = (blk - l2 * nb1) * lpw;
     const bool periodic = P.periodic != 0;
     const int lim = P.limiter;
-    const bool solve_only = P.rhs_mode != 0;
 
-    // ---------------- phase 1: coalesced load of U, slopes, b, chi -> LDS
-    const bool line_fast_in = (P.si_n == 1);
-    const int ncell = lpw * n;
-    for (int idx = tid; idx < ncell; idx += nthreads) {
-        int q, p;
-        if (line_fast_in) { q = idx / n; p = idx - q * n; }
-        else { p = idx / lpw; q = idx - p * lpw; }
-        const int l1 = l1_0 + q;
-        if (l1 >= P.nt1) continue;
-        const int64_t c = (int64_t)p * P.si_n + (int64_t)l1 * P.si_t1 + (int64_t)l2 * P.si_t2;
-        const T u = P.U[c];
-        const int li = q * LS + lds_pad<T>(p);
-        sU[li] = u;
-        if (!solve_only) {
-            const int64_t cm = c + (nb_coord(l1 - 1, P.nt1, periodic) - l1) * P.si_t1;
-            const int64_t cp = c + (nb_coord(l1 + 1, P.nt1, periodic) - l1) * P.si_t1;
-            sS1[li] = cell_slope<T>(lim, P.U[cm], u, P.U[cp]);
-            if (NDIM == 3) {
-                const int64_t dm = c + (nb_coord(l2 - 1, P.nt2, periodic) - l2) * P.si_t2;
-                const int64_t dp = c + (nb_coord(l2 + 1, P.nt2, periodic) - l2) * P.si_t2;
-                sS2[li] = cell_slope<T>(lim, P.U[dm], u, P.U[dp]);
-                sB2[li] = P.bt2[c];
-            }
-            sB1[li] = P.bt1[c];
+    // Threads [q*spl, (q+1)*spl) own line q of the tile (spl = 64*wpl lanes;
+    // powers of two, so line membership is a shift).
+    const int spl_log2 = P.spl_log2;
+    const int q = tid >> spl_log2;
+    const int k = tid & (seg_per_line - 1);
+    const int l1 = l1_0 + q;
+    const bool line_ok = l1 < P.nt1;
+    // element offsets of this line and of its transverse neighbours (the
+    // boundary rule applies once per line, not per cell)
+    const unsigned base = line_ok ? (unsigned)(l1 * P.si_t1 + l2 * P.si_t2) : 0u;
+    unsigned base1m = base, base1p = base, base2m = base, base2p = base;
+    if (line_ok && !solve_only) {
+        base1m = base + (int)(nb_coord(l1 - 1, P.nt1, periodic) - l1) * P.si_t1;
+        base1p = base + (int)(nb_coord(l1 + 1, P.nt1, periodic) - l1) * P.si_t1;
+        if (NDIM == 3) {
+            base2m = base + (int)(nb_coord(l2 - 1, P.nt2, periodic) - l2) * P.si_t2;
+            base2p = base + (int)(nb_coord(l2 + 1, P.nt2, periodic) - l2) * P.si_t2;
         }
-        sBn[li] = P.bn[c];
-        if (P.chi) sChi[li] = P.chi[c];
+    }
+
+    // ---------------- phase 1: coalesced loads -> LDS (U, alpha, slopes, beta)
+    // Lane k of the line loads cells k, k+spl, ... (at most MMAX of them: the
+    // host guarantees n <= MMAX*spl).  All loads of a chunk of up to 8 cells
+    // are issued before any is used; cells past the line end are clamped to
+    // the line's first cell.
+    constexpr int CH = MMAX < 8 ? MMAX : 8;
+    const T* rowU = sU + q * LS;
+#pragma unroll
+    for (int it0 = 0; it0 < MMAX; it0 += CH) {
+        if (it0 << spl_log2 >= n) break;
+        T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int p = k + ((it0 + j) << spl_log2);
+            const unsigned pc = p < n ? (unsigned)p : 0u;
+            u[j] = P.U[base + pc];
+            va[j] = P.alpha[base + pc];
+            if (!solve_only) {
+                u1m[j] = P.U[base1m + pc];
+                u1p[j] = P.U[base1p + pc];
+                vb1[j] = P.beta1[base + pc];
+                if (NDIM == 3) {
+                    u2m[j] = P.U[base2m + pc];
+                    u2p[j] = P.U[base2p + pc];
+                    vb2[j] = P.beta2[base + pc];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int p = k + ((it0 + j) << spl_log2);
+            if (!line_ok || p >= n) continue;
+            const int li = q * LS + lds_pad<T>(p);
+            sU[li] = u[j];
+            sA[li] = va[j];
+            if (!solve_only) {
+                sS1[li] = cell_slope<T>(lim, u1m[j], u[j], u1p[j]);
+                sB1[li] = vb1[j];
+                if (NDIM == 3) {
+                    sS2[li] = cell_slope<T>(lim, u2m[j], u[j], u2p[j]);
+                    sB2[li] = vb2[j];
+                }
+            }
+        }
     }
     __syncthreads();
 
     // ---------------- phase 2: per-lane segment elimination
-    const int q = tid / seg_per_line;
-    const int k = tid - q * seg_per_line;
-    const int nseg = P.P;
-    const bool line_ok = (l1_0 + q) < P.nt1;
+    const int nseg = 1 << P.nseg_log2;
     const bool active = line_ok && k < nseg;
-    const int s0 = active ? (int)(((int64_t)k * n) / nseg) : 0;
-    const int m = active ? (int)(((int64_t)(k + 1) * n) / nseg) - s0 : 1;
-    const T chi_perp = P.chi_perp;
+    const int s0 = active ? (k * n) >> P.nseg_log2 : 0;
+    const int m = active ? (((k + 1) * n) >> P.nseg_log2) - s0 : 1;
 
     T av[MMAX], bv[MMAX], cv[MMAX], rv[MMAX];
     T gv[MMAX], hv[MMAX], wv[MMAX];
     T ae = T(0), be = T(1), ce = T(0), re = T(0);  // row of the segment's last cell
     {
-        // faces f = 0..m: face between cells j = s0-1+f and j+1
+        // faces f = 0..m: the face between cells j0 = s0-1+f and j0+1 (mod n)
         T alpha_prev = T(0), flux_prev = T(0);
-        const T* rowU = sU + q * LS;
+        const T* rowA = sA + q * LS;
         const T* rowS1 = sS1 + q * LS;
         const T* rowS2 = sS2 + q * LS;
-        const T* rowBn = sBn + q * LS;
         const T* rowB1 = sB1 + q * LS;
         const T* rowB2 = sB2 + q * LS;
-        const T* rowChi = sChi + q * LS;
 #pragma unroll
         for (int f = 0; f <= MMAX; ++f) {
             if (f <= m && active) {
-                int j0 = s0 - 1 + f, j1 = s0 + f;
-                T alpha = T(0), flux = T(0);
-                bool wall = false;
-                if (j0 < 0) { if (periodic) j0 += n; else wall = true; }
-                if (j1 >= n) { if (periodic) j1 -= n; else wall = true; }
-                if (!wall) {
-                    const int i0 = lds_pad<T>(j0), i1 = lds_pad<T>(j1);
-                    const T bnf = T(0.5) * (rowBn[i0] + rowBn[i1]);
-                    T chif = P.chi_par;
-                    if (P.chi) chif = harmonic<T>(rowChi[i0], rowChi[i1]);
-                    const T dpar = chif - chi_perp;
-                    alpha = P.cnn * (chi_perp + dpar * bnf * bnf);
-                    if (!solve_only) {
-                        const T b1f = T(0.5) * (rowB1[i0] + rowB1[i1]);
-                        T tr = P.cnt1 * b1f * limit2<T>(lim, rowS1[i1], rowS1[i0]);
-                        if (NDIM == 3) {
-                            const T b2f = T(0.5) * (rowB2[i0] + rowB2[i1]);
-                            tr += P.cnt2 * b2f * limit2<T>(lim, rowS2[i1], rowS2[i0]);
-                        }
-                        flux = dpar * bnf * tr;
-                    }
+                int j0 = s0 - 1 + f;
+                if (j0 < 0) j0 += n;
+                int j1 = j0 + 1;
+                if (j1 == n) j1 = 0;
+                const int i0 = lds_pad<T>(j0), i1 = lds_pad<T>(j1);
+                const T alpha = rowA[i0];
+                T flux = T(0);
+                if (!solve_only) {
+                    flux = rowB1[i0] * limit2<T>(lim, rowS1[i1], rowS1[i0]);
+                    if (NDIM == 3) flux += rowB2[i0] * limit2<T>(lim, rowS2[i1], rowS2[i0]);
                 }
                 if (f > 0) {
                     const int i = f - 1;  // cell s0 + i, faces (f-1, f)
@@ -162,7 +181,7 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
 #pragma unroll
     for (int i = 0; i < MMAX - 1; ++i) {
         if (i < m - 1) {
-            const T inv = T(1) / (bv[i] - av[i] * hp);
+            const T inv = fast_rcp<T>(bv[i] - av[i] * hp);
             gv[i] = (rv[i] - av[i] * gp) * inv;
             hv[i] = cv[i] * inv;
             wv[i] = -av[i] * wp * inv;
@@ -186,63 +205,90 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
             }
         }
     }
-    // exchange (Y, Uc, V) with the segment to the right
-    pA[tid] = Y;
-    pB[tid] = Uc;
-    pC[tid] = V;
-    __syncthreads();
-    T Ra = T(0), Rb = T(0), Rc = T(0), Rd = T(1);
-    {
-        const int base = q * seg_per_line;
-        const int kr = (k + 1 == nseg) ? 0 : k + 1;
-        const T Yp = pA[base + kr], Up = pB[base + kr], Vp = pC[base + kr];
+
+    // Reduced row of this segment's interface unknown X_k (its last cell),
+    // kept normalised:  Ra X_{k-1} + X_k + Rc X_{k+1} = Rd.  It needs the
+    // right neighbour's first-cell expression (Y, Uc, V).
+    T Ra, Rc, Rd, XR, XL;
+    const int kr = (k + 1) & (nseg - 1);
+    if (P.wpl == 1) {
+        // one wave per line: lane == segment; shuffles, no barrier
+        const T Yp = __shfl(Y, kr, 64), Up = __shfl(Uc, kr, 64), Vp = __shfl(V, kr, 64);
         if (active) {
-            Ra = ae * wp;
-            Rb = be - ae * hp + ce * Up;
-            Rc = ce * Vp;
-            Rd = re - ae * gp - ce * Yp;
+            const T ib = fast_rcp<T>(be - ae * hp + ce * Up);
+            Ra = ae * wp * ib;
+            Rc = ce * Vp * ib;
+            Rd = (re - ae * gp - ce * Yp) * ib;
         } else {
-            Ra = T(0); Rb = T(1); Rc = T(0); Rd = T(0);
+            Ra = T(0); Rc = T(0); Rd = T(0);
         }
-    }
-    __syncthreads();
-    // ---------------- cyclic reduction over the nseg interface unknowns
-    {
-        const int base = q * seg_per_line;
-        pA[tid] = Ra; pB[tid] = Rb; pC[tid] = Rc; pD[tid] = Rd;
+        for (int s = 1; s < nseg; s <<= 1) {
+            const int km = (k - s) & (nseg - 1), kp = (k + s) & (nseg - 1);
+            const T am = __shfl(Ra, km, 64), cm = __shfl(Rc, km, 64), dm = __shfl(Rd, km, 64);
+            const T ap = __shfl(Ra, kp, 64), cp = __shfl(Rc, kp, 64), dp = __shfl(Rd, kp, 64);
+            if (k < nseg) {
+                const T ib = fast_rcp<T>(T(1) - Ra * cm - Rc * ap);
+                const T na = -Ra * am, nc = -Rc * cp, nd = Rd - Ra * dm - Rc * dp;
+                Ra = na * ib;
+                Rc = nc * ib;
+                Rd = nd * ib;
+            }
+        }
+        XR = Rd * fast_rcp<T>(T(1) + Ra + Rc);
+        XL = __shfl(XR, (k - 1) & (nseg - 1), 64);
+    } else {
+        // several waves per line: the same reduction through LDS
+        const int lb = q * seg_per_line;  // this line's slots
+        pA[tid] = Y;
+        pC[tid] = Uc;
+        pD[tid] = V;
+        __syncthreads();
+        {
+            const T Yp = pA[lb + kr], Up = pC[lb + kr], Vp = pD[lb + kr];
+            if (active) {
+                const T ib = fast_rcp<T>(be - ae * hp + ce * Up);
+                Ra = ae * wp * ib;
+                Rc = ce * Vp * ib;
+                Rd = (re - ae * gp - ce * Yp) * ib;
+            } else {
+                Ra = T(0); Rc = T(0); Rd = T(0);
+            }
+        }
+        __syncthreads();
+        pA[tid] = Ra; pC[tid] = Rc; pD[tid] = Rd;
         __syncthreads();
         for (int s = 1; s < nseg; s <<= 1) {
-            T na = Ra, nb = Rb, nc = Rc, nd = Rd;
+            T na = Ra, nc = Rc, nd = Rd;
             if (k < nseg) {
-                const int km = base + ((k - s) & (nseg - 1));
-                const int kp = base + ((k + s) & (nseg - 1));
-                const T am = pA[km], bm = pB[km], cm = pC[km], dm = pD[km];
-                const T ap = pA[kp], bp = pB[kp], cp = pC[kp], dp = pD[kp];
-                const T k1 = Ra / bm, k2 = Rc / bp;
-                na = -k1 * am;
-                nc = -k2 * cp;
-                nb = Rb - k1 * cm - k2 * ap;
-                nd = Rd - k1 * dm - k2 * dp;
+                const int km = lb + ((k - s) & (nseg - 1));
+                const int kp = lb + ((k + s) & (nseg - 1));
+                const T am = pA[km], cm = pC[km], dm = pD[km];
+                const T ap = pA[kp], cp = pC[kp], dp = pD[kp];
+                const T ib = fast_rcp<T>(T(1) - Ra * cm - Rc * ap);
+                na = -Ra * am * ib;
+                nc = -Rc * cp * ib;
+                nd = (Rd - Ra * dm - Rc * dp) * ib;
             }
             __syncthreads();
-            Ra = na; Rb = nb; Rc = nc; Rd = nd;
-            pA[tid] = Ra; pB[tid] = Rb; pC[tid] = Rc; pD[tid] = Rd;
+            Ra = na; Rc = nc; Rd = nd;
+            pA[tid] = Ra; pC[tid] = Rc; pD[tid] = Rd;
             __syncthreads();
         }
+        XR = Rd * fast_rcp<T>(T(1) + Ra + Rc);
+        pA[tid] = XR;
+        __syncthreads();
+        XL = pA[lb + ((k - 1) & (nseg - 1))];
     }
-    const T XR = Rd / (Ra + Rb + Rc);
-    pA[tid] = XR;
-    __syncthreads();
-    const T XL = pA[q * seg_per_line + ((k - 1) & (nseg - 1))];
 
     // ---------------- back substitution, result into LDS (reuse sU)
-    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
+    double lsum = 0.0;
+    T lmin = T(__builtin_huge_val()), lmax = T(-__builtin_huge_val());
     if (active) {
         T* rowX = sU + q * LS;
         T xn = XR;
         rowX[lds_pad<T>(s0 + m - 1)] = XR;
         lsum = (double)XR;
-        lmin = lmax = (double)XR;
+        lmin = lmax = XR;
 #pragma unroll
         for (int i = MMAX - 2; i >= 0; --i) {
             if (i <= m - 2) {
@@ -250,34 +296,49 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
                 rowX[lds_pad<T>(s0 + i)] = x;
                 xn = x;
                 lsum += (double)x;
-                lmin = fmin(lmin, (double)x);
-                lmax = fmax(lmax, (double)x);
+                lmin = x < lmin ? x : lmin;
+                lmax = x > lmax ? x : lmax;
             }
         }
     }
     __syncthreads();
 
-    // ---------------- phase 3: store the tile (transposed when out is t1-fastest)
-    const bool line_fast_out = (P.so_t1 != 1);
-    for (int idx = tid; idx < ncell; idx += nthreads) {
-        int qq, p;
-        if (line_fast_out) { qq = idx / n; p = idx - qq * n; }
-        else { p = idx / lpw; qq = idx - p * lpw; }
-        const int l1 = l1_0 + qq;
-        if (l1 >= P.nt1) continue;
-        const int64_t c = (int64_t)p * P.so_n + (int64_t)l1 * P.so_t1 + (int64_t)l2 * P.so_t2;
-        P.out[c] = sU[qq * LS + lds_pad<T>(p)];
+    // ---------------- phase 3: store the tile
+    if (P.so_t1 == 1) {
+        // transposed output (t1 fastest): consecutive threads take the lpw
+        // lines of one position p, so each store covers lpw adjacent elements
+        const int lpw_log2 = P.lpw_log2;
+        const int ncell = lpw * n;
+#pragma unroll
+        for (int it = 0; it < MMAX; ++it) {
+            const int idx = tid + it * nthreads;
+            if (idx >= ncell) break;
+            const int qq = idx & (lpw - 1), p = idx >> lpw_log2;
+            if (l1_0 + qq >= P.nt1) continue;
+            P.out[(unsigned)(p * P.so_n + (l1_0 + qq) + l2 * P.so_t2)] = sU[qq * LS + lds_pad<T>(p)];
+        }
+    } else {
+        // line-contiguous output
+        const unsigned obase = line_ok ? (unsigned)(l1 * P.so_t1 + l2 * P.so_t2) : 0u;
+#pragma unroll
+        for (int it = 0; it < MMAX; ++it) {
+            const int p = k + (it << spl_log2);
+            if (p >= n) break;
+            if (line_ok) P.out[obase + (unsigned)(p * P.so_n)] = rowU[lds_pad<T>(p)];
+        }
     }
 
-    // ---------------- fused FP64 energy / min / max (deterministic)
-    if (P.red.partials) block_reduce_and_finish(P.red, lsum, lmin, lmax);
+    // ---------------- FP64 energy / min / max partials, and the fold of the
+    // previous launch's partials (block 0 only)
+    if (P.red.partials) block_partials(P.red.partials, lsum, (double)lmin, (double)lmax);
+    if (P.fold.partials && blockIdx.x == 0) fold_partials(P.fold);
 }
 
 template <typename T, int NDIM>
 static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid, dim3 block, size_t lds,
                                    hipStream_t st) {
-#define ASD_SWEEP_CASE(MM)                                           \
-    case MM:                                                         \
+#define ASD_SWEEP_CASE(MM)                                                        \
+    case MM:                                                                      \
         hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM>), grid, block, lds, st, P); \
         return hipGetLastError();
     switch (mmax) {
@@ -314,14 +375,13 @@ hipError_t sweep_set_lds_limits(int bytes) {
 }
 
 template <typename T>
-hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block,
-                        size_t lds, hipStream_t st) {
+hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block, size_t lds,
+                        hipStream_t st) {
     if (ndim == 2) return launch_sweep_dim<T, 2>(P, mmax, grid, block, lds, st);
     return launch_sweep_dim<T, 3>(P, mmax, grid, block, lds, st);
 }
 
-template hipError_t launch_sweep<float>(const SweepParams<float>&, int, int, dim3, dim3, size_t,
-                                        hipStream_t);
+template hipError_t launch_sweep<float>(const SweepParams<float>&, int, int, dim3, dim3, size_t, hipStream_t);
 template hipError_t launch_sweep<double>(const SweepParams<double>&, int, int, dim3, dim3, size_t,
                                          hipStream_t);
 

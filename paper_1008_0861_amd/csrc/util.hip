@@ -53,6 +53,7 @@ hipError_t launch_permute(const T* in, T* out, const int n[3], const int64_t ds[
 
 template <typename T>
 __global__ void __launch_bounds__(256) reduce_kernel(const T* __restrict__ x, int64_t N, ReduceParams R) {
+    // partials only; a later launch folds them
     double s = 0.0, mn = __builtin_huge_val(), mx = -__builtin_huge_val();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -61,7 +62,14 @@ __global__ void __launch_bounds__(256) reduce_kernel(const T* __restrict__ x, in
         mn = fmin(mn, v);
         mx = fmax(mx, v);
     }
-    block_reduce_and_finish(R, s, mn, mx);
+    block_partials(R.partials, s, mn, mx);
+}
+
+__global__ void __launch_bounds__(256) fold_kernel(FoldParams f) { fold_partials(f); }
+
+hipError_t launch_fold(const FoldParams& f, hipStream_t st) {
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(256), 0, st, f);
+    return hipGetLastError();
 }
 
 int reduce_num_blocks(int64_t N) {
