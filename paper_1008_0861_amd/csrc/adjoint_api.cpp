@@ -1,10 +1,207 @@
-// placeholder, replaced by the adjoint implementation
+// asd_adjoint_step: reverse-mode derivative of nsteps 2-D semi-implicit
+// steps with respect to the initial state and a per-cell chi.
+//
+// Forward states are checkpointed every ckpt_every steps; the reverse pass
+// walks the segments backwards, recomputing each segment's states (T^n and
+// T*) from its checkpoint, then runs per step, last step first:
+//     mu_y = A_y^-1 lambda                       (line solves, y)
+//     lambda* = mu_y + J_Sy(T*)^T mu_y; chi grads from the y faces
+//     mu_x = A_x^-1 lambda*                      (line solves, x)
+//     lambda  = mu_x + J_Sx(T^n)^T mu_x; chi grads from the x faces
+// The line solves reuse the forward sweep kernel in solve-only mode (A_d is
+// symmetric).  All buffers live in the caller's adjoint workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
 #include "asd_internal.h"
-extern "C" int asd_adjoint_workspace_bytes(asd_grid g, int32_t, int32_t, size_t*) {
-    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
-    return asd_fail(ASD_EUNSUPPORTED, "adjoint not built yet");
+
+using namespace asd;
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct AdjPlan {
+    int nck;         // checkpoints (states at steps 0, k, 2k, ...)
+    int k;
+    size_t field;    // bytes per state
+    size_t total;
+};
+
+static AdjPlan adj_plan(asd_grid g, int nsteps, int k) {
+    AdjPlan p{};
+    p.k = k;
+    p.nck = nsteps > 0 ? (nsteps + k - 1) / k : 1;
+    p.field = align256((size_t)g->N * g->es);
+    // checkpoints + (k+1) recomputed states + k T* + transposed scratch +
+    // lambda + mu + three face scratch arrays
+    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k + 1) + 1 + 2 + 3);
+    return p;
 }
-extern "C" int asd_adjoint_step(asd_grid g, double, int32_t, int32_t, const void*, const void*, void*, void*, void*, size_t) {
+
+static int adj_check(asd_grid g, int nsteps, int k) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
-    return asd_fail(ASD_EUNSUPPORTED, "adjoint not built yet");
+    if (g->d.ndim != 2) return asd_fail(ASD_EUNSUPPORTED, "the adjoint is built for 2-D grids");
+    if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
+    if (k < 1) return asd_fail(ASD_EINVAL, "ckpt_every must be >= 1");
+    return ASD_OK;
+}
+
+extern "C" int asd_adjoint_workspace_bytes(asd_grid g, int32_t nsteps, int32_t ckpt_every, size_t* bytes) {
+    int rc = adj_check(g, nsteps, ckpt_every);
+    if (rc) return rc;
+    if (!bytes) return asd_fail(ASD_EINVAL, "bytes is NULL");
+    *bytes = adj_plan(g, nsteps, ckpt_every).total;
+    return ASD_OK;
+}
+
+template <typename T>
+static int permute_2d(asd_grid g, const void* in, void* out, bool a_to_b) {
+    const int nx = (int)g->d.n[0], ny = (int)g->d.n[1];
+    hipError_t e;
+    if (a_to_b) {
+        const int n[3] = {nx, ny, 1};
+        const int64_t ds[3] = {ny, 1, (int64_t)nx * ny};
+        e = launch_permute<T>((const T*)in, (T*)out, n, ds, g->st);
+    } else {
+        // a B array is a dense (nx, ny) array with y fastest
+        const int n[3] = {ny, nx, 1};
+        const int64_t ds[3] = {nx, 1, (int64_t)nx * ny};
+        e = launch_permute<T>((const T*)in, (T*)out, n, ds, g->st);
+    }
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "permute: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
+template <typename T>
+static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, const void* X, void* lam_out,
+                   void* gchi, void* W1, void* W2, void* GF) {
+    AdjParams<T> P{};
+    P.mu = (const T*)mu;
+    P.U = (const T*)U;
+    P.X = (const T*)X;
+    P.b[0] = (const T*)g->b[0];
+    P.b[1] = (const T*)g->b[1];
+    P.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)g->chi : nullptr;
+    P.W1 = (T*)W1;
+    P.W2 = (T*)W2;
+    P.GF = (T*)GF;
+    P.lam_out = (T*)lam_out;
+    P.gchi = (T*)gchi;
+    P.nx = (int)g->d.n[0];
+    P.ny = (int)g->d.n[1];
+    P.d = d;
+    P.dt = dt;
+    P.hn = g->d.h[d];
+    P.ht = g->d.h[1 - d];
+    P.chi_par = g->d.chi_par;
+    P.chi_perp = g->d.chi_perp;
+    P.periodic = g->d.bc == ASD_BC_PERIODIC;
+    P.limiter = g->d.limiter;
+    hipError_t e = launch_adjoint_stencil<T>(P, g->st);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "adjoint stencil: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
+template <typename T>
+static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, const void* lamN, void* gT0,
+                     void* gchi, char* ws) {
+    const AdjPlan pl = adj_plan(g, nsteps, k);
+    char* cur = ws;
+    auto take = [&]() {
+        char* p = cur;
+        cur += pl.field;
+        return (void*)p;
+    };
+    void* ck[4096];
+    if (pl.nck > 4096) return asd_fail(ASD_EUNSUPPORTED, "too many checkpoints (nsteps/ckpt_every > 4096)");
+    for (int c = 0; c < pl.nck; ++c) ck[c] = take();
+    void* S[1025];
+    void* TS[1024];
+    if (k > 1024) return asd_fail(ASD_EUNSUPPORTED, "ckpt_every must be <= 1024");
+    S[0] = nullptr;
+    for (int i = 1; i <= k; ++i) S[i] = take();
+    for (int i = 0; i < k; ++i) TS[i] = take();
+    void* tB = take();
+    void* lam = take();
+    void* mu = take();
+    void* W1 = take();
+    void* W2 = take();
+    void* GF = take();
+    int rc;
+    // forward pass: checkpoints at steps 0, k, 2k, ...
+    rc = enqueue_copy(g, T0, ck[0]);
+    if (rc) return rc;
+    for (int c = 1; c < pl.nck; ++c) {
+        const void* in = ck[c - 1];
+        for (int i = 0; i < k; ++i) {
+            void* out = (i == k - 1) ? ck[c] : S[1];
+            rc = enqueue_sweep(g, 0, dt, in, tB, 0, no_reduce(), no_fold(), nullptr, nullptr);
+            if (rc) return rc;
+            rc = enqueue_sweep(g, 1, dt, tB, out, 0, no_reduce(), no_fold(), nullptr, nullptr);
+            if (rc) return rc;
+            in = out;
+        }
+    }
+    // reverse pass
+    rc = enqueue_copy(g, lamN, lam);
+    if (rc) return rc;
+    if (gchi) {
+        // a fill kernel, not a memset: callers may capture this into a graph
+        hipError_t e = g->es == 8 ? launch_fill_f64((double*)gchi, 0.0, g->N, g->st)
+                                  : launch_fill_u32((unsigned*)gchi, 0u, g->N, g->st);
+        if (e != hipSuccess) return asd_fail(ASD_EHIP, "clear grad_chi: %s", hipGetErrorString(e));
+    }
+    for (int c = pl.nck - 1; c >= 0; --c) {
+        const int len = std::min(k, nsteps - c * k);
+        S[0] = ck[c];
+        for (int i = 0; i < len; ++i) {
+            rc = enqueue_sweep(g, 0, dt, S[i], tB, 0, no_reduce(), no_fold(), nullptr, nullptr);
+            if (rc) return rc;
+            rc = permute_2d<T>(g, tB, TS[i], false);
+            if (rc) return rc;
+            rc = enqueue_sweep(g, 1, dt, tB, S[i + 1], 0, no_reduce(), no_fold(), nullptr, nullptr);
+            if (rc) return rc;
+        }
+        for (int i = len - 1; i >= 0; --i) {
+            // y sweep: T* -> T^{n+1}
+            rc = permute_2d<T>(g, lam, tB, true);
+            if (rc) return rc;
+            rc = enqueue_sweep(g, 1, dt, tB, mu, 1, no_reduce(), no_fold(), nullptr, nullptr);
+            if (rc) return rc;
+            rc = stencil<T>(g, 1, dt, mu, TS[i], S[i + 1], lam, gchi, W1, W2, GF);
+            if (rc) return rc;
+            // x sweep: T^n -> T*
+            rc = enqueue_sweep(g, 0, dt, lam, tB, 1, no_reduce(), no_fold(), nullptr, nullptr);
+            if (rc) return rc;
+            rc = permute_2d<T>(g, tB, mu, false);
+            if (rc) return rc;
+            rc = stencil<T>(g, 0, dt, mu, S[i], TS[i], lam, gchi, W1, W2, GF);
+            if (rc) return rc;
+        }
+    }
+    return enqueue_copy(g, lam, gT0);
+}
+
+extern "C" int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, const void* dev_T0,
+                                const void* dev_lambda_final, void* dev_grad_T0, void* dev_grad_chi, void* dev_adj_ws,
+                                size_t adj_ws_bytes) {
+    int rc = adj_check(g, nsteps, ckpt_every);
+    if (rc) return rc;
+    if (!(std::isfinite(dt) && dt > 0.0)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
+    if (!dev_T0 || !dev_lambda_final || !dev_grad_T0) return asd_fail(ASD_EINVAL, "NULL state pointer");
+    if (dev_grad_chi && !(g->d.flags & ASD_FLAG_PER_CELL_CHI))
+        return asd_fail(ASD_EINVAL, "grad_chi needs ASD_FLAG_PER_CELL_CHI");
+    if (!dev_adj_ws) return asd_fail(ASD_EWORKSPACE, "adjoint workspace is NULL");
+    if ((uintptr_t)dev_adj_ws & 255) return asd_fail(ASD_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
+    const AdjPlan pl = adj_plan(g, nsteps, ckpt_every);
+    if (adj_ws_bytes < pl.total)
+        return asd_fail(ASD_EWORKSPACE, "adjoint workspace too small: %zu < %zu bytes", adj_ws_bytes, pl.total);
+    rc = check_fields(g, false);
+    if (rc) return rc;
+    rc = prepare(g, dt);
+    if (rc) return rc;
+    return g->es == 8 ? adjoint_t<double>(g, dt, nsteps, ckpt_every, dev_T0, dev_lambda_final, dev_grad_T0,
+                                          dev_grad_chi, (char*)dev_adj_ws)
+                      : adjoint_t<float>(g, dt, nsteps, ckpt_every, dev_T0, dev_lambda_final, dev_grad_T0,
+                                         dev_grad_chi, (char*)dev_adj_ws);
 }

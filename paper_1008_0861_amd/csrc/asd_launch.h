@@ -100,6 +100,27 @@ template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out);
 int explicit_num_blocks(int ndim, const int n[3]);
 
+// ----------------------------------------------------------------- adjoint
+// Reverse mode of one 2-D sweep along d (adjoint.hip); arrays x-fastest.
+template <typename T>
+struct AdjParams {
+    const T* mu;      // A_d^-1 lambda
+    const T* U;       // the sweep's input state
+    const T* X;       // the sweep's output state
+    const T* b[2];
+    const T* chi;     // per-cell chi or nullptr (then chi_par)
+    T* W1;            // face scratch: w dG/d(right slope)
+    T* W2;            // face scratch: w dG/d(left slope)
+    T* GF;            // face scratch: dL/dchi_f
+    T* lam_out;       // mu + J_S^T mu
+    T* gchi;          // nullable: += dL/dchi per cell
+    int nx, ny, d;
+    double dt, hn, ht, chi_par, chi_perp;
+    int periodic, limiter;
+};
+template <typename T>
+hipError_t launch_adjoint_stencil(const AdjParams<T>& P, hipStream_t st);
+
 // --------------------------------------------------------------- utilities
 // out[perm] = in: copy a dense (nz, ny, nx) array into another axis order.
 // dst_stride[d] is the destination stride of source axis d (x=0, y=1, z=2).

@@ -103,11 +103,14 @@ def batch_problems(nprob=256, master_seed=40, sides=None, ncfl=20.0, nsteps=100)
 def adjoint_problem(n=1024, nsteps=50, ncfl=20.0, seed_b=50, seed_chi=51, seed_pert=52):
     """Periodic unit square with per-cell chi = exp(0.5 g) (g smoothed, unit
     variance), b from a random A_z; meta["chi_target"] = chi * exp(0.1 g')
-    is the perturbed diffusivity that defines the target temperature."""
+    is the perturbed diffusivity that defines the target temperature.
+    T0 = exp(0.3 g'') with g'' smoothed over 4 cells: smooth everywhere, so
+    the limiters are differentiable at almost every face (a two-level or
+    flat field puts many faces on the a*b = 0 kink)."""
     bx, by = fields.grf_unit_field_2d(n, n, seed_b)
     chi = fields.chi_field_2d(n, n, seed_chi, amp=0.5)
     chi_t = chi * np.exp(0.1 * fields.smoothed_normal((n, n), seed_pert))
-    T0 = fields.blobs_2d(n, n, seed_b + 1000)
+    T0 = np.exp(0.3 * fields.smoothed_normal((n, n), seed_b + 1000))
     h = (1.0 / n, 1.0 / n)
     dt = ncfl_dt(ncfl, h, max(chi.max(), chi_t.max()))
     return Problem("adjoint", (bx, by), T0, h, bc="periodic", chi_par=1.0, chi=chi, dt=dt,
