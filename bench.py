@@ -116,7 +116,7 @@ def kernel_source_digest():
     """Digest of the sources that define the timed sweep kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep.hip", "asd_device.h", "asd_launch.h"):
+    for f in ("sweep.hip", "sweep_tile.h", "asd_device.h", "asd_launch.h"):
         h.update(open(os.path.join(ROOT, "paper_1008_0861_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -31,11 +31,23 @@ int asd_batch_init(const asd_desc *descs, int32_t nprob, void *dev_ws, size_t ws
  * the next step call) and set its time step dt (> 0, finite). */
 int asd_batch_set_problem(asd_batch b, int32_t p, void *dev_T, void *dev_bx, void *dev_by, double dt);
 
-/* nsteps steps of every problem.  mode 0: one persistent launch for all
- * problems and all steps (work-groups own whole problems, assigned largest
- * first); mode 1: one launch per problem per sweep (the sequential
- * reference). */
+/* nsteps steps of every problem.  Problems must be 2-D with a constant
+ * chi_par; every problem gets its own dt.
+ *   mode 0: one persistent launch for all problems and all steps
+ *           (work-groups own whole problems, assigned largest first);
+ *   mode 1: one launch per problem per sweep (the sequential reference);
+ *   mode 2: one launch per sweep for all problems (grouped line tiles);
+ *   mode -1: the schedule chosen by asd_batch_tune (0 before tuning). */
 int asd_batch_step(asd_batch b, int32_t nsteps, int32_t mode);
+
+/* Work-group size of the batch kernels: 256, 512 or 1024 threads
+ * (EUNSUPPORTED if some problem's lines do not fit). */
+int asd_batch_set_block(asd_batch b, int32_t nthreads);
+
+/* Autotuner: time modes 0 and 2 at every admissible work-group size on
+ * probe_steps steps (this advances the problems' T), keep the fastest for
+ * mode -1 and report it (nullable outputs).  Synchronises the stream. */
+int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t *best_mode, int32_t *best_threads);
 
 int asd_batch_destroy(asd_batch b);
 

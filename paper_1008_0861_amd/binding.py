@@ -33,7 +33,7 @@ EXPORTED = [
     "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_adjoint_workspace_bytes",
     "asd_adjoint_step", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
-    "asd_batch_destroy",
+    "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune",
     "asd_get_sweep_config", "asd_set_sweep_config", "asd_tune", "asd_set_graphs",
     "asd_bench_sweep", "asd_bench_copy",
 ]
@@ -89,6 +89,8 @@ def lib():
             "asd_batch_set_problem": (ctypes.c_int, [vp, i32, vp, vp, vp, dbl]),
             "asd_batch_step": (ctypes.c_int, [vp, i32, i32]),
             "asd_batch_destroy": (ctypes.c_int, [vp]),
+            "asd_batch_set_block": (ctypes.c_int, [vp, i32]),
+            "asd_batch_tune": (ctypes.c_int, [vp, i32, P(i32), P(i32)]),
             "asd_get_sweep_config": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
             "asd_set_sweep_config": (ctypes.c_int, [vp, i32, i32, i32]),
             "asd_tune": (ctypes.c_int, [vp, dbl, i32]),
@@ -272,6 +274,59 @@ class Grid:
     def close(self):
         if getattr(self, "handle", None):
             lib().asd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent 2-D problems advanced together (asd_batch_*).
+
+    problems: sequence of dicts with keys shape (ny, nx), h, chi_par, dt and
+    tensors T, bx, by (contiguous CUDA, the batch dtype).  T is advanced in
+    place.  bc, dtype and limiter are shared."""
+
+    def __init__(self, problems, bc="periodic", dtype=torch.float32, limiter="vanleer", stream=None):
+        self.descs = (Desc * len(problems))()
+        for i, pr in enumerate(problems):
+            self.descs[i] = make_desc(pr["shape"], pr["h"], bc, dtype, limiter, pr.get("chi_par", 1.0),
+                                      pr.get("chi_perp", 0.0))
+        n = ctypes.c_size_t()
+        check(lib().asd_batch_workspace_bytes(self.descs, len(problems), ctypes.byref(n)))
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        self._stream_ptr, self.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        check(lib().asd_batch_init(self.descs, len(problems), ctypes.c_void_p(self.workspace.data_ptr()), n.value,
+                                   self._stream_ptr, ctypes.byref(h)))
+        self.handle = h
+        self.problems = list(problems)
+        for i, pr in enumerate(problems):
+            for name in ("T", "bx", "by"):
+                t = pr[name]
+                if t.dtype != dtype or tuple(t.shape) != tuple(pr["shape"]) or not t.is_contiguous():
+                    raise ValueError(f"problem {i}: {name} must be contiguous {dtype} of shape {pr['shape']}")
+            check(lib().asd_batch_set_problem(h, i, ctypes.c_void_p(pr["T"].data_ptr()),
+                                              ctypes.c_void_p(pr["bx"].data_ptr()),
+                                              ctypes.c_void_p(pr["by"].data_ptr()), float(pr["dt"])))
+
+    def step(self, nsteps, mode=-1):
+        check(lib().asd_batch_step(self.handle, int(nsteps), int(mode)))
+
+    def set_block(self, nthreads):
+        check(lib().asd_batch_set_block(self.handle, int(nthreads)))
+
+    def tune(self, probe_steps=2):
+        m, t = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().asd_batch_tune(self.handle, int(probe_steps), ctypes.byref(m), ctypes.byref(t)))
+        return m.value, t.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().asd_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

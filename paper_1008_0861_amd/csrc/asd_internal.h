@@ -120,6 +120,10 @@ struct asd_grid_s {
 
 // capi.cpp
 int asd_fail(int code, const char* fmt, ...);
+int validate_desc(const asd_desc* d);
+template <typename T>
+int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode, const SweepCfg& c,
+                      asd::SweepParams<T>* P);
 int check_fields(asd_grid g, bool need_T);
 int prepare(asd_grid g, double dt);  // dt > 0: face coefficients for dt
 int64_t layout_stride(const asd_grid g, int L, int a);

@@ -100,6 +100,22 @@ template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out);
 int explicit_num_blocks(int ndim, const int n[3]);
 
+// ------------------------------------------------------------------- batch
+// One problem of a batch: its x sweep (T -> T*, transposed) and y sweep
+// (T* -> T), and the number of line groups of each (batch.hip).
+template <typename T>
+struct BatchProblem {
+    SweepParams<T> sweep[2];
+    int ngroups[2];
+};
+template <typename T>
+hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
+                                   int mmax, int nthreads, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
+                                int mmax, int nthreads, size_t lds, hipStream_t st);
+hipError_t batch_set_lds_limits(int bytes);
+
 // ----------------------------------------------------------------- adjoint
 // Reverse mode of one 2-D sweep along d (adjoint.hip); arrays x-fastest.
 template <typename T>

@@ -1,8 +1,345 @@
-// placeholder, replaced by the batched implementation
+// Batched independent 2-D problems (asd_batch_*): each problem is a full
+// grid (its own slice of the workspace, face coefficients and T* buffer);
+// the batch adds the launch tables of the persistent and grouped kernels,
+// the largest-first assignment of problems to workgroups, and an autotuner
+// that picks the schedule (persistent / grouped) and workgroup size by
+// timing them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <numeric>
+#include <vector>
+
 #include "../../include/asd_extra.h"
 #include "asd_internal.h"
-extern "C" int asd_batch_workspace_bytes(const asd_desc*, int32_t, size_t*) { return asd_fail(ASD_EUNSUPPORTED, "batch not built yet"); }
-extern "C" int asd_batch_init(const asd_desc*, int32_t, void*, size_t, void*, asd_batch*) { return asd_fail(ASD_EUNSUPPORTED, "batch not built yet"); }
-extern "C" int asd_batch_set_problem(asd_batch, int32_t, void*, void*, void*, double) { return asd_fail(ASD_EUNSUPPORTED, "batch not built yet"); }
-extern "C" int asd_batch_step(asd_batch, int32_t, int32_t) { return asd_fail(ASD_EUNSUPPORTED, "batch not built yet"); }
-extern "C" int asd_batch_destroy(asd_batch) { return asd_fail(ASD_EUNSUPPORTED, "batch not built yet"); }
+
+using namespace asd;
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct asd_batch_s {
+    asd_desc d0{};
+    int nprob = 0;
+    hipStream_t st = nullptr;
+    std::vector<asd_grid> sub;
+    std::vector<double> dt;
+    std::vector<char*> sub_ws;
+    // launch shape shared by every problem in the batch kernels
+    int mmax = 8, nthreads = 512, mode = 0;
+    size_t lds = 0;
+    std::vector<SweepCfg> cfg;  // [2 * p + d]
+    // device tables (workspace) and their host images
+    char* d_probs = nullptr;
+    int* d_off = nullptr;
+    int* d_list = nullptr;
+    int* d_gs[2] = {nullptr, nullptr};
+    int nwg = 0, ngroups[2] = {0, 0};
+    std::vector<char> h_probs;
+    std::vector<int> h_off, h_list, h_gs[2];
+    bool dirty = true;
+};
+
+static const int kMaxWorkgroups = 1024;
+
+static size_t probs_bytes(const asd_desc* d0, int nprob) {
+    const size_t one = d0->dtype == ASD_F64 ? sizeof(BatchProblem<double>) : sizeof(BatchProblem<float>);
+    return align256(one * (size_t)nprob);
+}
+static size_t table_bytes(int nprob) {
+    return align256(sizeof(int) * (size_t)(kMaxWorkgroups + 1)) + align256(sizeof(int) * (size_t)nprob) +
+           2 * align256(sizeof(int) * (size_t)(nprob + 1));
+}
+
+static int check_descs(const asd_desc* descs, int32_t nprob) {
+    if (!descs) return asd_fail(ASD_EINVAL, "descs is NULL");
+    if (nprob < 1) return asd_fail(ASD_EINVAL, "nprob must be >= 1");
+    for (int p = 0; p < nprob; ++p) {
+        int rc = validate_desc(&descs[p]);
+        if (rc) return rc;
+        if (descs[p].ndim != 2) return asd_fail(ASD_EUNSUPPORTED, "batched problems must be 2-D");
+        if (descs[p].bc != descs[0].bc || descs[p].dtype != descs[0].dtype || descs[p].limiter != descs[0].limiter)
+            return asd_fail(ASD_EINVAL, "problem %d: bc, dtype and limiter must match problem 0", p);
+        if (descs[p].flags & ASD_FLAG_PER_CELL_CHI)
+            return asd_fail(ASD_EUNSUPPORTED, "batched problems take a constant chi_par");
+    }
+    return ASD_OK;
+}
+
+extern "C" int asd_batch_workspace_bytes(const asd_desc* descs, int32_t nprob, size_t* bytes) {
+    int rc = check_descs(descs, nprob);
+    if (rc) return rc;
+    if (!bytes) return asd_fail(ASD_EINVAL, "bytes is NULL");
+    size_t tot = probs_bytes(descs, nprob) + table_bytes(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        size_t b = 0;
+        rc = asd_workspace_bytes(&descs[p], &b);
+        if (rc) return rc;
+        tot += align256(b);
+    }
+    *bytes = tot;
+    return ASD_OK;
+}
+
+// Launch shape of problem line length n for a fixed workgroup size.
+static bool batch_line_cfg(int es, int n, int nthreads, int mmax, SweepCfg* out) {
+    for (int wpl = 1; 64 * wpl <= nthreads; wpl *= 2) {
+        const int P = std::min(64 * wpl, pow2_floor(n));
+        if ((n + P - 1) / P > mmax) continue;
+        const int lpw = nthreads / (64 * wpl);
+        if (sweep_lds(es, 2, n, lpw, nthreads) > kLdsLimit) continue;
+        out->wpl = wpl;
+        out->lpw = lpw;
+        out->P = P;
+        out->mmax = mmax;
+        return true;
+    }
+    return false;
+}
+
+// Choose (mmax, nthreads) for all problems; fills b->cfg and b->lds.
+static int batch_shape(asd_batch b, int nthreads) {
+    const int es = b->d0.dtype == ASD_F64 ? 8 : 4;
+    for (int mmax : {4, 8, 16}) {
+        if (nthreads > sweep_threads_cap(es, mmax)) continue;
+        std::vector<SweepCfg> cfg(2 * b->nprob);
+        size_t lds = 0;
+        bool ok = true;
+        for (int p = 0; p < b->nprob && ok; ++p) {
+            for (int d = 0; d < 2 && ok; ++d) {
+                const int n = (int)b->sub[p]->d.n[d];
+                ok = batch_line_cfg(es, n, nthreads, mmax, &cfg[2 * p + d]);
+                if (ok) lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, nthreads));
+            }
+        }
+        if (!ok) continue;
+        b->mmax = mmax;
+        b->nthreads = nthreads;
+        b->cfg = cfg;
+        b->lds = lds;
+        b->dirty = true;
+        return ASD_OK;
+    }
+    return asd_fail(ASD_EUNSUPPORTED, "no batch launch shape with %d threads fits every problem", nthreads);
+}
+
+extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws, size_t ws_bytes, void* stream,
+                              asd_batch* out) {
+    size_t need = 0;
+    int rc = asd_batch_workspace_bytes(descs, nprob, &need);
+    if (rc) return rc;
+    if (!out) return asd_fail(ASD_EINVAL, "out is NULL");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return asd_fail(ASD_EWORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < need) return asd_fail(ASD_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    asd_batch b = new (std::nothrow) asd_batch_s();
+    if (!b) return asd_fail(ASD_EINVAL, "out of host memory");
+    b->d0 = descs[0];
+    b->nprob = nprob;
+    b->st = (hipStream_t)stream;
+    char* cur = (char*)dev_ws;
+    b->d_probs = cur;
+    cur += probs_bytes(descs, nprob);
+    b->d_off = (int*)cur;
+    cur += align256(sizeof(int) * (size_t)(kMaxWorkgroups + 1));
+    b->d_list = (int*)cur;
+    cur += align256(sizeof(int) * (size_t)nprob);
+    for (int d = 0; d < 2; ++d) {
+        b->d_gs[d] = (int*)cur;
+        cur += align256(sizeof(int) * (size_t)(nprob + 1));
+    }
+    b->sub.assign(nprob, nullptr);
+    b->dt.assign(nprob, 0.0);
+    for (int p = 0; p < nprob; ++p) {
+        size_t wb = 0;
+        asd_workspace_bytes(&descs[p], &wb);
+        rc = asd_init_grid(&descs[p], cur, wb, stream, &b->sub[p]);
+        if (rc) {
+            asd_batch_destroy(b);
+            return rc;
+        }
+        b->sub[p]->use_graphs = false;
+        cur += align256(wb);
+    }
+    rc = batch_shape(b, 512);
+    if (rc) rc = batch_shape(b, 256);
+    if (rc) {
+        asd_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return ASD_OK;
+}
+
+extern "C" int asd_batch_destroy(asd_batch b) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    for (asd_grid g : b->sub)
+        if (g) asd_destroy(g);
+    delete b;
+    return ASD_OK;
+}
+
+extern "C" int asd_batch_set_problem(asd_batch b, int32_t p, void* dev_T, void* dev_bx, void* dev_by, double dt) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (p < 0 || p >= b->nprob) return asd_fail(ASD_EINVAL, "problem index %d out of range", p);
+    if (!(std::isfinite(dt) && dt > 0.0)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
+    asd_grid g = b->sub[p];
+    int rc = asd_set_field(g, ASD_FIELD_T, dev_T, g->N, g->d.dtype);
+    if (!rc) rc = asd_set_field(g, ASD_FIELD_BX, dev_bx, g->N, g->d.dtype);
+    if (!rc) rc = asd_set_field(g, ASD_FIELD_BY, dev_by, g->N, g->d.dtype);
+    if (rc) return rc;
+    b->dt[p] = dt;
+    b->dirty = true;
+    return ASD_OK;
+}
+
+extern "C" int asd_batch_set_block(asd_batch b, int32_t nthreads) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (nthreads != 256 && nthreads != 512 && nthreads != 1024)
+        return asd_fail(ASD_EINVAL, "nthreads must be 256, 512 or 1024");
+    return batch_shape(b, nthreads);
+}
+
+// Build (if needed) and upload the launch tables.
+template <typename T>
+static int batch_tables(asd_batch b) {
+    if (!b->dirty) return ASD_OK;
+    const int np = b->nprob;
+    b->h_probs.assign(sizeof(BatchProblem<T>) * np, 0);
+    BatchProblem<T>* probs = (BatchProblem<T>*)b->h_probs.data();
+    std::vector<double> load(np);
+    for (int p = 0; p < np; ++p) {
+        asd_grid g = b->sub[p];
+        for (int d = 0; d < 2; ++d) {
+            const void* in = d == 0 ? g->T : g->tmp[0];
+            void* out = d == 0 ? g->tmp[0] : g->T;
+            int rc = fill_sweep_params<T>(g, d, in, out, 0, b->cfg[2 * p + d], &probs[p].sweep[d]);
+            if (rc) return rc;
+            const int nt1 = probs[p].sweep[d].nt1, lpw = b->cfg[2 * p + d].lpw;
+            probs[p].ngroups[d] = (nt1 + lpw - 1) / lpw;
+        }
+        load[p] = (double)g->N;
+    }
+    // largest first, each to the least-loaded workgroup
+    b->nwg = std::min(np, kMaxWorkgroups);
+    std::vector<int> order(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return load[a] > load[c]; });
+    std::vector<double> wl(b->nwg, 0.0);
+    std::vector<std::vector<int>> owned(b->nwg);
+    for (int p : order) {
+        const int w = (int)(std::min_element(wl.begin(), wl.end()) - wl.begin());
+        owned[w].push_back(p);
+        wl[w] += load[p];
+    }
+    b->h_off.assign(b->nwg + 1, 0);
+    b->h_list.clear();
+    for (int w = 0; w < b->nwg; ++w) {
+        b->h_off[w] = (int)b->h_list.size();
+        b->h_list.insert(b->h_list.end(), owned[w].begin(), owned[w].end());
+    }
+    b->h_off[b->nwg] = (int)b->h_list.size();
+    for (int d = 0; d < 2; ++d) {
+        b->h_gs[d].assign(np + 1, 0);
+        for (int p = 0; p < np; ++p) b->h_gs[d][p + 1] = b->h_gs[d][p] + probs[p].ngroups[d];
+        b->ngroups[d] = b->h_gs[d][np];
+    }
+    // synchronous uploads: the tables change only with the problem set
+    hipError_t e = hipMemcpy(b->d_probs, b->h_probs.data(), b->h_probs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_off, b->h_off.data(), sizeof(int) * b->h_off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_list, b->h_list.data(), sizeof(int) * b->h_list.size(), hipMemcpyHostToDevice);
+    for (int d = 0; d < 2 && e == hipSuccess; ++d)
+        e = hipMemcpy(b->d_gs[d], b->h_gs[d].data(), sizeof(int) * (np + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch tables: %s", hipGetErrorString(e));
+    b->dirty = false;
+    return ASD_OK;
+}
+
+template <typename T>
+static int batch_step_t(asd_batch b, int nsteps, int mode) {
+    for (int p = 0; p < b->nprob; ++p) {
+        asd_grid g = b->sub[p];
+        if (!(b->dt[p] > 0.0)) return asd_fail(ASD_ENOTSET, "problem %d has not been set", p);
+        int rc = check_fields(g, true);
+        if (rc) return rc;
+        const bool was_valid = g->coef_valid && g->coef_dt == b->dt[p];
+        rc = prepare(g, b->dt[p]);
+        if (rc) return rc;
+        if (!was_valid) b->dirty = true;
+    }
+    if (mode == 1) {
+        for (int p = 0; p < b->nprob; ++p) {
+            int rc = enqueue_si_loop(b->sub[p], b->dt[p], nsteps, nullptr);
+            if (rc) return rc;
+        }
+        return ASD_OK;
+    }
+    int rc = batch_tables<T>(b);
+    if (rc) return rc;
+    const BatchProblem<T>* probs = (const BatchProblem<T>*)b->d_probs;
+    hipError_t e = hipSuccess;
+    if (mode == 0) {
+        e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds, b->st);
+    } else {
+        for (int s = 0; s < nsteps && e == hipSuccess; ++s)
+            for (int d = 0; d < 2 && e == hipSuccess; ++d)
+                e = launch_batch_grouped<T>(probs, b->d_gs[d], b->nprob, b->ngroups[d], d, b->mmax, b->nthreads,
+                                            b->lds, b->st);
+    }
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch launch: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
+extern "C" int asd_batch_step(asd_batch b, int32_t nsteps, int32_t mode) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
+    if (mode < -1 || mode > 2) return asd_fail(ASD_EINVAL, "mode must be -1 (tuned), 0, 1 or 2");
+    if (mode == -1) mode = b->mode;
+    if (nsteps == 0) return ASD_OK;
+    return b->d0.dtype == ASD_F64 ? batch_step_t<double>(b, nsteps, mode) : batch_step_t<float>(b, nsteps, mode);
+}
+
+// Time the persistent and grouped schedules at every admissible workgroup
+// size on `probe_steps` steps each and keep the fastest as mode -1.  The
+// problems' T are advanced by the probes; callers reset them afterwards.
+extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mode, int32_t* best_threads) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (probe_steps < 1) return asd_fail(ASD_EINVAL, "probe_steps must be >= 1");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return asd_fail(ASD_EHIP, "event create");
+    float best = 1e30f;
+    int bm = 0, bt = b->nthreads;
+    int rc = ASD_OK;
+    for (int nt : {256, 512, 1024}) {
+        if (batch_shape(b, nt) != ASD_OK) continue;
+        for (int mode : {0, 2}) {
+            rc = asd_batch_step(b, 1, mode);  // warm-up (tables, coefficients)
+            if (rc) break;
+            if (hipEventRecord(e0, b->st) != hipSuccess) { rc = asd_fail(ASD_EHIP, "event record"); break; }
+            rc = asd_batch_step(b, probe_steps, mode);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, b->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = asd_fail(ASD_EHIP, "event timing");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                bm = mode;
+                bt = nt;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = batch_shape(b, bt);
+    if (rc) return rc;
+    b->mode = bm;
+    if (best_mode) *best_mode = bm;
+    if (best_threads) *best_threads = bt;
+    return ASD_OK;
+}

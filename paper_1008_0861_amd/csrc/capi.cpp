@@ -49,7 +49,7 @@ extern "C" const char* asd_last_error(void) { return g_err.c_str(); }
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-static int validate_desc(const asd_desc* d) {
+int validate_desc(const asd_desc* d) {
     if (!d) return asd_fail(ASD_EINVAL, "desc is NULL");
     if (d->ndim != 2 && d->ndim != 3) return asd_fail(ASD_EINVAL, "ndim must be 2 or 3 (got %d)", d->ndim);
     if (d->bc != ASD_BC_PERIODIC && d->bc != ASD_BC_INSULATING)
@@ -244,7 +244,10 @@ static hipError_t g_attr_err = hipSuccess;
 
 template <typename T>
 static int do_prepare(asd_grid g, double dt) {
-    std::call_once(g_attr_once, [] { g_attr_err = sweep_set_lds_limits((int)kLdsLimit); });
+    std::call_once(g_attr_once, [] {
+        g_attr_err = sweep_set_lds_limits((int)kLdsLimit);
+        if (g_attr_err == hipSuccess) g_attr_err = batch_set_lds_limits((int)kLdsLimit);
+    });
     if (g_attr_err != hipSuccess) return hip_check(g_attr_err, "kernel attributes");
     if (!g->ws_inited) {
         int rc = hip_check(launch_fill_u32(g->flags, 0u, 1, g->st), "fill");
@@ -321,12 +324,11 @@ FoldParams make_fold(asd_grid g, const double* partials, int nblocks, double* en
     return f;
 }
 
+// Parameters of sweep d of grid g from `in` to `out` with launch shape c.
 template <typename T>
-static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
-                           const ReduceParams& red, const FoldParams& fold, const SweepCfg* override_cfg,
-                           int* nblocks_out) {
+int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode, const SweepCfg& c,
+                      SweepParams<T>* Pout) {
     const SweepGeom G = sweep_geom(g->d.ndim, d);
-    const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
     SweepParams<T> P{};
     P.U = (const T*)in;
     P.out = (T*)out;
@@ -354,6 +356,21 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
     P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode;
     if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
+    *Pout = P;
+    return ASD_OK;
+}
+template int fill_sweep_params<float>(asd_grid, int, const void*, void*, int, const SweepCfg&, SweepParams<float>*);
+template int fill_sweep_params<double>(asd_grid, int, const void*, void*, int, const SweepCfg&, SweepParams<double>*);
+
+template <typename T>
+static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
+                           const ReduceParams& red, const FoldParams& fold, const SweepCfg* override_cfg,
+                           int* nblocks_out) {
+    (void)dt;  // the coefficients were computed for dt by prepare()
+    const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
+    SweepParams<T> P;
+    int rc = fill_sweep_params<T>(g, d, in, out, rhs_mode, c, &P);
+    if (rc) return rc;
     P.red = red;
     P.fold = fold;
     const int nb1 = (P.nt1 + c.lpw - 1) / c.lpw;
