@@ -132,6 +132,111 @@ def measured_traffic(cfg):
     return t.get("bytes_per_launch")
 
 
+def matched_l1_speedup(stream, torch, asd):
+    """Wall-clock speed-up of the semi-implicit scheme over the explicit
+    limited scheme at matched L1 error, on the 1024^2 FP32 workload run to
+    t_end = 100 semi-implicit steps at ncfl = 20.  Reference: the explicit
+    scheme in FP64 at ncfl = 0.25.  The semi-implicit run counted is the one
+    at the largest ncfl whose L1 error is within max(L1 of explicit at
+    ncfl = 1, 1e-3 * ||T_end - T_0||_1)."""
+    import synth
+    base = synth.grf2d_problem(NX, nsteps=1)
+    h = base.h
+    unit = min(h) ** 2 / 4.0  # dt at ncfl = 1
+    t_end = 100 * 20 * unit
+
+    def run(prec, scheme, ncfl, time_it=False):
+        nsteps = int(round(t_end / (ncfl * unit)))
+        g = make_grid(base, prec, stream, torch, asd)
+        dt = t_end / nsteps
+        f = g.step_semi_implicit if scheme == "si" else g.step_explicit
+        with torch.cuda.stream(stream):
+            if scheme == "si":
+                g.tune(dt, reps=10)
+            if time_it:  # same call twice: the first captures the step graph
+                T0 = g.T.clone()
+                f(dt, nsteps)
+                g.T.copy_(T0)
+                stream.synchronize()
+                ms = timed(lambda: f(dt, nsteps), stream, torch)
+            else:
+                f(dt, nsteps)
+                ms = None
+        stream.synchronize()
+        return g.T.double(), ms, nsteps
+
+    ref, _, nref = run("f64", "ex", 0.25)
+    T0 = torch.from_numpy(base.T0).cuda()
+    change = float((ref - T0).abs().mean())
+    eps = 1e-3 * change
+    ex, ms_ex, n_ex = run("f32", "ex", 1.0, time_it=True)
+    l1_ex = float((ex - ref).abs().mean())
+    rows = []
+    for ncfl in (2, 5, 10, 20, 50, 100):
+        si, ms, n = run("f32", "si", float(ncfl), time_it=True)
+        rows.append(dict(ncfl=ncfl, steps=n, l1=float((si - ref).abs().mean()), ms=round(ms, 3)))
+    def pick(tol):
+        ok = [r for r in rows if r["l1"] <= max(l1_ex, tol)]
+        best = max(ok, key=lambda r: r["ncfl"]) if ok else None
+        return dict(tolerance=tol, ncfl=best["ncfl"] if best else None,
+                    speedup=round(ms_ex / best["ms"], 2) if best else None)
+
+    return {
+        "reference": f"explicit FP64, ncfl 0.25, {nref} steps",
+        "l1_change": change,
+        "explicit": dict(ncfl=1, steps=n_ex, l1=l1_ex, ms=round(ms_ex, 3)),
+        "semi_implicit": rows,
+        # L1 tolerance as a fraction of ||T_end - T_0||_1 (mean per cell)
+        "at_1e-3_change": pick(eps),
+        "at_1e-2_change": pick(10 * eps),
+        "at_3e-2_change": pick(30 * eps),
+    }
+
+
+def batched(stream, torch, asd, nsteps=100):
+    """256 independent problems (sides 64..512, FP32), nsteps steps: tuned
+    batched schedule vs one launch per problem per sweep."""
+    import synth
+    probs = synth.batch_problems(nprob=256, master_seed=40, nsteps=nsteps)
+    with torch.cuda.stream(stream):
+        items = [dict(shape=p.shape, h=p.h, chi_par=p.chi_par, dt=p.dt, T=torch.from_numpy(p.T0).float().cuda(),
+                      bx=torch.from_numpy(p.b[0]).float().cuda(), by=torch.from_numpy(p.b[1]).float().cuda())
+                 for p in probs]
+        b = asd.Batch(items, dtype=torch.float32)
+        mode, nthreads = b.tune(probe_steps=2)
+        b.step(2)
+    stream.synchronize()
+    cells = sum(p.ncells for p in probs)
+    out = {"problems": 256, "cells": cells, "steps": nsteps, "tuned_mode": mode, "tuned_threads": nthreads}
+    for name, m in (("tuned", -1), ("persistent", 0), ("grouped", 2), ("sequential", 1)):
+        with torch.cuda.stream(stream):
+            ms = timed(lambda: b.step(nsteps, m), stream, torch)
+        out[name + "_Gcells"] = round(cells * nsteps / (ms * 1e-3) / 1e9, 3)
+    out["tuned_vs_sequential"] = round(out["tuned_Gcells"] / out["sequential_Gcells"], 2)
+    return out
+
+
+def three_d(stream, torch, asd, nsteps=50):
+    """256^3 periodic curl-field problem, FP32 state, ncfl = 10 (chi dt/h^2 =
+    2.5), FP64 energy every step: Gcell-updates/s and energy drift."""
+    import synth
+    p = synth.curl3d_problem(256, nsteps=nsteps)
+    g = make_grid(p, "f32", stream, torch, asd)
+    ebuf = torch.empty(nsteps + 1, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        g.tune(p.dt, reps=5)
+        T0 = g.T.clone()
+        g.step_semi_implicit(p.dt, nsteps, out=ebuf)
+        g.T.copy_(T0)
+        stream.synchronize()
+        ms = timed(lambda: g.step_semi_implicit(p.dt, nsteps, out=ebuf), stream, torch)
+    e = ebuf.cpu().numpy()
+    return {"cells": p.ncells, "steps": nsteps, "ms_per_step": round(ms / nsteps, 4),
+            "Gcells": round(p.ncells * nsteps / (ms * 1e-3) / 1e9, 3),
+            "algorithmic_GBs": round(p.ncells * 60 * nsteps / (ms * 1e-3) / 1e9, 1),
+            "energy_rel_drift": float(abs(e[-1] - e[0]) / abs(e[0]))}
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle, serial on one host core, on the same 1024^2 workload:
     as many whole steps as fit in about budget_s seconds (at least 2)."""
@@ -249,6 +354,9 @@ def main():
             msx = timed(lambda: gx.step_explicit(dtx, 2000, out=ebx), stream, torch) / 2000
         extra["explicit_fp32_Gcells"] = round(N / (msx * 1e-3) / 1e9, 3)
         extra["explicit_ms_per_step"] = round(msx, 6)
+        result["speedup_vs_explicit"] = matched_l1_speedup(stream, torch, asd)
+        extra["batched"] = batched(stream, torch, asd)
+        extra["curl3d_256"] = three_d(stream, torch, asd)
         result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
