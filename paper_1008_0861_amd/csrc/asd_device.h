@@ -86,30 +86,176 @@ __device__ __forceinline__ int64_t nb_coord(int64_t c, int64_t n, bool periodic)
     return c;
 }
 
-// Shared-memory index with one pad element per 32 (FP32) / 16 (FP64)
-// elements, so that lanes walking contiguous segments of a line hit
-// distinct LDS banks.
-template <typename T>
-__device__ __forceinline__ int lds_pad(int p) {
-    return sizeof(T) == 4 ? p + (p >> 5) : p + (p >> 4);
-}
-template <typename T>
-__host__ __device__ inline int lds_line_stride(int n) {
-    int s = (sizeof(T) == 4) ? n + (n >> 5) + 1 : n + (n >> 4) + 1;
-    return s | 1;  // odd stride: consecutive lines start in different banks
+// LDS layout of one sweep tile (byte offsets; computed by the host, stored
+// in the sweep parameters).  Each line of the tile owns a row of cell
+// slots of four elements [S1, A, B1, U]: the limited transverse slope, the
+// normal and transverse coefficients of the face after the cell, and the
+// state (replaced by the solution once the line is solved).  In 3-D a
+// second row holds the pairs [S2, B2].  Slot n repeats cell 0 (the right
+// neighbour of the last cell of a periodic line; a wall face has zero
+// coefficients, so the copy is harmless there), and a few spare slots
+// follow it.  When every segment of the line has the same power-of-two
+// length, a 16-byte pad (a pair-sized pad in the second row) follows every
+// 2^pad cells, 2^pad being the distance between the segments of
+// neighbouring lanes, so that those lanes hit distinct banks; no segment
+// then contains a pad, and a segment's slots are always consecutive.
+// When several waves share a line, the interface reduction has two
+// exchange buffers with one slot per thread; the second lives in the dead
+// [S1, A, B1] part of the line's first slots when the line has at least as
+// many cells as lanes.
+__host__ __device__ inline int cell_off1(int p, int es, int pad) { return p * 4 * es + ((p >> pad) << 4); }
+__host__ __device__ inline int cell_off2(int p, int es, int pad) { return (p + (p >> pad)) * 2 * es; }
+
+static constexpr int kRowSpare = 17;  // spare slots after the copy of cell 0 (reads up to MMAX + 1 past a segment start)
+
+struct TileLayout {
+    int aligned;   // every segment has the kernel's maximal length (pads in use)
+    int pad;       // log2 of the cells per pad (30: no pad)
+    int row1;      // bytes per line, slot rows
+    int row2;      // bytes per line, pair rows (3-D)
+    int rows2_at;  // offset of the pair rows
+    int pcr0_at;   // offset of exchange buffer 0
+    int pcr1_at;   // offset of exchange buffer 1, or -1: inside the slot rows
+    int total;     // bytes
+};
+
+__host__ __device__ inline TileLayout tile_layout(int es, int ndim, int n, int lpw, int nthreads, int wpl,
+                                                  int nseg_log2, int mmax) {
+    TileLayout L;
+    const int m = n >> nseg_log2;
+    L.aligned = (m << nseg_log2) == n && m == mmax;  // mmax is a power of two
+    L.pad = 30;
+    if (L.aligned && m * wpl >= 2) {
+        int l = 0;
+        while ((2 << l) <= m * wpl) ++l;
+        L.pad = l;  // 2^pad = m * wpl: segments of neighbouring lanes
+    }
+    int r1 = cell_off1(n + 1 + kRowSpare, es, L.pad);
+    if (((r1 >> 4) & 1) == 0) r1 += 16;  // odd number of 16-byte units: rows start in different banks
+    L.row1 = r1;
+    int r2 = 0;
+    if (ndim == 3) {
+        r2 = (cell_off2(n + 1 + kRowSpare, es, L.pad) + 15) & ~15;
+        if (((r2 >> 4) & 1) == 0) r2 += 16;
+    }
+    L.row2 = r2;
+    L.rows2_at = lpw * r1;
+    int at = L.rows2_at + lpw * r2;
+    L.pcr0_at = at;
+    L.pcr1_at = -1;
+    if (wpl > 1) {
+        at += nthreads * 4 * es;
+        if (64 * wpl > n) {
+            L.pcr1_at = at;
+            at += nthreads * 4 * es;
+        }
+    }
+    L.total = at;
+    return L;
 }
 
-// Wave / block reductions used by the fused FP64 energy epilogue.
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// 16-byte-aligned LDS accesses of slots (4 elements), triples and pairs.
+template <typename T>
+__device__ __forceinline__ void lds_put4(unsigned char* p, T a, T b, T c, T d);
+template <>
+__device__ __forceinline__ void lds_put4<float>(unsigned char* p, float a, float b, float c, float d) {
+    *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+template <>
+__device__ __forceinline__ void lds_put4<double>(unsigned char* p, double a, double b, double c, double d) {
+    reinterpret_cast<double2*>(p)[0] = make_double2(a, b);
+    reinterpret_cast<double2*>(p)[1] = make_double2(c, d);
+}
+template <typename T>
+__device__ __forceinline__ void lds_get4(const unsigned char* p, T& a, T& b, T& c, T& d);
+template <>
+__device__ __forceinline__ void lds_get4<float>(const unsigned char* p, float& a, float& b, float& c, float& d) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    a = v.x; b = v.y; c = v.z; d = v.w;
+}
+template <>
+__device__ __forceinline__ void lds_get4<double>(const unsigned char* p, double& a, double& b, double& c,
+                                                 double& d) {
+    const double2 v0 = reinterpret_cast<const double2*>(p)[0];
+    const double2 v1 = reinterpret_cast<const double2*>(p)[1];
+    a = v0.x; b = v0.y; c = v1.x; d = v1.y;
+}
+// Global load at a 32-bit byte offset from a wave-uniform base (a scalar
+// base plus a vector offset, no 64-bit address arithmetic per load).
+template <typename T>
+__device__ __forceinline__ T ldg_off(const T* base, unsigned byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(base) + byte_off);
+}
+
+// first three elements of a slot only (the fourth is left untouched)
+template <typename T>
+__device__ __forceinline__ void lds_put3(unsigned char* p, T a, T b, T c) {
+    T* q = reinterpret_cast<T*>(p);
+    q[0] = a;
+    q[1] = b;
+    q[2] = c;
+}
+template <typename T>
+__device__ __forceinline__ void lds_put2(unsigned char* p, T a, T b) {
+    T* q = reinterpret_cast<T*>(p);
+    q[0] = a;
+    q[1] = b;
+}
+template <typename T>
+__device__ __forceinline__ void lds_get2(const unsigned char* p, T& a, T& b) {
+    const T* q = reinterpret_cast<const T*>(p);
+    a = q[0];
+    b = q[1];
+}
+
+// Wave reductions with DPP lane moves, in a fixed order: pairs, quads,
+// half rows and rows of 16 lanes; then rows 1 and 3 take rows 0 and 2, and
+// rows 2-3 take row 1.  Lane 63 ends with the result over all 64 lanes.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_mov(T old, T v) {
+    if constexpr (sizeof(T) == 8) return dpp_f64<CTRL, ROWS>(old, v);
+    else return dpp_f32<CTRL, ROWS>(old, v);
+}
+enum : int { DPP_QP_1032 = 0xB1, DPP_QP_2301 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141,
+             DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143 };
+
+__device__ __forceinline__ double wave_sum_lane63(double v) {
+    v += dpp_mov<DPP_QP_1032, 0xf>(0.0, v);
+    v += dpp_mov<DPP_QP_2301, 0xf>(0.0, v);
+    v += dpp_mov<DPP_ROW_HALF_MIRROR, 0xf>(0.0, v);
+    v += dpp_mov<DPP_ROW_MIRROR, 0xf>(0.0, v);
+    v += dpp_mov<DPP_ROW_BCAST15, 0xa>(0.0, v);
+    v += dpp_mov<DPP_ROW_BCAST31, 0xc>(0.0, v);
     return v;
 }
-__device__ __forceinline__ double wave_min(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+template <typename T>
+__device__ __forceinline__ T wave_min_lane63(T v) {
+    v = fmin(v, dpp_mov<DPP_QP_1032, 0xf>(v, v));
+    v = fmin(v, dpp_mov<DPP_QP_2301, 0xf>(v, v));
+    v = fmin(v, dpp_mov<DPP_ROW_HALF_MIRROR, 0xf>(v, v));
+    v = fmin(v, dpp_mov<DPP_ROW_MIRROR, 0xf>(v, v));
+    v = fmin(v, dpp_mov<DPP_ROW_BCAST15, 0xa>(v, v));
+    v = fmin(v, dpp_mov<DPP_ROW_BCAST31, 0xc>(v, v));
     return v;
 }
-__device__ __forceinline__ double wave_max(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+template <typename T>
+__device__ __forceinline__ T wave_max_lane63(T v) {
+    v = fmax(v, dpp_mov<DPP_QP_1032, 0xf>(v, v));
+    v = fmax(v, dpp_mov<DPP_QP_2301, 0xf>(v, v));
+    v = fmax(v, dpp_mov<DPP_ROW_HALF_MIRROR, 0xf>(v, v));
+    v = fmax(v, dpp_mov<DPP_ROW_MIRROR, 0xf>(v, v));
+    v = fmax(v, dpp_mov<DPP_ROW_BCAST15, 0xa>(v, v));
+    v = fmax(v, dpp_mov<DPP_ROW_BCAST31, 0xc>(v, v));
     return v;
 }
 

@@ -26,12 +26,18 @@ inline int pow2_floor(int v) {
     return p;
 }
 
-// LDS of a sweep launch: U, alpha, slope and beta per transverse axis for
-// each line, and three reduction arrays per thread.
-inline size_t sweep_lds(int es, int ndim, int n, int lpw, int nthreads) {
-    const int LS = es == 8 ? asd::lds_line_stride<double>(n) : asd::lds_line_stride<float>(n);
-    const int narr = ndim == 2 ? 4 : 6;
-    return (size_t)es * ((size_t)narr * lpw * LS + 3 * (size_t)nthreads);
+inline int ilog2(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+
+// LDS bytes of a sweep launch (tile_layout: slot rows of the lpw lines and
+// the interface-exchange buffers).
+inline size_t sweep_lds(int es, int ndim, int n, int lpw, int nthreads, int mmax) {
+    const int wpl = nthreads / (64 * lpw);
+    const int P = std::min(64 * wpl, pow2_floor(n));
+    return (size_t)asd::tile_layout(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax).total;
 }
 
 inline int sweep_threads_cap(int es, int mmax) {
@@ -77,10 +83,10 @@ inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int
     if (64 * wpl > cap) return false;
     int lpw = want_lpw;
     if (lpw <= 0) lpw = std::max(1, 256 / (64 * wpl));
-    while (lpw > 1 && (64 * wpl * lpw > cap || sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw) > kLdsLimit))
+    while (lpw > 1 && (64 * wpl * lpw > cap || sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw, mmax) > kLdsLimit))
         lpw /= 2;
     if (64 * wpl * lpw > cap) return false;
-    if (sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw) > kLdsLimit) return false;
+    if (sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw, mmax) > kLdsLimit) return false;
     out->wpl = wpl;
     out->lpw = lpw;
     out->P = P;

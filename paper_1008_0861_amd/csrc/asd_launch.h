@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "asd_device.h"
+
 namespace asd {
 
 // Fused FP64 reduction of a state, without any cross-block fence: the
@@ -44,6 +46,7 @@ struct SweepParams {
     int spl_log2;     // log2(64*wpl)
     int lpw_log2;     // log2(lpw)
     int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)
+    TileLayout lds;   // LDS layout of a tile (tile_layout)
     ReduceParams red;
     FoldParams fold;
 };
@@ -110,10 +113,10 @@ struct BatchProblem {
 };
 template <typename T>
 hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
-                                   int mmax, int nthreads, size_t lds, hipStream_t st);
+                                   int mmax, int nthreads, size_t lds, int limiter, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
-                                int mmax, int nthreads, size_t lds, hipStream_t st);
+                                int mmax, int nthreads, size_t lds, int limiter, hipStream_t st);
 hipError_t batch_set_lds_limits(int bytes);
 
 // ----------------------------------------------------------------- adjoint
@@ -159,16 +162,15 @@ hipError_t launch_axpy(T* y, const T* x, T a, int64_t N, hipStream_t st);
 // ------------------------------------------------- block reduction epilogue
 // Block-wide (sum, min, max); every thread must call it.  Writes the
 // block's partial.
-__device__ __forceinline__ void block_partials(double* partials, double s, double mn, double mx) {
+template <typename M>
+__device__ __forceinline__ void block_partials(double* partials, double s, M mn, M mx) {
     __shared__ double red_s[16], red_mn[16], red_mx[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
-    for (int off = 32; off > 0; off >>= 1) {
-        s += __shfl_xor(s, off, 64);
-        mn = fmin(mn, __shfl_xor(mn, off, 64));
-        mx = fmax(mx, __shfl_xor(mx, off, 64));
-    }
-    if (lane == 0) { red_s[wid] = s; red_mn[wid] = mn; red_mx[wid] = mx; }
+    s = wave_sum_lane63(s);
+    mn = wave_min_lane63<M>(mn);
+    mx = wave_max_lane63<M>(mx);
+    if (lane == 63) { red_s[wid] = s; red_mn[wid] = (double)mn; red_mx[wid] = (double)mx; }
     __syncthreads();
     if (threadIdx.x == 0) {
         double ts = 0.0, tmn = red_mn[0], tmx = red_mx[0];

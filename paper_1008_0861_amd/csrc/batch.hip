@@ -15,7 +15,7 @@
 
 namespace asd {
 
-template <typename T, int MMAX>
+template <typename T, int MMAX, int LIMC>
 __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     batch_persistent_kernel(const BatchProblem<T>* probs, const int* off, const int* list, int nsteps) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -29,7 +29,7 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
             for (int d = 0; d < 2; ++d) {
                 const SweepParams<T> P = bp->sweep[d];
                 const int ng = bp->ngroups[d];
-                for (int g = 0; g < ng; ++g) sweep_tile<T, 2, MMAX>(P, g * P.lpw, 0, smem_raw, lsum, lmin, lmax);
+                for (int g = 0; g < ng; ++g) sweep_tile<T, 2, MMAX, LIMC>(P, g * P.lpw, 0, smem_raw, lsum, lmin, lmax);
                 // sweep_tile ends with a block barrier: this sweep's stores are
                 // visible to every thread of the workgroup before the next sweep
             }
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     }
 }
 
-template <typename T, int MMAX>
+template <typename T, int MMAX, int LIMC>
 __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     batch_grouped_kernel(const BatchProblem<T>* probs, const int* group_start, int nprob, int d) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -51,16 +51,22 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     const SweepParams<T> P = probs[lo].sweep[d];
     double lsum;
     T lmin, lmax;
-    sweep_tile<T, 2, MMAX>(P, (b - group_start[lo]) * P.lpw, 0, smem_raw, lsum, lmin, lmax);
+    sweep_tile<T, 2, MMAX, LIMC>(P, (b - group_start[lo]) * P.lpw, 0, smem_raw, lsum, lmin, lmax);
 }
 
-template <typename T, int MMAX>
-static hipError_t set_batch_attrs(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)batch_persistent_kernel<T, MMAX>,
+template <typename T, int MMAX, int LIMC>
+static hipError_t set_batch_attrs_lim(int bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)batch_persistent_kernel<T, MMAX, LIMC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)batch_grouped_kernel<T, MMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                bytes);
+        e = hipFuncSetAttribute((const void*)batch_grouped_kernel<T, MMAX, LIMC>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+template <typename T, int MMAX>
+static hipError_t set_batch_attrs(int bytes) {
+    hipError_t e = set_batch_attrs_lim<T, MMAX, LIM_VANLEER>(bytes);
+    if (e == hipSuccess) e = set_batch_attrs_lim<T, MMAX, -1>(bytes);
     return e;
 }
 
@@ -74,13 +80,23 @@ hipError_t batch_set_lds_limits(int bytes) {
     return e;
 }
 
+// The problems of a batch share one limiter (checked by the host); van
+// Leer has its own straight-line instantiation.
+#define ASD_BATCH_LAUNCH(KERNEL, MM, ...)                                                   \
+    do {                                                                                    \
+        if (limiter == LIM_VANLEER)                                                         \
+            hipLaunchKernelGGL((KERNEL<T, MM, LIM_VANLEER>), __VA_ARGS__);                  \
+        else                                                                                \
+            hipLaunchKernelGGL((KERNEL<T, MM, -1>), __VA_ARGS__);                           \
+    } while (0)
+
 template <typename T>
 hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
-                                   int mmax, int nthreads, size_t lds, hipStream_t st) {
+                                   int mmax, int nthreads, size_t lds, int limiter, hipStream_t st) {
     switch (mmax) {
-        case 4: hipLaunchKernelGGL((batch_persistent_kernel<T, 4>), dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps); break;
-        case 8: hipLaunchKernelGGL((batch_persistent_kernel<T, 8>), dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps); break;
-        case 16: hipLaunchKernelGGL((batch_persistent_kernel<T, 16>), dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps); break;
+        case 4: ASD_BATCH_LAUNCH(batch_persistent_kernel, 4, dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps); break;
+        case 8: ASD_BATCH_LAUNCH(batch_persistent_kernel, 8, dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps); break;
+        case 16: ASD_BATCH_LAUNCH(batch_persistent_kernel, 16, dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -88,23 +104,24 @@ hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off,
 
 template <typename T>
 hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
-                                int mmax, int nthreads, size_t lds, hipStream_t st) {
+                                int mmax, int nthreads, size_t lds, int limiter, hipStream_t st) {
     switch (mmax) {
-        case 4: hipLaunchKernelGGL((batch_grouped_kernel<T, 4>), dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d); break;
-        case 8: hipLaunchKernelGGL((batch_grouped_kernel<T, 8>), dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d); break;
-        case 16: hipLaunchKernelGGL((batch_grouped_kernel<T, 16>), dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d); break;
+        case 4: ASD_BATCH_LAUNCH(batch_grouped_kernel, 4, dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d); break;
+        case 8: ASD_BATCH_LAUNCH(batch_grouped_kernel, 8, dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d); break;
+        case 16: ASD_BATCH_LAUNCH(batch_grouped_kernel, 16, dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+#undef ASD_BATCH_LAUNCH
 
 template hipError_t launch_batch_persistent<float>(const BatchProblem<float>*, const int*, const int*, int, int, int,
-                                                   int, size_t, hipStream_t);
+                                                   int, size_t, int, hipStream_t);
 template hipError_t launch_batch_persistent<double>(const BatchProblem<double>*, const int*, const int*, int, int,
-                                                    int, int, size_t, hipStream_t);
+                                                    int, int, size_t, int, hipStream_t);
 template hipError_t launch_batch_grouped<float>(const BatchProblem<float>*, const int*, int, int, int, int, int,
-                                                size_t, hipStream_t);
+                                                size_t, int, hipStream_t);
 template hipError_t launch_batch_grouped<double>(const BatchProblem<double>*, const int*, int, int, int, int, int,
-                                                 size_t, hipStream_t);
+                                                 size_t, int, hipStream_t);
 
 }  // namespace asd

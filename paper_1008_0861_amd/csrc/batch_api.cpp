@@ -88,7 +88,7 @@ static bool batch_line_cfg(int es, int n, int nthreads, int mmax, SweepCfg* out)
         const int P = std::min(64 * wpl, pow2_floor(n));
         if ((n + P - 1) / P > mmax) continue;
         const int lpw = nthreads / (64 * wpl);
-        if (sweep_lds(es, 2, n, lpw, nthreads) > kLdsLimit) continue;
+        if (sweep_lds(es, 2, n, lpw, nthreads, mmax) > kLdsLimit) continue;
         out->wpl = wpl;
         out->lpw = lpw;
         out->P = P;
@@ -110,7 +110,7 @@ static int batch_shape(asd_batch b, int nthreads) {
             for (int d = 0; d < 2 && ok; ++d) {
                 const int n = (int)b->sub[p]->d.n[d];
                 ok = batch_line_cfg(es, n, nthreads, mmax, &cfg[2 * p + d]);
-                if (ok) lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, nthreads));
+                if (ok) lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, nthreads, mmax));
             }
         }
         if (!ok) continue;
@@ -279,12 +279,13 @@ static int batch_step_t(asd_batch b, int nsteps, int mode) {
     const BatchProblem<T>* probs = (const BatchProblem<T>*)b->d_probs;
     hipError_t e = hipSuccess;
     if (mode == 0) {
-        e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds, b->st);
+        e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds,
+                                       b->d0.limiter, b->st);
     } else {
         for (int s = 0; s < nsteps && e == hipSuccess; ++s)
             for (int d = 0; d < 2 && e == hipSuccess; ++d)
                 e = launch_batch_grouped<T>(probs, b->d_gs[d], b->nprob, b->ngroups[d], d, b->mmax, b->nthreads,
-                                            b->lds, b->st);
+                                            b->lds, b->d0.limiter, b->st);
     }
     if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch launch: %s", hipGetErrorString(e));
     return ASD_OK;

@@ -295,12 +295,6 @@ int prepare(asd_grid g, double dt) { return g->es == 8 ? do_prepare<double>(g, d
 
 // --------------------------------------------------------------- sweeps
 
-static int ilog2(int v) {
-    int l = 0;
-    while ((1 << (l + 1)) <= v) ++l;
-    return l;
-}
-
 ReduceParams no_reduce() {
     ReduceParams r{};
     return r;
@@ -355,6 +349,7 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.spl_log2 = ilog2(64 * c.wpl);
     P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode;
+    P.lds = tile_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), c.wpl, P.nseg_log2, c.mmax);
     if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
     *Pout = P;
     return ASD_OK;
@@ -378,7 +373,7 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
     if (nblocks_out) *nblocks_out = (int)nblocks;
     if (red.partials && nblocks > g->max_blocks)
         return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
-    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads());
+    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), c.mmax);
     return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st),
                      "sweep launch");
 }

@@ -5,7 +5,7 @@
 
 namespace asd {
 
-template <typename T, int NDIM, int MMAX>
+template <typename T, int NDIM, int MMAX, int LIMC>
 __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_kernel(SweepParams<T> P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // XCD-aware block order: consecutive logical blocks on the same XCD so
@@ -19,19 +19,24 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
     const int l1_0 = (blk - l2 * nb1) * P.lpw;
     double lsum;
     T lmin, lmax;
-    sweep_tile<T, NDIM, MMAX>(P, l1_0, l2, smem_raw, lsum, lmin, lmax);
+    sweep_tile<T, NDIM, MMAX, LIMC>(P, l1_0, l2, smem_raw, lsum, lmin, lmax);
     // FP64 energy / min / max partials, and the fold of the previous
     // launch's partials (block 0 only)
-    if (P.red.partials) block_partials(P.red.partials, lsum, (double)lmin, (double)lmax);
+    if (P.red.partials) block_partials<T>(P.red.partials, lsum, lmin, lmax);
     if (P.fold.partials && blockIdx.x == 0) fold_partials(P.fold);
 }
 
+// Van Leer (the default limiter) gets its own straight-line instantiation;
+// the other limiters share one that reads the limiter at run time.
 template <typename T, int NDIM>
 static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid, dim3 block, size_t lds,
                                    hipStream_t st) {
-#define ASD_SWEEP_CASE(MM)                                                        \
-    case MM:                                                                      \
-        hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM>), grid, block, lds, st, P); \
+#define ASD_SWEEP_CASE(MM)                                                                     \
+    case MM:                                                                                   \
+        if (P.limiter == LIM_VANLEER)                                                          \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, LIM_VANLEER>), grid, block, lds, st, P); \
+        else                                                                                   \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1>), grid, block, lds, st, P);      \
         return hipGetLastError();
     switch (mmax) {
         ASD_SWEEP_CASE(1)
@@ -46,16 +51,22 @@ static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid,
 
 // Raise the dynamic-LDS limit of every sweep instantiation to the gfx950
 // maximum.  Called once per process, before any launch or stream capture.
-template <typename T, int NDIM>
-static hipError_t set_attrs_dim(int bytes) {
-    const void* fns[] = {(const void*)sweep_kernel<T, NDIM, 1>, (const void*)sweep_kernel<T, NDIM, 2>,
-                         (const void*)sweep_kernel<T, NDIM, 4>, (const void*)sweep_kernel<T, NDIM, 8>,
-                         (const void*)sweep_kernel<T, NDIM, 16>};
+template <typename T, int NDIM, int LIMC>
+static hipError_t set_attrs_lim(int bytes) {
+    const void* fns[] = {(const void*)sweep_kernel<T, NDIM, 1, LIMC>, (const void*)sweep_kernel<T, NDIM, 2, LIMC>,
+                         (const void*)sweep_kernel<T, NDIM, 4, LIMC>, (const void*)sweep_kernel<T, NDIM, 8, LIMC>,
+                         (const void*)sweep_kernel<T, NDIM, 16, LIMC>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+template <typename T, int NDIM>
+static hipError_t set_attrs_dim(int bytes) {
+    hipError_t e = set_attrs_lim<T, NDIM, LIM_VANLEER>(bytes);
+    if (e == hipSuccess) e = set_attrs_lim<T, NDIM, -1>(bytes);
+    return e;
 }
 
 hipError_t sweep_set_lds_limits(int bytes) {

@@ -13,19 +13,27 @@
 // arrays, so every line is handled as a cyclic system.
 //
 // gfx950 mapping.  A workgroup owns `lpw` neighbouring lines; each line is
-// owned by `wpl` waves.  Phase 1 streams the lines (and the neighbouring
-// lines needed for the transverse slopes) from HBM into LDS with coalesced
-// loads, all issued before use.  Phase 2 splits each line into P contiguous
-// segments, one per lane; a lane eliminates its segment interior in
-// registers, leaving one interface unknown per segment (its last cell).
+// owned by `wpl` waves (a wave never spans two lines, so every per-line
+// quantity is wave-uniform and lives in scalar registers).  Phase 1 streams
+// the lines (and the neighbouring lines needed for the transverse slopes)
+// from HBM with coalesced loads, all issued before use, and packs each
+// cell's slope, coefficients and state into one LDS slot (tile_layout).
+// Phase 2 splits each line into P contiguous segments, one per lane, dealt
+// to the line's waves in turn; a lane reads its segment's slots (one vector
+// LDS read per cell), builds the rows and eliminates the segment interior
+// in registers, leaving one interface unknown per segment (its last cell).
 // The P interface unknowns form a cyclic tridiagonal system (the Schur
-// complement), solved by parallel cyclic reduction in log2(P) steps: across
-// lanes with shuffles when a wave owns the line, through LDS otherwise.
-// Each equation is kept normalised (unit diagonal), so a reduction step
-// costs one reciprocal.  Phase 3 writes the tile back, transposed when the
-// output layout has the transverse axis fastest (the next sweep then reads
+// complement), solved by parallel cyclic reduction in log2(P) steps: every
+// step whose stride is at least wpl pairs two lanes of one wave (a
+// shuffle); only the log2(wpl) shorter strides go through LDS.  Each
+// equation is kept normalised (unit diagonal), so a reduction step costs
+// one reciprocal.  Phase 3 writes the tile back, transposed when the output
+// layout has the transverse axis fastest (the next sweep then reads
 // contiguous lines again).  The systems are symmetric, strictly diagonally
 // dominant M-matrices: no pivoting anywhere.
+//
+// LIMC: the limiter as a compile-time constant (straight-line code), or -1
+// to read it from the parameters.
 #pragma once
 
 #include "asd_device.h"
@@ -37,40 +45,32 @@ namespace asd {
 // sweep described by P.  Every thread of the block must call it; it ends
 // with a barrier so that consecutive tiles may reuse the LDS.  Returns the
 // thread's FP64 sum and min / max of the values it wrote.
-template <typename T, int NDIM, int MMAX>
-__device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem_raw,
+template <typename T, int NDIM, int MMAX, int LIMC>
+__device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem,
                                            double& lsum, T& lmin, T& lmax) {
-    T* smem = reinterpret_cast<T*>(smem_raw);
+    constexpr int ES = (int)sizeof(T);
+    constexpr int SLOT = 4 * ES;  // bytes of a cell slot / exchange slot
+    constexpr int UPOS = 3 * ES;  // byte offset of U inside a cell slot
     const int n = P.n;
-    const int LS = lds_line_stride<T>(n);
     const int lpw = P.lpw;
-    const int seg_per_line = 64 * P.wpl;  // lanes per line
+    const int spl = 64 * P.wpl;  // lanes per line
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
     const bool solve_only = P.rhs_mode != 0;
-
-    // LDS regions, each lpw * LS elements
-    T* sU = smem;
-    T* sA = sU + lpw * LS;
-    T* sS1 = sA + lpw * LS;
-    T* sB1 = sS1 + lpw * LS;
-    T* sS2 = sB1 + lpw * LS;                    // 3-D only
-    T* sB2 = sS2 + (NDIM == 3 ? lpw * LS : 0);  // 3-D only
-    T* pcr = sB2 + (NDIM == 3 ? lpw * LS : 0);  // 3 * nthreads elements
-    T* pA = pcr;
-    T* pC = pA + nthreads;
-    T* pD = pC + nthreads;
-
     const bool periodic = P.periodic != 0;
-    const int lim = P.limiter;
+    const int lim = LIMC >= 0 ? LIMC : P.limiter;
+    const TileLayout& Lo = P.lds;
+    const int pad = Lo.pad;
 
     // Threads [q*spl, (q+1)*spl) own line q of the tile (spl = 64*wpl lanes;
-    // powers of two, so line membership is a shift).
+    // a power of two, so line membership is a shift, uniform over a wave).
     const int spl_log2 = P.spl_log2;
-    const int q = tid >> spl_log2;
-    const int k = tid & (seg_per_line - 1);
+    const int q = __builtin_amdgcn_readfirstlane(tid >> spl_log2);
+    const int k = tid & (spl - 1);
     const int l1 = l1_0 + q;
     const bool line_ok = l1 < P.nt1;
+    unsigned char* row1 = smem + q * Lo.row1;
+    unsigned char* row2 = smem + Lo.rows2_at + q * Lo.row2;
     // element offsets of this line and of its transverse neighbours (the
     // boundary rule applies once per line, not per cell)
     const unsigned base = line_ok ? (unsigned)(l1 * P.si_t1 + l2 * P.si_t2) : 0u;
@@ -83,48 +83,68 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
             base2p = base + (int)(nb_coord(l2 + 1, P.nt2, periodic) - l2) * P.si_t2;
         }
     }
+    const T* gU = P.U + base;
+    const T* gU1m = P.U + base1m;
+    const T* gU1p = P.U + base1p;
+    const T* gU2m = P.U + base2m;
+    const T* gU2p = P.U + base2p;
+    const T* gA = P.alpha + base;
+    const T* gB1 = P.beta1 + base;
+    const T* gB2 = NDIM == 3 ? P.beta2 + base : nullptr;
 
-    // ---------------- phase 1: coalesced loads -> LDS (U, alpha, slopes, beta)
-    // Lane k of the line loads cells k, k+spl, ... (at most MMAX of them: the
+    // ---------------- phase 1: coalesced loads -> LDS slots
+    // Lane k of the line takes cells k, k+spl, ... (at most MMAX of them: the
     // host guarantees n <= MMAX*spl).  All loads of a chunk of up to 8 cells
     // are issued before any is used; cells past the line end are clamped to
-    // the line's first cell.
+    // the line's last cell.  spl is a multiple of the pad period, so cells
+    // spl apart are a fixed number of bytes apart in LDS.
+    const int ostep1 = spl * SLOT + ((spl >> pad) << 4);
+    const int ostep2 = (spl + (spl >> pad)) * 2 * ES;
+    const int ok1 = cell_off1(k, ES, pad);
+    const int ok2 = cell_off2(k, ES, pad);
     constexpr int CH = MMAX < 8 ? MMAX : 8;
-    const T* rowU = sU + q * LS;
 #pragma unroll
     for (int it0 = 0; it0 < MMAX; it0 += CH) {
-        if (it0 << spl_log2 >= n) break;
+        if ((it0 << spl_log2) >= n) break;
         T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            const int p = k + ((it0 + j) << spl_log2);
-            const unsigned pc = p < n ? (unsigned)p : 0u;
-            u[j] = P.U[base + pc];
-            va[j] = P.alpha[base + pc];
+            const unsigned p = (unsigned)(k + ((it0 + j) << spl_log2));
+            const unsigned bo = min(p, (unsigned)(n - 1)) * (unsigned)ES;
+            u[j] = ldg_off(gU, bo);
+            va[j] = ldg_off(gA, bo);
             if (!solve_only) {
-                u1m[j] = P.U[base1m + pc];
-                u1p[j] = P.U[base1p + pc];
-                vb1[j] = P.beta1[base + pc];
+                u1m[j] = ldg_off(gU1m, bo);
+                u1p[j] = ldg_off(gU1p, bo);
+                vb1[j] = ldg_off(gB1, bo);
                 if (NDIM == 3) {
-                    u2m[j] = P.U[base2m + pc];
-                    u2p[j] = P.U[base2p + pc];
-                    vb2[j] = P.beta2[base + pc];
+                    u2m[j] = ldg_off(gU2m, bo);
+                    u2p[j] = ldg_off(gU2p, bo);
+                    vb2[j] = ldg_off(gB2, bo);
                 }
             }
         }
+        if (line_ok) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int p = k + ((it0 + j) << spl_log2);
-            if (!line_ok || p >= n) continue;
-            const int li = q * LS + lds_pad<T>(p);
-            sU[li] = u[j];
-            sA[li] = va[j];
-            if (!solve_only) {
-                sS1[li] = cell_slope<T>(lim, u1m[j], u[j], u1p[j]);
-                sB1[li] = vb1[j];
-                if (NDIM == 3) {
-                    sS2[li] = cell_slope<T>(lim, u2m[j], u[j], u2p[j]);
-                    sB2[li] = vb2[j];
+            for (int j = 0; j < CH; ++j) {
+                const int p = k + ((it0 + j) << spl_log2);
+                if (p >= n) continue;
+                // solve-only sweeps store zero slopes and transverse
+                // coefficients: their transverse flux is then exactly zero
+                T s1 = T(0), b1 = T(0), s2 = T(0), b2 = T(0);
+                if (!solve_only) {
+                    s1 = cell_slope<T>(lim, u1m[j], u[j], u1p[j]);
+                    b1 = vb1[j];
+                    if (NDIM == 3) {
+                        s2 = cell_slope<T>(lim, u2m[j], u[j], u2p[j]);
+                        b2 = vb2[j];
+                    }
+                }
+                lds_put4<T>(row1 + ok1 + (it0 + j) * ostep1, s1, va[j], b1, u[j]);
+                if (NDIM == 3) lds_put2<T>(row2 + ok2 + (it0 + j) * ostep2, s2, b2);
+                if (p == 0) {  // the copy of cell 0 after the last cell
+                    lds_put4<T>(row1 + cell_off1(n, ES, pad), s1, va[j], b1, u[j]);
+                    if (NDIM == 3) lds_put2<T>(row2 + cell_off2(n, ES, pad), s2, b2);
                 }
             }
         }
@@ -132,52 +152,71 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
     __syncthreads();
 
     // ---------------- phase 2: per-lane segment elimination
+    // Segments are interleaved over the line's waves: lane l of wave w owns
+    // segment kseg = l * wpl + w.
+    const int wpl_log2 = spl_log2 - 6;
     const int nseg = 1 << P.nseg_log2;
-    const bool active = line_ok && k < nseg;
-    const int s0 = active ? (k * n) >> P.nseg_log2 : 0;
-    const int m = active ? (((k + 1) * n) >> P.nseg_log2) - s0 : 1;
+    const int kseg = ((k & 63) << wpl_log2) | (k >> 6);
+    const bool active = line_ok && kseg < nseg;
+    const int s0 = active ? (kseg * n) >> P.nseg_log2 : 0;
+    const int m = active ? (((kseg + 1) * n) >> P.nseg_log2) - s0 : 1;
+    const int os0 = cell_off1(s0, ES, pad);  // the segment's first slot
+
+    // The segment's slots: index 0 is the left neighbour cell s0-1 (mod n),
+    // index c+1 is cell s0+c, c = 0..MMAX (slots past the segment's right
+    // neighbour hold values that are ignored).  The segment's own slots are
+    // consecutive; the neighbours are found separately where a pad or the
+    // wrap may lie between (the copy of cell 0 covers the wrap on the
+    // right).  All reads are issued before any arithmetic.
+    T cs1[MMAX + 2], ca[MMAX + 2], cb1[MMAX + 2], cu[MMAX + 2], cs2[MMAX + 2], cb2[MMAX + 2];
+    {
+        int jl = s0 - 1;
+        if (jl < 0) jl += n;
+        const int jr = s0 + MMAX;  // right neighbour of an aligned segment (m == MMAX)
+        const int os2 = cell_off2(s0, ES, pad);
+        const int ol1 = cell_off1(jl, ES, pad), ol2 = cell_off2(jl, ES, pad);
+        const int or1 = Lo.aligned ? cell_off1(jr, ES, pad) : os0 + MMAX * SLOT;
+        const int or2 = Lo.aligned ? cell_off2(jr, ES, pad) : os2 + MMAX * 2 * ES;
+        lds_get4<T>(row1 + ol1, cs1[0], ca[0], cb1[0], cu[0]);
+        if (NDIM == 3) lds_get2<T>(row2 + ol2, cs2[0], cb2[0]);
+#pragma unroll
+        for (int c = 0; c < MMAX; ++c) {
+            lds_get4<T>(row1 + os0 + c * SLOT, cs1[c + 1], ca[c + 1], cb1[c + 1], cu[c + 1]);
+            if (NDIM == 3) lds_get2<T>(row2 + os2 + c * 2 * ES, cs2[c + 1], cb2[c + 1]);
+        }
+        lds_get4<T>(row1 + or1, cs1[MMAX + 1], ca[MMAX + 1], cb1[MMAX + 1], cu[MMAX + 1]);
+        if (NDIM == 3) lds_get2<T>(row2 + or2, cs2[MMAX + 1], cb2[MMAX + 1]);
+    }
 
     T av[MMAX], bv[MMAX], cv[MMAX], rv[MMAX];
     T gv[MMAX], hv[MMAX], wv[MMAX];
     T ae = T(0), be = T(1), ce = T(0), re = T(0);  // row of the segment's last cell
     {
-        // faces f = 0..m: the face between cells j0 = s0-1+f and j0+1 (mod n).
-        // The line system A x = U + F_{+} - F_{-} is solved in increment
-        // form, x = U + delta with A delta = Phi_{+} - Phi_{-} and the face
-        // flux Phi_f = F_f + alpha_f (U_{j0+1} - U_{j0}): algebraically the
-        // same solution, but the solve's rounding now scales with |delta|
-        // rather than |x|, and the right-hand side telescopes exactly.
+        // Face f = 0..MMAX lies between slots f and f+1.  The line system
+        // A x = U + F_{+} - F_{-} is solved in increment form,
+        // x = U + delta with A delta = Phi_{+} - Phi_{-} and the face flux
+        // Phi_f = F_f + alpha_f (U_right - U_left): algebraically the same
+        // solution, but the solve's rounding now scales with |delta| rather
+        // than |x|, and the right-hand side telescopes exactly.
         T phi_prev = T(0), alpha_prev = T(0);
-        const T* rowA = sA + q * LS;
-        const T* rowS1 = sS1 + q * LS;
-        const T* rowS2 = sS2 + q * LS;
-        const T* rowB1 = sB1 + q * LS;
-        const T* rowB2 = sB2 + q * LS;
 #pragma unroll
         for (int f = 0; f <= MMAX; ++f) {
-            if (f <= m && active) {
-                int j0 = s0 - 1 + f;
-                if (j0 < 0) j0 += n;
-                int j1 = j0 + 1;
-                if (j1 == n) j1 = 0;
-                const int i0 = lds_pad<T>(j0), i1 = lds_pad<T>(j1);
-                const T alpha = rowA[i0];
-                T phi = alpha * (rowU[i1] - rowU[i0]);
-                if (!solve_only) {
-                    phi += rowB1[i0] * limit2<T>(lim, rowS1[i1], rowS1[i0]);
-                    if (NDIM == 3) phi += rowB2[i0] * limit2<T>(lim, rowS2[i1], rowS2[i0]);
-                }
-                if (f > 0) {
-                    const int i = f - 1;  // cell s0 + i, faces (f-1, f)
-                    av[i] = -alpha_prev;
-                    cv[i] = -alpha;
-                    bv[i] = T(1) + alpha_prev + alpha;
-                    rv[i] = phi - phi_prev;
-                    if (f == m) { ae = av[i]; be = bv[i]; ce = cv[i]; re = rv[i]; }
-                }
-                alpha_prev = alpha;
-                phi_prev = phi;
+            T phi = ca[f] * (cu[f + 1] - cu[f]) + cb1[f] * limit2<T>(lim, cs1[f + 1], cs1[f]);
+            if (NDIM == 3) phi += cb2[f] * limit2<T>(lim, cs2[f + 1], cs2[f]);
+            if (f > 0) {
+                const int i = f - 1;  // cell s0 + i, faces (f-1, f)
+                av[i] = -alpha_prev;
+                cv[i] = -ca[f];
+                bv[i] = T(1) + alpha_prev + ca[f];
+                rv[i] = phi - phi_prev;
+                const bool last = f == m;
+                ae = last ? av[i] : ae;
+                be = last ? bv[i] : be;
+                ce = last ? cv[i] : ce;
+                re = last ? rv[i] : re;
             }
+            alpha_prev = ca[f];
+            phi_prev = phi;
         }
     }
     // interior elimination: x_i = g_i - h_i x_{i+1} + w_i X_left, i = 0..m-2
@@ -214,9 +253,9 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
     // kept normalised:  Ra X_{k-1} + X_k + Rc X_{k+1} = Rd.  It needs the
     // right neighbour's first-cell expression (Y, Uc, V).
     T Ra, Rc, Rd, XR, XL;
-    const int kr = (k + 1) & (nseg - 1);
     if (P.wpl == 1) {
-        // one wave per line: lane == segment; shuffles, no barrier
+        // one wave per line: lane == segment; shuffles only, no barrier
+        const int kr = (k + 1) & (nseg - 1);
         const T Yp = __shfl(Y, kr, 64), Up = __shfl(Uc, kr, 64), Vp = __shfl(V, kr, 64);
         if (active) {
             const T ib = fast_rcp<T>(be - ae * hp + ce * Up);
@@ -241,14 +280,28 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
         XR = Rd * fast_rcp<T>(T(1) + Ra + Rc);
         XL = __shfl(XR, (k - 1) & (nseg - 1), 64);
     } else {
-        // several waves per line: the same reduction through LDS
-        const int lb = q * seg_per_line;  // this line's slots
-        pA[tid] = Y;
-        pC[tid] = Uc;
-        pD[tid] = V;
+        // several waves per line.  Exchanges between waves go through two
+        // LDS buffers used alternately: a buffer is rewritten only after the
+        // barrier that follows the last reads of it, so each exchange costs
+        // one barrier.  Segment j's entry sits at the index of the thread
+        // that owns it, (j mod wpl)*64 + j/wpl: a wave's stores are
+        // contiguous.
+        const int lb = q * spl;
+        const int wmask = P.wpl - 1;
+        auto slot = [&](int b, int j) -> unsigned char* {
+            const int t = ((j & wmask) << 6) + (j >> wpl_log2);
+            if (b == 0) return smem + Lo.pcr0_at + (lb + t) * SLOT;
+            return Lo.pcr1_at < 0 ? row1 + cell_off1(t, ES, pad) : smem + Lo.pcr1_at + (lb + t) * SLOT;
+        };
+        int cur = 0;
+        // right neighbour's first-cell expression -> this segment's reduced
+        // row (buffer 0 has its own area: other waves may still be reading
+        // the slot rows)
+        lds_put3<T>(slot(0, kseg), Y, Uc, V);
         __syncthreads();
         {
-            const T Yp = pA[lb + kr], Up = pC[lb + kr], Vp = pD[lb + kr];
+            T Yp, Up, Vp, unused;
+            lds_get4<T>(slot(0, (kseg + 1) & (nseg - 1)), Yp, Up, Vp, unused);
             if (active) {
                 const T ib = fast_rcp<T>(be - ae * hp + ce * Up);
                 Ra = ae * wp * ib;
@@ -258,55 +311,60 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
                 Ra = T(0); Rc = T(0); Rd = T(0);
             }
         }
-        __syncthreads();
-        pA[tid] = Ra; pC[tid] = Rc; pD[tid] = Rd;
-        __syncthreads();
-        for (int s = 1; s < nseg; s <<= 1) {
-            T na = Ra, nc = Rc, nd = Rd;
-            if (k < nseg) {
-                const int km = lb + ((k - s) & (nseg - 1));
-                const int kp = lb + ((k + s) & (nseg - 1));
-                const T am = pA[km], cm = pC[km], dm = pD[km];
-                const T ap = pA[kp], cp = pC[kp], dp = pD[kp];
+        // strides below wpl: partners in other waves
+        for (int s = 1; s < nseg && s < P.wpl; s <<= 1) {
+            cur ^= 1;
+            lds_put3<T>(slot(cur, kseg), Ra, Rc, Rd);
+            __syncthreads();
+            if (active) {
+                T am, cm, dm, ap, cp, dp, unused;
+                lds_get4<T>(slot(cur, (kseg - s) & (nseg - 1)), am, cm, dm, unused);
+                lds_get4<T>(slot(cur, (kseg + s) & (nseg - 1)), ap, cp, dp, unused);
                 const T ib = fast_rcp<T>(T(1) - Ra * cm - Rc * ap);
-                na = -Ra * am * ib;
-                nc = -Rc * cp * ib;
-                nd = (Rd - Ra * dm - Rc * dp) * ib;
+                const T na = -Ra * am, nc = -Rc * cp, nd = Rd - Ra * dm - Rc * dp;
+                Ra = na * ib;
+                Rc = nc * ib;
+                Rd = nd * ib;
             }
-            __syncthreads();
-            Ra = na; Rc = nc; Rd = nd;
-            pA[tid] = Ra; pC[tid] = Rc; pD[tid] = Rd;
-            __syncthreads();
+        }
+        // strides wpl and up: partners are lanes of this wave, s / wpl apart
+        // (the line's nseg / wpl segments of this wave sit in its first lanes)
+        const int lane = k & 63;
+        for (int s = P.wpl; s < nseg; s <<= 1) {
+            const int nl = nseg >> wpl_log2, sl = s >> wpl_log2;
+            const int lm = (lane - sl) & (nl - 1), lp = (lane + sl) & (nl - 1);
+            const T am = __shfl(Ra, lm, 64), cm = __shfl(Rc, lm, 64), dm = __shfl(Rd, lm, 64);
+            const T ap = __shfl(Ra, lp, 64), cp = __shfl(Rc, lp, 64), dp = __shfl(Rd, lp, 64);
+            if (active) {
+                const T ib = fast_rcp<T>(T(1) - Ra * cm - Rc * ap);
+                const T na = -Ra * am, nc = -Rc * cp, nd = Rd - Ra * dm - Rc * dp;
+                Ra = na * ib;
+                Rc = nc * ib;
+                Rd = nd * ib;
+            }
         }
         XR = Rd * fast_rcp<T>(T(1) + Ra + Rc);
-        pA[tid] = XR;
+        cur ^= 1;
+        *reinterpret_cast<T*>(slot(cur, kseg)) = XR;
         __syncthreads();
-        XL = pA[lb + ((k - 1) & (nseg - 1))];
+        XL = *reinterpret_cast<const T*>(slot(cur, (kseg - 1) & (nseg - 1)));
     }
 
-    // ---------------- back substitution: x = U + delta, into LDS (reuse sU;
-    // each lane reads and overwrites only its own cells)
+    // ---------------- back substitution: x = U + delta, written over U in
+    // the lane's own slots (the U positions are never part of an exchange)
     lsum = 0.0;
     lmin = T(__builtin_huge_val());
     lmax = T(-__builtin_huge_val());
     if (active) {
-        T* rowX = sU + q * LS;
         T dn = XR;
-        {
-            const int ix = lds_pad<T>(s0 + m - 1);
-            const T x = rowX[ix] + XR;
-            rowX[ix] = x;
-            lsum = (double)x;
-            lmin = lmax = x;
-        }
 #pragma unroll
-        for (int i = MMAX - 2; i >= 0; --i) {
-            if (i <= m - 2) {
-                const T d = gv[i] - hv[i] * dn + wv[i] * XL;
+        for (int i = MMAX - 1; i >= 0; --i) {
+            if (i < m) {
+                T d = XR;
+                if (i < MMAX - 1 && i != m - 1) d = gv[i] - hv[i] * dn + wv[i] * XL;
                 dn = d;
-                const int ix = lds_pad<T>(s0 + i);
-                const T x = rowX[ix] + d;
-                rowX[ix] = x;
+                const T x = cu[i + 1] + d;
+                *reinterpret_cast<T*>(row1 + os0 + i * SLOT + UPOS) = x;
                 lsum += (double)x;
                 lmin = x < lmin ? x : lmin;
                 lmax = x > lmax ? x : lmax;
@@ -321,22 +379,28 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
         // lines of one position p, so each store covers lpw adjacent elements
         const int lpw_log2 = P.lpw_log2;
         const int ncell = lpw * n;
+        const int qq = tid & (lpw - 1);
+        const int p0 = tid >> lpw_log2;
+        const int pstep = nthreads >> lpw_log2;
+        T* ob = P.out + (l1_0 + l2 * P.so_t2);
+        const bool qq_ok = l1_0 + qq < P.nt1;
+        // pstep == spl: consecutive positions of a thread are ostep1 apart in LDS
+        const unsigned char* rq = smem + qq * Lo.row1 + UPOS + cell_off1(p0, ES, pad);
+        const unsigned o0 = (unsigned)(p0 * P.so_n + qq);
+        const unsigned ostep = (unsigned)(pstep * P.so_n);
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
-            const int idx = tid + it * nthreads;
-            if (idx >= ncell) break;
-            const int qq = idx & (lpw - 1), p = idx >> lpw_log2;
-            if (l1_0 + qq >= P.nt1) continue;
-            P.out[(unsigned)(p * P.so_n + (l1_0 + qq) + l2 * P.so_t2)] = sU[qq * LS + lds_pad<T>(p)];
+            if (tid + it * nthreads >= ncell) break;
+            if (qq_ok) ob[o0 + it * ostep] = *reinterpret_cast<const T*>(rq + it * ostep1);
         }
-    } else {
+    } else if (line_ok) {
         // line-contiguous output
-        const unsigned obase = line_ok ? (unsigned)(l1 * P.so_t1 + l2 * P.so_t2) : 0u;
+        T* ob = P.out + (l1 * P.so_t1 + l2 * P.so_t2);
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
             const int p = k + (it << spl_log2);
             if (p >= n) break;
-            if (line_ok) P.out[obase + (unsigned)(p * P.so_n)] = rowU[lds_pad<T>(p)];
+            ob[(unsigned)(p * P.so_n)] = *reinterpret_cast<const T*>(row1 + ok1 + it * ostep1 + UPOS);
         }
     }
 
