@@ -85,9 +85,23 @@ def run_si(g, p, steps, warmup, stream, torch):
     return ms / steps, e
 
 
-def kernel_durations(g, p, stream, torch, reps=200):
-    """Average duration of each sweep kernel, launched back to back on the
-    grid's stream between two events (T is not modified)."""
+def sweep_duration_in_loop(g, p, stream, torch, steps=400):
+    """Average duration of one sweep launch inside the step loop: steps whole
+    steps (x sweep then y sweep, each reading what the previous one wrote,
+    no energy) launched eagerly on the grid's stream between two events,
+    divided by the 2 * steps launches."""
+    g.set_graphs(False)
+    with torch.cuda.stream(stream):
+        g.step_semi_implicit(p.dt, 10)
+        ms = timed(lambda: g.step_semi_implicit(p.dt, steps), stream, torch)
+    g.set_graphs(True)
+    return ms / (2 * steps)
+
+
+def kernel_durations_repeated(g, p, stream, torch, reps=200):
+    """Average duration of each sweep kernel launched back to back on the
+    same input (its data stays cache-resident: an optimistic figure, shown
+    for comparison only; T is not modified)."""
     out = []
     with torch.cuda.stream(stream):
         g.bench_sweep(0, p.dt, 0)  # valid inputs for every sweep
@@ -302,10 +316,10 @@ def main():
             asd.bench_copy(src, dst, stream)
         stream.synchronize()
 
-    durs = kernel_durations(g, p, stream, torch)
-    dom = max(range(len(durs)), key=lambda a: durs[a])
+    d_loop = sweep_duration_in_loop(g, p, stream, torch)
+    durs = kernel_durations_repeated(g, p, stream, torch)
     bytes_per_launch = N * (4 + 4 + 8)  # T in, T out, (b_n, b_t) per cell, FP32
-    achieved = bytes_per_launch / (durs[dom] * 1e-3) / 1e9
+    achieved = bytes_per_launch / (d_loop * 1e-3) / 1e9
     step_gbs = N * 32 / (ms_step * 1e-3) / 1e9
 
     result = {
@@ -325,13 +339,14 @@ def main():
                    "chi_par": 1.0, "chi_perp": 0.0, "fused_fp64_energy": True, "sweep_configs": cfgs},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"sweep_kernel axis {'xy'[dom]}",
+            "kernel": "sweep_kernel (x and y sweeps, average launch inside the step loop)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(cfgs[dom]),
-            "kernel_ms": [round(d, 6) for d in durs],
+            "traffic": measured_traffic(cfgs),
+            "kernel_ms": round(d_loop, 6),
+            "kernel_ms_repeated_input": [round(d, 6) for d in durs],
             "step_algorithmic_GBs": round(step_gbs, 1),
             "kernel_digest": kernel_source_digest(),
         },

@@ -135,9 +135,9 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
         const void* in = ck[c - 1];
         for (int i = 0; i < k; ++i) {
             void* out = (i == k - 1) ? ck[c] : S[1];
-            rc = enqueue_sweep(g, 0, dt, in, tB, 0, no_reduce(), no_fold(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 0, dt, in, tB, 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
-            rc = enqueue_sweep(g, 1, dt, tB, out, 0, no_reduce(), no_fold(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 1, dt, tB, out, 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             in = out;
         }
@@ -155,23 +155,23 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
         const int len = std::min(k, nsteps - c * k);
         S[0] = ck[c];
         for (int i = 0; i < len; ++i) {
-            rc = enqueue_sweep(g, 0, dt, S[i], tB, 0, no_reduce(), no_fold(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 0, dt, S[i], tB, 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             rc = permute_2d<T>(g, tB, TS[i], false);
             if (rc) return rc;
-            rc = enqueue_sweep(g, 1, dt, tB, S[i + 1], 0, no_reduce(), no_fold(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 1, dt, tB, S[i + 1], 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
         }
         for (int i = len - 1; i >= 0; --i) {
             // y sweep: T* -> T^{n+1}
             rc = permute_2d<T>(g, lam, tB, true);
             if (rc) return rc;
-            rc = enqueue_sweep(g, 1, dt, tB, mu, 1, no_reduce(), no_fold(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 1, dt, tB, mu, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             rc = stencil<T>(g, 1, dt, mu, TS[i], S[i + 1], lam, gchi, W1, W2, GF);
             if (rc) return rc;
             // x sweep: T^n -> T*
-            rc = enqueue_sweep(g, 0, dt, lam, tB, 1, no_reduce(), no_fold(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 0, dt, lam, tB, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             rc = permute_2d<T>(g, tB, mu, false);
             if (rc) return rc;

@@ -109,7 +109,8 @@ struct asd_grid_s {
     double coef_dt = 0.0;
     void* tmp[2] = {nullptr, nullptr};
     char* coef[3][3] = {};     // [sweep][alpha, beta_t1, beta_t2], sweep's input layout
-    double* partials[2] = {nullptr, nullptr};  // per-block (sum, min, max) of reducing launches
+    double* ring = nullptr;    // reduction partials: ring_slots + 1 slots of max_blocks (sum, min, max)
+    int ring_slots = 2;
     int64_t max_blocks = 0;
     unsigned* flags = nullptr;
     double* stats = nullptr;
@@ -134,17 +135,18 @@ int check_fields(asd_grid g, bool need_T);
 int prepare(asd_grid g, double dt);  // dt > 0: face coefficients for dt
 int64_t layout_stride(const asd_grid g, int L, int a);
 asd::ReduceParams no_reduce();
-asd::FoldParams no_fold();
-asd::FoldParams make_fold(asd_grid g, const double* partials, int nblocks, double* energy_out, const double* e0);
+asd::FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, double* energy_out,
+                          const double* e0);
+inline double* ring_slot(asd_grid g, int i) { return g->ring + (size_t)i * g->max_blocks * 3; }
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
-                  const asd::ReduceParams& red, const asd::FoldParams& fold, const SweepCfg* cfg,
+                  const asd::ReduceParams& red, const SweepCfg* cfg,
                   int* nblocks_out);
 int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy);
 int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy);
 int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const asd::ReduceParams& red,
-                     const asd::FoldParams& fold, int* nblocks_out);
+                     int* nblocks_out);
 int enqueue_copy(asd_grid g, const void* src, void* dst);
-int enqueue_reduce(asd_grid g, const void* x, int buf, double* energy_out, const double* e0, asd::FoldParams* fold);
+int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0, asd::FoldParams* fold);
 int enqueue_fold(asd_grid g, const asd::FoldParams& f);
 // graph.cpp
 int run_si_graph(asd_grid g, double dt, int nsteps, double* energy);

@@ -10,17 +10,20 @@ namespace asd {
 
 // Fused FP64 reduction of a state, without any cross-block fence: the
 // producing launch writes one (sum, min, max) partial per block; a later
-// launch on the same stream (block 0 of the next kernel, or fold_kernel)
-// folds them in a fixed order, so the result is deterministic and the
-// kernel boundary makes the partials visible.
+// fold_kernel launch on the same stream folds them in a fixed order, so the
+// result is deterministic and the kernel boundary makes the partials
+// visible.  One fold launch can finish several reductions (consecutive
+// steps' partials, slot_stride doubles apart): block b folds reduction b.
 struct ReduceParams {
     double* partials;    // 3 doubles per block; nullptr disables the reduction
 };
 struct FoldParams {
     const double* partials;  // nullptr: nothing to fold
-    int nblocks;
-    double* energy_out;  // nullable: receives sum * dV
-    double* stats_out;   // nullable: {sum * dV, min, max}
+    int nblocks;         // producing blocks per reduction
+    int count;           // reductions folded by this launch
+    int slot_stride;     // doubles between the partials of consecutive reductions
+    double* energy_out;  // nullable: receives sum * dV, one value per reduction
+    double* stats_out;   // nullable: {sum * dV, min, max} of the last reduction
     unsigned* flags;     // nullable: ORed with status bits
     const double* e0;    // nullable: reference energy for the drift flag
     double dV;
@@ -48,7 +51,6 @@ struct SweepParams {
     int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)
     TileLayout lds;   // LDS layout of a tile (tile_layout)
     ReduceParams red;
-    FoldParams fold;
 };
 
 // Face coefficients of the sweep along axis d, written in that sweep's
@@ -97,7 +99,6 @@ struct ExplicitParams {
     int periodic;
     int limiter;
     ReduceParams red;
-    FoldParams fold;
 };
 template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out);
@@ -186,25 +187,25 @@ __device__ __forceinline__ void block_partials(double* partials, double s, M mn,
     }
 }
 
-// Fold f.nblocks partials in a fixed order (thread i takes i, i+nthreads,
-// ..., then a fixed tree); every thread of the calling block must call it.
+// Fold reduction b = blockIdx.x of f: its nblocks partials in a fixed order
+// (thread i takes i, i+nthreads, ..., then a fixed tree).
 __device__ __forceinline__ void fold_partials(const FoldParams& f) {
     __shared__ double fs[16], fmn[16], fmx[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
+    const int b = blockIdx.x;
+    const double* part = f.partials + (size_t)b * f.slot_stride;
     double ts = 0.0, tmn = __builtin_huge_val(), tmx = -__builtin_huge_val();
-    for (int b = threadIdx.x; b < f.nblocks; b += blockDim.x) {
-        const double* pp = f.partials + 3 * (size_t)b;
+    for (int i = threadIdx.x; i < f.nblocks; i += blockDim.x) {
+        const double* pp = part + 3 * (size_t)i;
         ts += pp[0];
         tmn = fmin(tmn, pp[1]);
         tmx = fmax(tmx, pp[2]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        ts += __shfl_xor(ts, off, 64);
-        tmn = fmin(tmn, __shfl_xor(tmn, off, 64));
-        tmx = fmax(tmx, __shfl_xor(tmx, off, 64));
-    }
-    if (lane == 0) { fs[wid] = ts; fmn[wid] = tmn; fmx[wid] = tmx; }
+    ts = wave_sum_lane63(ts);
+    tmn = wave_min_lane63<double>(tmn);
+    tmx = wave_max_lane63<double>(tmx);
+    if (lane == 63) { fs[wid] = ts; fmn[wid] = tmn; fmx[wid] = tmx; }
     __syncthreads();
     if (threadIdx.x == 0) {
         double S = 0.0, MN = fmn[0], MX = fmx[0];
@@ -214,8 +215,8 @@ __device__ __forceinline__ void fold_partials(const FoldParams& f) {
             MX = fmax(MX, fmx[w]);
         }
         const double E = S * f.dV;
-        if (f.energy_out) *f.energy_out = E;
-        if (f.stats_out) { f.stats_out[0] = E; f.stats_out[1] = MN; f.stats_out[2] = MX; }
+        if (f.energy_out) f.energy_out[b] = E;
+        if (f.stats_out && b == f.count - 1) { f.stats_out[0] = E; f.stats_out[1] = MN; f.stats_out[2] = MX; }
         if (f.flags) {
             unsigned fl = 0;
             if (!(E == E) || E - E != 0.0 || !(MN == MN) || !(MX == MX) || MX - MX != 0.0) fl |= 1u;
@@ -224,7 +225,7 @@ __device__ __forceinline__ void fold_partials(const FoldParams& f) {
                 const double e0 = *f.e0;
                 if (fabs(E - e0) > 1e-6 * fabs(e0)) fl |= 4u;
             }
-            if (fl) *f.flags |= fl;
+            if (fl) atomicOr(f.flags, fl);
         }
     }
 }

@@ -65,7 +65,7 @@ static void bench_buffers(asd_grid g, int axis, const void** in, void** out) {
 static int bench_prepare_inputs(asd_grid g, double dt) {
     for (int axis = 0; axis + 1 < g->d.ndim; ++axis) {
         const void* in = axis == 0 ? g->T : g->tmp[axis - 1];
-        int rc = enqueue_sweep(g, axis, dt, in, g->tmp[axis], 0, no_reduce(), no_fold(), nullptr, nullptr);
+        int rc = enqueue_sweep(g, axis, dt, in, g->tmp[axis], 0, no_reduce(), nullptr, nullptr);
         if (rc) return rc;
     }
     return ASD_OK;
@@ -85,7 +85,7 @@ extern "C" int asd_bench_sweep(asd_grid g, int32_t axis, double dt, int32_t reps
     void* out;
     bench_buffers(g, axis, &in, &out);
     for (int r = 0; r < reps; ++r) {
-        rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), no_fold(), nullptr, nullptr);
+        rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), nullptr, nullptr);
         if (rc) return rc;
     }
     return ASD_OK;
@@ -101,19 +101,32 @@ extern "C" int asd_bench_copy(const void* src, void* dst, size_t nbytes, void* s
 
 // ------------------------------------------------------------- autotuner
 
-static int time_cfg(asd_grid g, int axis, double dt, int reps, const SweepCfg& c, float* ms) {
-    const void* in;
-    void* out;
-    bench_buffers(g, axis, &in, &out);
+// Time reps whole steps (every sweep in order, each reading what the
+// previous one wrote, as in the step loop) with the launch shapes cfg[],
+// on the two scratch buffers: the first sweep reads T, T is never written.
+static int time_chain(asd_grid g, double dt, int reps, const SweepCfg* cfg, float* ms) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return asd_fail(ASD_EHIP, "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return asd_fail(ASD_EHIP, "event create");
     }
-    int rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), no_fold(), &c, nullptr);  // warm-up
+    const void* in = g->T;
+    int cur = 0;  // scratch buffer written next
+    auto chain = [&](int steps) {
+        int rc = ASD_OK;
+        for (int s = 0; s < steps && !rc; ++s)
+            for (int d = 0; d < g->d.ndim && !rc; ++d) {
+                void* out = g->tmp[cur];
+                rc = enqueue_sweep(g, d, dt, in, out, 0, no_reduce(), &cfg[d], nullptr);
+                in = out;
+                cur ^= 1;
+            }
+        return rc;
+    };
+    int rc = chain(1);  // warm-up
     if (!rc && hipEventRecord(e0, g->st) != hipSuccess) rc = asd_fail(ASD_EHIP, "event record");
-    for (int r = 0; !rc && r < reps; ++r) rc = enqueue_sweep(g, axis, dt, in, out, 0, no_reduce(), no_fold(), &c, nullptr);
+    if (!rc) rc = chain(reps);
     if (!rc && hipEventRecord(e1, g->st) != hipSuccess) rc = asd_fail(ASD_EHIP, "event record");
     if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = asd_fail(ASD_EHIP, "event sync");
     if (!rc && hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = asd_fail(ASD_EHIP, "elapsed");
@@ -122,6 +135,9 @@ static int time_cfg(asd_grid g, int axis, double dt, int reps, const SweepCfg& c
     return rc;
 }
 
+// Autotuner: for each sweep axis in turn, every admissible (waves per line,
+// lines per workgroup) shape is timed inside whole steps (the other axes at
+// their current shapes), and the fastest is kept; two passes.
 extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
     if (!(std::isfinite(dt) && dt > 0.0)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
@@ -131,28 +147,31 @@ extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
     rc = prepare(g, dt);
     if (rc) return rc;
     const bool chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) != 0;
-    rc = bench_prepare_inputs(g, dt);  // T itself is untouched
-    if (rc) return rc;
-    for (int axis = 0; axis < g->d.ndim; ++axis) {
-        SweepCfg best = g->cfg[axis];
-        float best_ms = 1e30f;
-        for (int wpl = 1; wpl <= 16; wpl *= 2) {
-            for (int lpw = 1; wpl * lpw <= 16; lpw *= 2) {
-                SweepCfg c;
-                if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c)) continue;
-                if (c.wpl != wpl || c.lpw != lpw) continue;
-                // sweeps whose blocks exceed the reduction scratch are fine here
-                float ms = 0.f;
-                rc = time_cfg(g, axis, dt, reps, c, &ms);
-                if (rc) return rc;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = c;
+    SweepCfg cur[3] = {g->cfg[0], g->cfg[1], g->cfg[2]};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int axis = 0; axis < g->d.ndim; ++axis) {
+            SweepCfg best = cur[axis];
+            float best_ms = 1e30f;
+            for (int wpl = 1; wpl <= 16; wpl *= 2) {
+                for (int lpw = 1; wpl * lpw <= 16; lpw *= 2) {
+                    SweepCfg c;
+                    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c)) continue;
+                    if (c.wpl != wpl || c.lpw != lpw) continue;
+                    SweepCfg trial[3] = {cur[0], cur[1], cur[2]};
+                    trial[axis] = c;
+                    float ms = 0.f;
+                    rc = time_chain(g, dt, reps, trial, &ms);
+                    if (rc) return rc;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = c;
+                    }
                 }
             }
+            cur[axis] = best;
         }
-        g->cfg[axis] = best;
     }
+    for (int a = 0; a < 3; ++a) g->cfg[a] = cur[a];
     g->graph_valid = false;
     return ASD_OK;
 }

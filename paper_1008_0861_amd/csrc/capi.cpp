@@ -92,7 +92,17 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct WsPlan {
     size_t tmp[2], coef[3][3], partials, small, total;
     int64_t max_blocks;
+    int ring_slots;
 };
+
+// Reduction partials: a ring of slots, one per step whose energy is still
+// to be folded (folded together every ring_slots steps), plus one slot for
+// standalone reductions.  The ring holds up to 32 slots within 4 MiB.
+static int ring_slots_for(int64_t max_blocks) {
+    const size_t slot = (size_t)max_blocks * 3 * sizeof(double);
+    const size_t k = ((size_t)4 << 20) / slot;
+    return (int)std::max<size_t>(2, std::min<size_t>(32, k));
+}
 
 static int64_t max_reduce_blocks(const asd_desc* d) {
     // sweeps at their smallest (one line per block), explicit tiles, reductions
@@ -117,8 +127,9 @@ static WsPlan plan_ws(const asd_desc* d) {
     for (int dd = 0; dd < d->ndim; ++dd)
         for (int q = 0; q < d->ndim; ++q) { p.coef[dd][q] = off; off += fb; }
     p.max_blocks = max_reduce_blocks(d);
-    p.partials = off;  // two buffers, alternated by successive producers
-    off += 2 * align256((size_t)p.max_blocks * 3 * sizeof(double));
+    p.ring_slots = ring_slots_for(p.max_blocks);
+    p.partials = off;
+    off += align256((size_t)(p.ring_slots + 1) * p.max_blocks * 3 * sizeof(double));
     p.small = off;
     off += 256;
     p.total = off;
@@ -156,8 +167,8 @@ extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes
     for (int i = 0; i < 2; ++i) g->tmp[i] = p.tmp[i] == (size_t)-1 ? nullptr : g->ws + p.tmp[i];
     for (int dd = 0; dd < 3; ++dd)
         for (int q = 0; q < 3; ++q) g->coef[dd][q] = p.coef[dd][q] == (size_t)-1 ? nullptr : g->ws + p.coef[dd][q];
-    g->partials[0] = (double*)(g->ws + p.partials);
-    g->partials[1] = (double*)(g->ws + p.partials + align256((size_t)p.max_blocks * 3 * sizeof(double)));
+    g->ring = (double*)(g->ws + p.partials);
+    g->ring_slots = p.ring_slots;
     g->max_blocks = p.max_blocks;
     char* sm = g->ws + p.small;
     g->flags = (unsigned*)sm;
@@ -299,15 +310,14 @@ ReduceParams no_reduce() {
     ReduceParams r{};
     return r;
 }
-FoldParams no_fold() {
-    FoldParams f{};
-    return f;
-}
 
-FoldParams make_fold(asd_grid g, const double* partials, int nblocks, double* energy_out, const double* e0) {
+FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, double* energy_out,
+                     const double* e0) {
     FoldParams f{};
     f.partials = partials;
     f.nblocks = nblocks;
+    f.count = count;
+    f.slot_stride = (int)(g->max_blocks * 3);
     f.energy_out = energy_out;
     f.stats_out = g->stats;
     f.flags = g->flags;
@@ -359,15 +369,13 @@ template int fill_sweep_params<double>(asd_grid, int, const void*, void*, int, c
 
 template <typename T>
 static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
-                           const ReduceParams& red, const FoldParams& fold, const SweepCfg* override_cfg,
-                           int* nblocks_out) {
+                           const ReduceParams& red, const SweepCfg* override_cfg, int* nblocks_out) {
     (void)dt;  // the coefficients were computed for dt by prepare()
     const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
     SweepParams<T> P;
     int rc = fill_sweep_params<T>(g, d, in, out, rhs_mode, c, &P);
     if (rc) return rc;
     P.red = red;
-    P.fold = fold;
     const int nb1 = (P.nt1 + c.lpw - 1) / c.lpw;
     const int64_t nblocks = (int64_t)nb1 * P.nt2;
     if (nblocks_out) *nblocks_out = (int)nblocks;
@@ -379,19 +387,19 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
 }
 
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode, const ReduceParams& red,
-                  const FoldParams& fold, const SweepCfg* cfg, int* nblocks_out) {
-    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, fold, cfg, nblocks_out)
-                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, fold, cfg, nblocks_out);
+                  const SweepCfg* cfg, int* nblocks_out) {
+    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out)
+                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out);
 }
 
-// Reduce a state into partial buffer `buf`; returns the fold that finishes it.
-int enqueue_reduce(asd_grid g, const void* x, int buf, double* energy_out, const double* e0, FoldParams* fold) {
+// Reduce a state into the standalone slot; returns the fold that finishes it.
+int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0, FoldParams* fold) {
     const int nb = reduce_num_blocks(g->N);
     ReduceParams r{};
-    r.partials = g->partials[buf];
+    r.partials = ring_slot(g, g->ring_slots);
     hipError_t e = g->es == 8 ? launch_reduce<double>((const double*)x, g->N, r, nb, g->st)
                               : launch_reduce<float>((const float*)x, g->N, r, nb, g->st);
-    *fold = make_fold(g, g->partials[buf], nb, energy_out, e0);
+    *fold = make_fold(g, r.partials, nb, 1, energy_out, e0);
     return hip_check(e, "reduce launch");
 }
 
@@ -421,36 +429,35 @@ static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
 }
 
 // The whole multi-step call as a kernel sequence (used eagerly and under
-// graph capture).  Energy: the initial state is reduced first; every step's
-// last kernel writes per-block partials that the next kernel (or a final
-// fold) folds into energy[s+1].
+// graph capture).  Energy: the initial state is reduced and folded first;
+// every step's last kernel writes per-block partials into the next ring
+// slot, and one fold launch turns a full ring (or the last steps) into
+// energy[s+1] for each of those steps, off the sweeps' critical path.
 int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy) {
     const int nd = g->d.ndim;
-    int buf = 0;
-    FoldParams pending = no_fold();
     int rc = ASD_OK;
     if (energy) {
-        rc = enqueue_reduce(g, g->T, buf, energy, nullptr, &pending);
-        buf ^= 1;
+        FoldParams f0;
+        rc = enqueue_reduce(g, g->T, energy, nullptr, &f0);
+        if (rc == ASD_OK) rc = enqueue_fold(g, f0);
     }
+    int used = 0;  // ring slots holding unfolded steps
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
         const void* in = g->T;
         for (int d = 0; d < nd && rc == ASD_OK; ++d) {
             void* out = (d == nd - 1) ? g->T : g->tmp[d];
             const bool produce = energy && d == nd - 1;
             ReduceParams red = no_reduce();
-            if (produce) red.partials = g->partials[buf];
+            if (produce) red.partials = ring_slot(g, used);
             int nb = 0;
-            rc = enqueue_sweep(g, d, dt, in, out, 0, red, d == 0 ? pending : no_fold(), nullptr, &nb);
-            if (d == 0) pending = no_fold();
-            if (produce) {
-                pending = make_fold(g, g->partials[buf], nb, energy + s + 1, energy);
-                buf ^= 1;
+            rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
+            if (rc == ASD_OK && produce && (++used == g->ring_slots || s == nsteps - 1)) {
+                rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, energy + s + 2 - used, energy));
+                used = 0;
             }
             in = out;
         }
     }
-    if (rc == ASD_OK) rc = enqueue_fold(g, pending);
     return rc;
 }
 
@@ -470,7 +477,7 @@ extern "C" int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, dou
 
 template <typename T>
 static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red,
-                              const FoldParams& fold, int* nblocks_out) {
+                              int* nblocks_out) {
     ExplicitParams<T> P{};
     P.U = (const T*)src;
     P.out = (T*)dst;
@@ -492,14 +499,13 @@ static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst,
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
     P.limiter = g->d.limiter;
     P.red = red;
-    P.fold = fold;
     return hip_check(launch_explicit<T>(P, g->d.ndim, g->st, nblocks_out), "explicit launch");
 }
 
 int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const ReduceParams& red,
-                     const FoldParams& fold, int* nblocks_out) {
-    return g->es == 8 ? enqueue_explicit_t<double>(g, dt, src, dst, red, fold, nblocks_out)
-                      : enqueue_explicit_t<float>(g, dt, src, dst, red, fold, nblocks_out);
+                     int* nblocks_out) {
+    return g->es == 8 ? enqueue_explicit_t<double>(g, dt, src, dst, red, nblocks_out)
+                      : enqueue_explicit_t<float>(g, dt, src, dst, red, nblocks_out);
 }
 
 int enqueue_copy(asd_grid g, const void* src, void* dst) {
@@ -508,27 +514,29 @@ int enqueue_copy(asd_grid g, const void* src, void* dst) {
     return hip_check(e, "copy launch");
 }
 
-// Explicit steps ping-pong between T and tmp[0]; an odd count ends with a copy.
+// Explicit steps ping-pong between T and tmp[0]; an odd count ends with a
+// copy.  Energy partials go through the ring as in the semi-implicit loop.
 int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy) {
-    int buf = 0;
-    FoldParams pending = no_fold();
     int rc = ASD_OK;
     if (energy) {
-        rc = enqueue_reduce(g, g->T, buf, energy, nullptr, &pending);
-        buf ^= 1;
+        FoldParams f0;
+        rc = enqueue_reduce(g, g->T, energy, nullptr, &f0);
+        if (rc == ASD_OK) rc = enqueue_fold(g, f0);
     }
     void* a = g->T;
     void* b = g->tmp[0];
+    int used = 0;
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
         ReduceParams red = no_reduce();
-        if (energy) red.partials = g->partials[buf];
+        if (energy) red.partials = ring_slot(g, used);
         int nb = 0;
-        rc = enqueue_explicit(g, dt, a, b, red, pending, &nb);
-        pending = energy ? make_fold(g, g->partials[buf], nb, energy + s + 1, energy) : no_fold();
-        buf ^= 1;
+        rc = enqueue_explicit(g, dt, a, b, red, &nb);
+        if (rc == ASD_OK && energy && (++used == g->ring_slots || s == nsteps - 1)) {
+            rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, energy + s + 2 - used, energy));
+            used = 0;
+        }
         std::swap(a, b);
     }
-    if (rc == ASD_OK) rc = enqueue_fold(g, pending);
     if (rc == ASD_OK && a != g->T) rc = enqueue_copy(g, a, g->T);
     return rc;
 }
@@ -554,7 +562,7 @@ extern "C" int asd_status(asd_grid g, uint32_t* flags, double* stats) {
     rc = prepare(g, 0.0);
     if (rc) return rc;
     FoldParams f;
-    rc = enqueue_reduce(g, g->T, 0, nullptr, nullptr, &f);
+    rc = enqueue_reduce(g, g->T, nullptr, nullptr, &f);
     if (rc) return rc;
     rc = enqueue_fold(g, f);
     if (rc) return rc;

@@ -133,7 +133,6 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
         lmin = lmax = (double)un;
     }
     if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
-    if (P.fold.partials && blockIdx.x == 0) fold_partials(P.fold);
 }
 
 int explicit_num_blocks(int ndim, const int n[3]) {

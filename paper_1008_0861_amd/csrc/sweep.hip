@@ -20,10 +20,8 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
     double lsum;
     T lmin, lmax;
     sweep_tile<T, NDIM, MMAX, LIMC>(P, l1_0, l2, smem_raw, lsum, lmin, lmax);
-    // FP64 energy / min / max partials, and the fold of the previous
-    // launch's partials (block 0 only)
+    // FP64 energy / min / max partials (folded by a later launch)
     if (P.red.partials) block_partials<T>(P.red.partials, lsum, lmin, lmax);
-    if (P.fold.partials && blockIdx.x == 0) fold_partials(P.fold);
 }
 
 // Van Leer (the default limiter) gets its own straight-line instantiation;

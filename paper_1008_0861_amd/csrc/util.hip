@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(256) reduce_kernel(const T* __restrict__ x, in
 __global__ void __launch_bounds__(256) fold_kernel(FoldParams f) { fold_partials(f); }
 
 hipError_t launch_fold(const FoldParams& f, hipStream_t st) {
-    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(256), 0, st, f);
+    if (f.count < 1) return hipSuccess;
+    hipLaunchKernelGGL(fold_kernel, dim3(f.count), dim3(256), 0, st, f);
     return hipGetLastError();
 }
 

@@ -113,6 +113,22 @@ def test_explicit_parity(prec, shape, bc):
     assert max_rel_err(got, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("scheme", ["si", "ex"])
+@pytest.mark.parametrize("graphs", [True, False])
+def test_energy_series_across_fold_batches(scheme, graphs):
+    """75 steps: the per-step energies are folded in batches of up to 32
+    steps (two full batches and a remainder); every entry matches the
+    oracle's FP64 energy, on the captured-graph and on the eager path."""
+    p = _random_problem((48, 40), "insulating", seed=5, nsteps=75)
+    dt = p.dt if scheme == "si" else synth.ncfl_dt(1.0, p.h, 1.0)
+    _, eref = oracle_run(p, "f64", scheme=scheme, dt=dt, energy=True)
+    gp = GpuProblem(p, "f64")
+    gp.g.set_graphs(graphs)
+    _, e = gp.run(scheme=scheme, dt=dt, energy=True)
+    assert e.shape == (76,)
+    np.testing.assert_allclose(e, eref, rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("limiter", ["vanleer", "minmod", "mc", "linear"])
 def test_explicit_limiters_per_cell_chi(limiter):
     p = _random_problem((50, 70), "insulating", limiter=limiter, per_cell_chi=True, chi_perp=1e-3, seed=2)
