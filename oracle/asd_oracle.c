@@ -19,6 +19,10 @@
  *     T* = (1 + dt D_xx)^-1 (1 - dt D_xy [- dt D_xz]) T^n        (Eq. xup)
  *     T^{n+1} = (1 + dt D_yy)^-1 (1 - dt D_yx [- dt D_yz]) T*   (Eq. yup)
  *     [3-D: then the z sweep with transverse terms from T**]
+ *   The 4-step variant (section 2.1, Eq. 4step) keeps the explicit
+ *   transverse term of each direction at dt and applies its implicit normal
+ *   operator twice at dt/2:
+ *     T* = (1 + dt D_xx/2)^-2 (1 - dt D_xy) T^n,  then y (and z) alike.
  *   The "normal" term of each sweep is implicit (one tridiagonal system per
  *   grid line); the "transverse" term is explicit and uses the limited face
  *   difference of section 2 (van Leer by default, Eq. vanLeer; minmod and MC
@@ -207,24 +211,25 @@ static double face_chi(const orc_grid *g, long c0, long c1)
 
 /*
  * Coefficients of the face between cells p0 and p1 = p0 + e_d:
- *   alpha      = dt * D_dd / h_d^2              (normal, implicit part)
- *   beta[t]    = dt * D_dt / (h_d h_t), t != d  (transverse, explicit part)
- * with b at the face the arithmetic mean of the two cells.
+ *   alpha      = dt_n * D_dd / h_d^2              (normal, implicit part)
+ *   beta[t]    = dt_t * D_dt / (h_d h_t), t != d  (transverse, explicit part)
+ * with b at the face the arithmetic mean of the two cells (dt_n = dt_t = dt
+ * in the 2-step scheme).
  */
 static void face_coefficients(const orc_grid *g, int d, const long p0[3], const long p1[3],
-                              double dt, double *alpha, double beta[3])
+                              double dt_n, double dt_t, double *alpha, double beta[3])
 {
     const long c0 = cell_index(g, p0), c1 = cell_index(g, p1);
     double bf[3] = {0.0, 0.0, 0.0};
     for (int q = 0; q < g->ndim; ++q) bf[q] = 0.5 * (g->b[q][c0] + g->b[q][c1]);
     const double chif = face_chi(g, c0, c1);
     const double dnn = g->chi_perp + (chif - g->chi_perp) * bf[d] * bf[d];
-    *alpha = dt * dnn / (g->h[d] * g->h[d]);
+    *alpha = dt_n * dnn / (g->h[d] * g->h[d]);
     for (int t = 0; t < 3; ++t) beta[t] = 0.0;
     for (int t = 0; t < g->ndim; ++t) {
         if (t == d) continue;
         const double dnt = (chif - g->chi_perp) * bf[d] * bf[t];
-        beta[t] = dt * dnt / (g->h[d] * g->h[t]);
+        beta[t] = dt_t * dnt / (g->h[d] * g->h[t]);
     }
 }
 
@@ -251,7 +256,7 @@ static double transverse_difference(const orc_grid *g, const double *U, const lo
  * Wall faces (insulating, k = -1 or k = n-1) carry no flux.
  */
 static void line_face(const orc_grid *g, const double *U, int d, const long base[3], long k,
-                      double dt, double *alpha, double *flux)
+                      double dt_n, double dt_t, double *alpha, double *flux)
 {
     const long n = g->n[d];
     *alpha = 0.0;
@@ -267,7 +272,7 @@ static void line_face(const orc_grid *g, const double *U, int d, const long base
     p0[d] = k0;
     p1[d] = k1;
     double beta[3];
-    face_coefficients(g, d, p0, p1, dt, alpha, beta);
+    face_coefficients(g, d, p0, p1, dt_n, dt_t, alpha, beta);
     double f = 0.0;
     for (int t = 0; t < g->ndim; ++t) {
         if (t == d) continue;
@@ -281,11 +286,11 @@ static void line_face(const orc_grid *g, const double *U, int d, const long base
 /* ------------------------------------------------------------------ */
 
 /*
- * out = (1 + dt D_dd)^-1 (U + transverse fluxes of U) along axis d.
- * Every coefficient is computed from the complete input U before out is
- * written (out must not alias U).
+ * out = (1 + dt_n D_dd)^-1 (U + transverse fluxes of U at dt_t) along axis
+ * d.  Every coefficient is computed from the complete input U before out is
+ * written (out must not alias U).  dt_t = 0 is a pure implicit solve.
  */
-int orc_sweep(const orc_grid *g, int d, double dt, const double *U, double *out)
+int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double *U, double *out)
 {
     const long n = g->n[d];
     if (g->bc == ORC_BC_PERIODIC && n < 3) return -1;
@@ -310,7 +315,7 @@ int orc_sweep(const orc_grid *g, int d, double dt, const double *U, double *out)
             base[ax2] = l2;
             /* faces k + 1/2 for k = -1 .. n-1; entry k+1 holds face k+1/2 */
             for (long k = -1; k < n; ++k)
-                line_face(g, U, d, base, k, dt, &alpha[k + 1], &flux[k + 1]);
+                line_face(g, U, d, base, k, dt_n, dt_t, &alpha[k + 1], &flux[k + 1]);
             for (long i = 0; i < n; ++i) {
                 const double am = alpha[i];     /* face i - 1/2 */
                 const double ap = alpha[i + 1]; /* face i + 1/2 */
@@ -340,6 +345,12 @@ int orc_sweep(const orc_grid *g, int d, double dt, const double *U, double *out)
     free(r);
     free(x);
     return rc;
+}
+
+/* One sweep of the 2-step scheme (Eq. xup / yup): normal and transverse at dt. */
+int orc_sweep(const orc_grid *g, int d, double dt, const double *U, double *out)
+{
+    return orc_sweep2(g, d, dt, dt, U, out);
 }
 
 static long cell_count(const orc_grid *g) { return g->n[0] * g->n[1] * g->n[2]; }
@@ -391,6 +402,31 @@ int orc_step_si(const orc_grid *g, double dt, int nsteps, double *T, double *ene
 }
 
 /*
+ * nsteps steps of the 4-step scheme (Eq. 4step), in place on T.  For each
+ * axis in the order x, y (, z): the transverse term at dt from the current
+ * state with the first normal solve at dt/2, then a second normal solve at
+ * dt/2 of that result.
+ */
+int orc_step_si4(const orc_grid *g, double dt, int nsteps, double *T, double *energy)
+{
+    if (!grid_ok(g) || nsteps < 0 || !T) return -1;
+    const long N = cell_count(g);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!tmp) return -1;
+    int rc = 0;
+    if (energy) energy[0] = orc_energy(g, T);
+    for (int s = 0; rc == 0 && s < nsteps; ++s) {
+        for (int d = 0; rc == 0 && d < g->ndim; ++d) {
+            rc = orc_sweep2(g, d, 0.5 * dt, dt, T, tmp);
+            if (rc == 0) rc = orc_sweep2(g, d, 0.5 * dt, 0.0, tmp, T);
+        }
+        if (energy) energy[s + 1] = orc_energy(g, T);
+    }
+    free(tmp);
+    return rc;
+}
+
+/*
  * Explicit limited step (the CFL-bound baseline):
  *   T^{n+1}_c = T^n_c + sum_d [ alpha_{c+1/2}(T_{c+e} - T_c) - alpha_{c-1/2}(T_c - T_{c-e})
  *                               + F_{c+1/2} - F_{c-1/2} ],
@@ -416,8 +452,8 @@ int orc_step_explicit(const orc_grid *g, double dt, int nsteps, double *T, doubl
                     base[ax2] = l2;
                     for (long i = 0; i < n; ++i) {
                         double am, fm, ap, fp;
-                        line_face(g, T, d, base, i - 1, dt, &am, &fm);
-                        line_face(g, T, d, base, i, dt, &ap, &fp);
+                        line_face(g, T, d, base, i - 1, dt, dt, &am, &fm);
+                        line_face(g, T, d, base, i, dt, dt, &ap, &fp);
                         long p[3] = {base[0], base[1], base[2]};
                         p[d] = i;
                         const double tc = T[cell_index(g, p)];

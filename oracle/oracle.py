@@ -51,7 +51,9 @@ def lib():
             f.argtypes = [ctypes.c_long, _dp, _dp, _dp, _dp, _dp]
         L.orc_sweep.restype = ctypes.c_int
         L.orc_sweep.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_int, ctypes.c_double, _dp, _dp]
-        for name in ("orc_step_si", "orc_step_explicit"):
+        L.orc_sweep2.restype = ctypes.c_int
+        L.orc_sweep2.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        for name in ("orc_step_si", "orc_step_si4", "orc_step_explicit"):
             f = getattr(L, name)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_double, ctypes.c_int, _dp, _dp]
@@ -129,12 +131,24 @@ class OracleGrid:
             raise RuntimeError(f"orc_sweep failed ({rc})")
         return out
 
-    def step_si(self, T, dt, nsteps=1, energy=False):
-        """nsteps semi-implicit steps; returns T (and energies if asked)."""
+    def sweep2(self, axis, dt_normal, dt_transverse, U):
+        """Sweep with the normal (implicit) part at dt_normal and the
+        transverse (explicit) part at dt_transverse (0: a pure solve)."""
+        U = self._check(U)
+        out = np.empty_like(U)
+        rc = lib().orc_sweep2(ctypes.byref(self._s), int(axis), float(dt_normal), float(dt_transverse),
+                              _ptr(U), _ptr(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_sweep2 failed ({rc})")
+        return out
+
+    def step_si(self, T, dt, nsteps=1, energy=False, four_step=False):
+        """nsteps semi-implicit steps (the 2-step scheme, or the 4-step
+        scheme of Eq. 4step); returns T (and energies if asked)."""
         T = self._check(T).copy()
         e = np.empty(nsteps + 1) if energy else None
-        rc = lib().orc_step_si(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
-                               _ptr(e) if e is not None else _dp())
+        f = lib().orc_step_si4 if four_step else lib().orc_step_si
+        rc = f(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T), _ptr(e) if e is not None else _dp())
         if rc != 0:
             raise RuntimeError(f"orc_step_si failed ({rc})")
         return (T, e) if energy else T
