@@ -71,6 +71,7 @@ extern "C" {
 /* asd_desc.flags */
 #define ASD_FLAG_PER_CELL_CHI 1u   /* chi is a per-cell field, harmonic mean at faces */
 #define ASD_FLAG_ALLOW_UNSTABLE 2u /* skip the EUNSTABLE check */
+#define ASD_FLAG_FOUR_STEP 4u      /* asd_step_semi_implicit takes the 4-step scheme (section 2.1, Eq. 4step) */
 
 /* asd_status flags */
 #define ASD_STATUS_NONFINITE 1u    /* NaN/Inf in energy or T */
@@ -123,7 +124,13 @@ int asd_set_field(asd_grid g, int32_t field, void *dev_ptr, int64_t nelem, int32
  * dev_energy: NULL or a device FP64 array of nsteps+1 entries that receives
  * sum T dV of the initial state and after every step (FP64 accumulation).
  * EUNSTABLE: 3-D with chi dt / min h^2 > 8.25 (section 2.1) unless
- * ASD_FLAG_ALLOW_UNSTABLE.  nsteps may be 0. */
+ * ASD_FLAG_ALLOW_UNSTABLE.  nsteps may be 0.
+ * With ASD_FLAG_FOUR_STEP the step is the 4-step scheme (section 2.1,
+ * Eq. 4step): per direction the transverse term at dt and the normal
+ * operator applied twice at dt/2,
+ *     T* = (1 + dt D_xx/2)^-2 (1 - dt D_xy [- dt D_xz]) T^n, then y (then z),
+ * two tridiagonal solves per line and direction; unconditionally stable in
+ * 3-D as well (no EUNSTABLE). */
 int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, double *dev_energy);
 
 /* nsteps steps of the explicit limited scheme (forward Euler of the same

@@ -25,6 +25,7 @@ F32, F64 = 0, 1
 FIELD = {"T": 0, "bx": 1, "by": 2, "bz": 3, "chi": 4}
 FLAG_PER_CELL_CHI = 1
 FLAG_ALLOW_UNSTABLE = 2
+FLAG_FOUR_STEP = 4
 STATUS_NONFINITE, STATUS_NEG_T, STATUS_ENERGY_DRIFT = 1, 2, 4
 
 # every entry point of include/asd.h and include/asd_extra.h
@@ -125,7 +126,7 @@ def _dtype_code(dtype):
 
 
 def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0, chi_perp=0.0,
-              per_cell_chi=False, allow_unstable=False):
+              per_cell_chi=False, allow_unstable=False, four_step=False):
     """Build an asd_desc.  shape is (ny, nx) or (nz, ny, nx), h is (hx, hy[, hz])."""
     d = Desc()
     d.ndim = len(shape)
@@ -138,7 +139,8 @@ def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", c
         d.h[q] = float(h[q]) if q < len(h) else 1.0
     d.chi_par = float(chi_par)
     d.chi_perp = float(chi_perp)
-    d.flags = (FLAG_PER_CELL_CHI if per_cell_chi else 0) | (FLAG_ALLOW_UNSTABLE if allow_unstable else 0)
+    d.flags = ((FLAG_PER_CELL_CHI if per_cell_chi else 0) | (FLAG_ALLOW_UNSTABLE if allow_unstable else 0)
+               | (FLAG_FOUR_STEP if four_step else 0))
     d.reserved = 0
     return d
 
@@ -163,11 +165,13 @@ class Grid:
     """
 
     def __init__(self, shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0,
-                 chi_perp=0.0, per_cell_chi=False, allow_unstable=False, device="cuda", stream=None):
+                 chi_perp=0.0, per_cell_chi=False, allow_unstable=False, device="cuda", stream=None,
+                 four_step=False):
         self.shape = tuple(int(s) for s in shape)
         self.dtype = dtype
         self.device = torch.device(device)
-        self.desc = make_desc(self.shape, h, bc, dtype, limiter, chi_par, chi_perp, per_cell_chi, allow_unstable)
+        self.desc = make_desc(self.shape, h, bc, dtype, limiter, chi_par, chi_perp, per_cell_chi, allow_unstable,
+                              four_step)
         nbytes = workspace_bytes(self.desc)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream_ptr, self.stream = _stream_handle(stream)

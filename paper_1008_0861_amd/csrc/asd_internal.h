@@ -128,6 +128,12 @@ struct asd_grid_s {
 // capi.cpp
 int asd_fail(int code, const char* fmt, ...);
 int validate_desc(const asd_desc* d);
+// Sweep mode bits (the rhs_mode argument of fill_sweep_params / enqueue_sweep).
+enum : int {
+    SWEEP_SOLVE_ONLY = 1,   // right-hand side = U (no transverse term)
+    SWEEP_KEEP_LAYOUT = 2,  // output in the input layout
+};
+
 template <typename T>
 int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode, const SweepCfg& c,
                       asd::SweepParams<T>* P);

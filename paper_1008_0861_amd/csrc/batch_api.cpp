@@ -63,6 +63,8 @@ static int check_descs(const asd_desc* descs, int32_t nprob) {
             return asd_fail(ASD_EINVAL, "problem %d: bc, dtype and limiter must match problem 0", p);
         if (descs[p].flags & ASD_FLAG_PER_CELL_CHI)
             return asd_fail(ASD_EUNSUPPORTED, "batched problems take a constant chi_par");
+        if (descs[p].flags & ASD_FLAG_FOUR_STEP)
+            return asd_fail(ASD_EUNSUPPORTED, "batched problems take the 2-step scheme");
     }
     return ASD_OK;
 }

@@ -58,7 +58,7 @@ int validate_desc(const asd_desc* d) {
     if (d->limiter < ASD_LIM_VANLEER || d->limiter > ASD_LIM_LINEAR)
         return asd_fail(ASD_EINVAL, "bad limiter %d", d->limiter);
     if (d->reserved != 0) return asd_fail(ASD_EINVAL, "reserved must be 0");
-    if (d->flags & ~(ASD_FLAG_PER_CELL_CHI | ASD_FLAG_ALLOW_UNSTABLE))
+    if (d->flags & ~(ASD_FLAG_PER_CELL_CHI | ASD_FLAG_ALLOW_UNSTABLE | ASD_FLAG_FOUR_STEP))
         return asd_fail(ASD_EINVAL, "unknown flags 0x%x", d->flags);
     const int64_t nmin = d->bc == ASD_BC_PERIODIC ? 3 : 2;
     for (int q = 0; q < d->ndim; ++q) {
@@ -285,7 +285,9 @@ static int do_prepare(asd_grid g, double dt) {
             const double hd = g->d.h[G.d];
             const double h1 = g->d.h[G.t1];
             const double h2 = nd == 3 ? g->d.h[G.t2] : 1.0;
-            C.cnn = dt / (hd * hd);
+            // the 4-step scheme solves its normal operator at dt/2 (Eq. 4step)
+            const double dt_n = (g->d.flags & ASD_FLAG_FOUR_STEP) ? 0.5 * dt : dt;
+            C.cnn = dt_n / (hd * hd);
             C.ct1 = dt / (hd * h1);
             C.ct2 = dt / (hd * h2);
             C.chi_par = g->d.chi_par;
@@ -347,9 +349,12 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.si_n = (int)layout_stride(g, G.Lin, G.d);
     P.si_t1 = (int)layout_stride(g, G.Lin, G.t1);
     P.si_t2 = (int)layout_stride(g, G.Lin, G.t2);
-    P.so_n = (int)layout_stride(g, G.Lout, G.d);
-    P.so_t1 = (int)layout_stride(g, G.Lout, G.t1);
-    P.so_t2 = (int)layout_stride(g, G.Lout, G.t2);
+    // SWEEP_KEEP_LAYOUT: the output keeps the input layout (line-contiguous
+    // stores) instead of the sweep's transposed output layout
+    const int Lout = (rhs_mode & SWEEP_KEEP_LAYOUT) ? G.Lin : G.Lout;
+    P.so_n = (int)layout_stride(g, Lout, G.d);
+    P.so_t1 = (int)layout_stride(g, Lout, G.t1);
+    P.so_t2 = (int)layout_stride(g, Lout, G.t2);
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
     P.limiter = g->d.limiter;
     P.wpl = c.wpl;
@@ -358,7 +363,7 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.nseg_log2 = ilog2(c.P);
     P.spl_log2 = ilog2(64 * c.wpl);
     P.lpw_log2 = ilog2(c.lpw);
-    P.rhs_mode = rhs_mode;
+    P.rhs_mode = rhs_mode & SWEEP_SOLVE_ONLY;
     P.lds = tile_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), c.wpl, P.nseg_log2, c.mmax);
     if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
     *Pout = P;
@@ -422,7 +427,7 @@ static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
             return asd_fail(ASD_EUNSTABLE, "explicit dt above the 2-D limit (chi dt sum 1/h^2 = %g > 1)", chi * dt * sum_inv);
         if (g->d.ndim == 3 && chi * dt / hmin2 > 0.444)
             return asd_fail(ASD_EUNSTABLE, "explicit dt above the 3-D limit (chi dt/h^2 = %g > 0.444)", chi * dt / hmin2);
-    } else if (g->d.ndim == 3 && chi * dt / hmin2 > 8.25) {
+    } else if (g->d.ndim == 3 && !(g->d.flags & ASD_FLAG_FOUR_STEP) && chi * dt / hmin2 > 8.25) {
         return asd_fail(ASD_EUNSTABLE, "3-D semi-implicit dt above the limit (chi dt/h^2 = %g > 8.25)", chi * dt / hmin2);
     }
     return ASD_OK;
@@ -435,6 +440,7 @@ static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
 // energy[s+1] for each of those steps, off the sweeps' critical path.
 int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy) {
     const int nd = g->d.ndim;
+    const bool four = (g->d.flags & ASD_FLAG_FOUR_STEP) != 0;
     int rc = ASD_OK;
     if (energy) {
         FoldParams f0;
@@ -445,12 +451,23 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy) {
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
         const void* in = g->T;
         for (int d = 0; d < nd && rc == ASD_OK; ++d) {
-            void* out = (d == nd - 1) ? g->T : g->tmp[d];
             const bool produce = energy && d == nd - 1;
             ReduceParams red = no_reduce();
             if (produce) red.partials = ring_slot(g, used);
             int nb = 0;
-            rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
+            void* out;
+            if (!four) {
+                out = (d == nd - 1) ? g->T : g->tmp[d];
+                rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
+            } else {
+                // 4-step: transverse term at dt with the first half-step
+                // solve, written in the input layout, then the second
+                // half-step solve into the next sweep's layout.  States:
+                // T -> tmp0 (-> T in 3-D) -> T.
+                out = d == 0 ? g->tmp[0] : g->T;
+                rc = enqueue_sweep(g, d, dt, in, g->tmp[1], SWEEP_KEEP_LAYOUT, no_reduce(), nullptr, nullptr);
+                if (rc == ASD_OK) rc = enqueue_sweep(g, d, dt, g->tmp[1], out, SWEEP_SOLVE_ONLY, red, nullptr, &nb);
+            }
             if (rc == ASD_OK && produce && (++used == g->ring_slots || s == nsteps - 1)) {
                 rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, energy + s + 2 - used, energy));
                 used = 0;

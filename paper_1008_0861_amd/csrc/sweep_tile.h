@@ -41,41 +41,47 @@
 
 namespace asd {
 
-// One tile: lines l1_0 .. l1_0+lpw-1 (transverse coordinate t2 = l2) of the
-// sweep described by P.  Every thread of the block must call it; it ends
-// with a barrier so that consecutive tiles may reuse the LDS.  Returns the
-// thread's FP64 sum and min / max of the values it wrote.
-template <typename T, int NDIM, int MMAX, int LIMC>
-__device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem,
-                                           double& lsum, T& lmin, T& lmax) {
-    constexpr int ES = (int)sizeof(T);
-    constexpr int SLOT = 4 * ES;  // bytes of a cell slot / exchange slot
-    constexpr int UPOS = 3 * ES;  // byte offset of U inside a cell slot
-    const int n = P.n;
-    const int lpw = P.lpw;
-    const int spl = 64 * P.wpl;  // lanes per line
-    const int tid = threadIdx.x;
-    const int nthreads = blockDim.x;
-    const bool solve_only = P.rhs_mode != 0;
-    const bool periodic = P.periodic != 0;
-    const int lim = LIMC >= 0 ? LIMC : P.limiter;
-    const TileLayout& Lo = P.lds;
-    const int pad = Lo.pad;
+// Per-thread view of one tile: lines l1_0 .. l1_0+lpw-1 (transverse
+// coordinate t2 = l2) of the sweep described by P, staged in the LDS buffer
+// starting at buf.  Threads [q*spl, (q+1)*spl) own line q of the tile
+// (spl = 64*wpl lanes: a power of two, so line membership is a shift,
+// uniform over a wave).
+template <typename T>
+struct TileCtx {
+    int l1_0, l2, q, k, l1;
+    int line_ok;
+    unsigned char* buf;
+    unsigned char* row1;
+    unsigned char* row2;
+    const T *gU, *gU1m, *gU1p, *gU2m, *gU2p, *gA, *gB1, *gB2;
+    int ok1, ok2;        // LDS offsets of the thread's first cell (k) in its line's rows
+    int ostep1, ostep2;  // LDS bytes between cells spl apart
+};
 
-    // Threads [q*spl, (q+1)*spl) own line q of the tile (spl = 64*wpl lanes;
-    // a power of two, so line membership is a shift, uniform over a wave).
-    const int spl_log2 = P.spl_log2;
-    const int q = __builtin_amdgcn_readfirstlane(tid >> spl_log2);
-    const int k = tid & (spl - 1);
-    const int l1 = l1_0 + q;
-    const bool line_ok = l1 < P.nt1;
-    unsigned char* row1 = smem + q * Lo.row1;
-    unsigned char* row2 = smem + Lo.rows2_at + q * Lo.row2;
+template <typename T, int NDIM>
+__device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0, int l2, unsigned char* buf) {
+    constexpr int ES = (int)sizeof(T);
+    const TileLayout& Lo = P.lds;
+    const int spl = 64 * P.wpl;
+    const int pad = Lo.pad;
+    const bool periodic = P.periodic != 0;
+    const bool solve_only = P.rhs_mode != 0;
+    TileCtx<T> c;
+    c.l1_0 = l1_0;
+    c.l2 = l2;
+    c.q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> P.spl_log2);
+    c.k = threadIdx.x & (spl - 1);
+    c.l1 = l1_0 + c.q;
+    c.line_ok = c.l1 < P.nt1;
+    c.buf = buf;
+    c.row1 = buf + c.q * Lo.row1;
+    c.row2 = buf + Lo.rows2_at + c.q * Lo.row2;
     // element offsets of this line and of its transverse neighbours (the
     // boundary rule applies once per line, not per cell)
-    const unsigned base = line_ok ? (unsigned)(l1 * P.si_t1 + l2 * P.si_t2) : 0u;
+    const int l1 = c.l1;
+    const unsigned base = c.line_ok ? (unsigned)(l1 * P.si_t1 + l2 * P.si_t2) : 0u;
     unsigned base1m = base, base1p = base, base2m = base, base2p = base;
-    if (line_ok && !solve_only) {
+    if (c.line_ok && !solve_only) {
         base1m = base + (int)(nb_coord(l1 - 1, P.nt1, periodic) - l1) * P.si_t1;
         base1p = base + (int)(nb_coord(l1 + 1, P.nt1, periodic) - l1) * P.si_t1;
         if (NDIM == 3) {
@@ -83,73 +89,115 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
             base2p = base + (int)(nb_coord(l2 + 1, P.nt2, periodic) - l2) * P.si_t2;
         }
     }
-    const T* gU = P.U + base;
-    const T* gU1m = P.U + base1m;
-    const T* gU1p = P.U + base1p;
-    const T* gU2m = P.U + base2m;
-    const T* gU2p = P.U + base2p;
-    const T* gA = P.alpha + base;
-    const T* gB1 = P.beta1 + base;
-    const T* gB2 = NDIM == 3 ? P.beta2 + base : nullptr;
+    c.gU = P.U + base;
+    c.gU1m = P.U + base1m;
+    c.gU1p = P.U + base1p;
+    c.gU2m = P.U + base2m;
+    c.gU2p = P.U + base2p;
+    c.gA = P.alpha + base;
+    c.gB1 = P.beta1 + base;
+    c.gB2 = NDIM == 3 ? P.beta2 + base : nullptr;
+    // spl is a multiple of the pad period, so cells spl apart are a fixed
+    // number of bytes apart in LDS
+    c.ok1 = cell_off1(c.k, ES, pad);
+    c.ok2 = cell_off2(c.k, ES, pad);
+    c.ostep1 = spl * 4 * ES + ((spl >> pad) << 4);
+    c.ostep2 = (spl + (spl >> pad)) * 2 * ES;
+    return c;
+}
 
-    // ---------------- phase 1: coalesced loads -> LDS slots
-    // Lane k of the line takes cells k, k+spl, ... (at most MMAX of them: the
-    // host guarantees n <= MMAX*spl).  All loads of a chunk of up to 8 cells
-    // are issued before any is used; cells past the line end are clamped to
-    // the line's last cell.  spl is a multiple of the pad period, so cells
-    // spl apart are a fixed number of bytes apart in LDS.
-    const int ostep1 = spl * SLOT + ((spl >> pad) << 4);
-    const int ostep2 = (spl + (spl >> pad)) * 2 * ES;
-    const int ok1 = cell_off1(k, ES, pad);
-    const int ok2 = cell_off2(k, ES, pad);
-    constexpr int CH = MMAX < 8 ? MMAX : 8;
+// Global data of CH of the thread's cells (k + (it0 + j) spl, j < CH).
+template <typename T, int NDIM, int CH>
+struct CellLoads {
+    T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH];
+};
+
+// ---------------- phase 1a: coalesced loads of a chunk of cells.  Lane k of
+// the line takes cells k, k+spl, ... (at most MMAX of them: the host
+// guarantees n <= MMAX*spl).  All loads are issued before any is used; cells
+// past the line end are clamped to the line's last cell.
+template <typename T, int NDIM, int CH>
+__device__ __forceinline__ void load_cells(const SweepParams<T>& P, const TileCtx<T>& c, int it0,
+                                           CellLoads<T, NDIM, CH>& r) {
+    constexpr int ES = (int)sizeof(T);
+    const bool solve_only = P.rhs_mode != 0;
 #pragma unroll
-    for (int it0 = 0; it0 < MMAX; it0 += CH) {
-        if ((it0 << spl_log2) >= n) break;
-        T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const unsigned p = (unsigned)(k + ((it0 + j) << spl_log2));
-            const unsigned bo = min(p, (unsigned)(n - 1)) * (unsigned)ES;
-            u[j] = ldg_off(gU, bo);
-            va[j] = ldg_off(gA, bo);
-            if (!solve_only) {
-                u1m[j] = ldg_off(gU1m, bo);
-                u1p[j] = ldg_off(gU1p, bo);
-                vb1[j] = ldg_off(gB1, bo);
-                if (NDIM == 3) {
-                    u2m[j] = ldg_off(gU2m, bo);
-                    u2p[j] = ldg_off(gU2p, bo);
-                    vb2[j] = ldg_off(gB2, bo);
-                }
-            }
-        }
-        if (line_ok) {
-#pragma unroll
-            for (int j = 0; j < CH; ++j) {
-                const int p = k + ((it0 + j) << spl_log2);
-                if (p >= n) continue;
-                // solve-only sweeps store zero slopes and transverse
-                // coefficients: their transverse flux is then exactly zero
-                T s1 = T(0), b1 = T(0), s2 = T(0), b2 = T(0);
-                if (!solve_only) {
-                    s1 = cell_slope<T>(lim, u1m[j], u[j], u1p[j]);
-                    b1 = vb1[j];
-                    if (NDIM == 3) {
-                        s2 = cell_slope<T>(lim, u2m[j], u[j], u2p[j]);
-                        b2 = vb2[j];
-                    }
-                }
-                lds_put4<T>(row1 + ok1 + (it0 + j) * ostep1, s1, va[j], b1, u[j]);
-                if (NDIM == 3) lds_put2<T>(row2 + ok2 + (it0 + j) * ostep2, s2, b2);
-                if (p == 0) {  // the copy of cell 0 after the last cell
-                    lds_put4<T>(row1 + cell_off1(n, ES, pad), s1, va[j], b1, u[j]);
-                    if (NDIM == 3) lds_put2<T>(row2 + cell_off2(n, ES, pad), s2, b2);
-                }
+    for (int j = 0; j < CH; ++j) {
+        const unsigned p = (unsigned)(c.k + ((it0 + j) << P.spl_log2));
+        const unsigned bo = min(p, (unsigned)(P.n - 1)) * (unsigned)ES;
+        r.u[j] = ldg_off(c.gU, bo);
+        r.va[j] = ldg_off(c.gA, bo);
+        if (!solve_only) {
+            r.u1m[j] = ldg_off(c.gU1m, bo);
+            r.u1p[j] = ldg_off(c.gU1p, bo);
+            r.vb1[j] = ldg_off(c.gB1, bo);
+            if (NDIM == 3) {
+                r.u2m[j] = ldg_off(c.gU2m, bo);
+                r.u2p[j] = ldg_off(c.gU2p, bo);
+                r.vb2[j] = ldg_off(c.gB2, bo);
             }
         }
     }
-    __syncthreads();
+}
+
+// ---------------- phase 1b: limited transverse slopes, packed into the
+// cells' LDS slots (and the copy of cell 0 after the last cell).
+template <typename T, int NDIM, int CH, int LIMC>
+__device__ __forceinline__ void stage_cells(const SweepParams<T>& P, const TileCtx<T>& c, int it0,
+                                            const CellLoads<T, NDIM, CH>& r) {
+    constexpr int ES = (int)sizeof(T);
+    const bool solve_only = P.rhs_mode != 0;
+    const int lim = LIMC >= 0 ? LIMC : P.limiter;
+    const int n = P.n;
+    if (!c.line_ok) return;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int p = c.k + ((it0 + j) << P.spl_log2);
+        if (p >= n) continue;
+        // solve-only sweeps store zero slopes and transverse coefficients:
+        // their transverse flux is then exactly zero
+        T s1 = T(0), b1 = T(0), s2 = T(0), b2 = T(0);
+        if (!solve_only) {
+            s1 = cell_slope<T>(lim, r.u1m[j], r.u[j], r.u1p[j]);
+            b1 = r.vb1[j];
+            if (NDIM == 3) {
+                s2 = cell_slope<T>(lim, r.u2m[j], r.u[j], r.u2p[j]);
+                b2 = r.vb2[j];
+            }
+        }
+        lds_put4<T>(c.row1 + c.ok1 + (it0 + j) * c.ostep1, s1, r.va[j], b1, r.u[j]);
+        if (NDIM == 3) lds_put2<T>(c.row2 + c.ok2 + (it0 + j) * c.ostep2, s2, b2);
+        if (p == 0) {  // the copy of cell 0 after the last cell
+            lds_put4<T>(c.row1 + cell_off1(n, ES, P.lds.pad), s1, r.va[j], b1, r.u[j]);
+            if (NDIM == 3) lds_put2<T>(c.row2 + cell_off2(n, ES, P.lds.pad), s2, b2);
+        }
+    }
+}
+
+// Phases 2-3 of a staged tile: every thread of the block must call it; it
+// ends with a barrier so that the tile's LDS buffer may be refilled.
+// smem: the block's LDS base (exchange buffers).  Returns the thread's FP64
+// sum and min / max of the values it wrote.
+template <typename T, int NDIM, int MMAX, int LIMC>
+__device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileCtx<T>& ctx, unsigned char* smem,
+                                            double& lsum, T& lmin, T& lmax) {
+    constexpr int ES = (int)sizeof(T);
+    constexpr int SLOT = 4 * ES;  // bytes of a cell slot / exchange slot
+    constexpr int UPOS = 3 * ES;  // byte offset of U inside a cell slot
+    const int n = P.n;
+    const int lpw = P.lpw;
+    const int spl = 64 * P.wpl;
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int lim = LIMC >= 0 ? LIMC : P.limiter;
+    const TileLayout& Lo = P.lds;
+    const int pad = Lo.pad;
+    const int spl_log2 = P.spl_log2;
+    const int q = ctx.q, k = ctx.k, l1 = ctx.l1, l1_0 = ctx.l1_0, l2 = ctx.l2;
+    const bool line_ok = ctx.line_ok;
+    unsigned char* row1 = ctx.row1;
+    unsigned char* row2 = ctx.row2;
+    const int ok1 = ctx.ok1, ostep1 = ctx.ostep1;
 
     // ---------------- phase 2: per-lane segment elimination
     // Segments are interleaved over the line's waves: lane l of wave w owns
@@ -385,7 +433,7 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
         T* ob = P.out + (l1_0 + l2 * P.so_t2);
         const bool qq_ok = l1_0 + qq < P.nt1;
         // pstep == spl: consecutive positions of a thread are ostep1 apart in LDS
-        const unsigned char* rq = smem + qq * Lo.row1 + UPOS + cell_off1(p0, ES, pad);
+        const unsigned char* rq = ctx.buf + qq * Lo.row1 + UPOS + cell_off1(p0, ES, pad);
         const unsigned o0 = (unsigned)(p0 * P.so_n + qq);
         const unsigned ostep = (unsigned)(pstep * P.so_n);
 #pragma unroll
@@ -405,6 +453,24 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
     }
 
     __syncthreads();  // the LDS may be refilled by the next tile
+}
+
+// One whole tile (phases 1-3) in LDS buffer 0, loading in chunks of up to 8
+// cells per thread.
+template <typename T, int NDIM, int MMAX, int LIMC>
+__device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem,
+                                           double& lsum, T& lmin, T& lmax) {
+    const TileCtx<T> c = tile_ctx<T, NDIM>(P, l1_0, l2, smem);
+    constexpr int CH = MMAX < 8 ? MMAX : 8;
+#pragma unroll
+    for (int it0 = 0; it0 < MMAX; it0 += CH) {
+        if ((it0 << P.spl_log2) >= P.n) break;
+        CellLoads<T, NDIM, CH> r;
+        load_cells<T, NDIM, CH>(P, c, it0, r);
+        stage_cells<T, NDIM, CH, LIMC>(P, c, it0, r);
+    }
+    __syncthreads();
+    solve_store<T, NDIM, MMAX, LIMC>(P, c, smem, lsum, lmin, lmax);
 }
 
 }  // namespace asd
