@@ -56,10 +56,10 @@ def timed(fn, stream, torch):
     return e0.elapsed_time(e1)
 
 
-def make_grid(p, prec, stream, torch, asd):
+def make_grid(p, prec, stream, torch, asd, four_step=False):
     dt = torch.float32 if prec == "f32" else torch.float64
     with torch.cuda.stream(stream):
-        g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=dt, chi_par=p.chi_par, chi_perp=p.chi_perp)
+        g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=dt, chi_par=p.chi_par, chi_perp=p.chi_perp, four_step=four_step)
         b = [torch.from_numpy(c).to(dt).cuda() for c in p.b]
         T = torch.from_numpy(p.T0).to(dt).cuda()
         g.set_b(*b)
@@ -230,12 +230,14 @@ def batched(stream, torch, asd, nsteps=100):
     return out
 
 
-def three_d(stream, torch, asd, nsteps=50):
-    """256^3 periodic curl-field problem, FP32 state, ncfl = 10 (chi dt/h^2 =
-    2.5), FP64 energy every step: Gcell-updates/s and energy drift."""
+def three_d(stream, torch, asd, nsteps=50, ncfl=10.0, four_step=False):
+    """256^3 periodic curl-field problem, FP32 state, FP64 energy every step:
+    Gcell-updates/s and energy drift.  Default: the 2-step scheme at ncfl =
+    10 (chi dt/h^2 = 2.5); the 4-step scheme also runs beyond the 2-step
+    scheme's 3-D limit of 8.25."""
     import synth
-    p = synth.curl3d_problem(256, nsteps=nsteps)
-    g = make_grid(p, "f32", stream, torch, asd)
+    p = synth.curl3d_problem(256, nsteps=nsteps, ncfl=ncfl)
+    g = make_grid(p, "f32", stream, torch, asd, four_step=four_step)
     ebuf = torch.empty(nsteps + 1, dtype=torch.float64, device="cuda")
     with torch.cuda.stream(stream):
         g.tune(p.dt, reps=5)
@@ -245,9 +247,12 @@ def three_d(stream, torch, asd, nsteps=50):
         stream.synchronize()
         ms = timed(lambda: g.step_semi_implicit(p.dt, nsteps, out=ebuf), stream, torch)
     e = ebuf.cpu().numpy()
-    return {"cells": p.ncells, "steps": nsteps, "ms_per_step": round(ms / nsteps, 4),
+    return {"scheme": "4-step" if four_step else "2-step", "chi_dt_over_h2": round(ncfl / 4.0, 3),
+            "cells": p.ncells, "steps": nsteps, "ms_per_step": round(ms / nsteps, 4),
             "Gcells": round(p.ncells * nsteps / (ms * 1e-3) / 1e9, 3),
-            "algorithmic_GBs": round(p.ncells * 60 * nsteps / (ms * 1e-3) / 1e9, 1),
+            # per cell-update: 3 sweeps x (4 B in + 4 B out + 12 B coefficients); the
+            # 4-step scheme adds per direction a solve (4 B in + 4 B alpha + 4 B out)
+            "algorithmic_GBs": round(p.ncells * (96 if four_step else 60) * nsteps / (ms * 1e-3) / 1e9, 1),
             "energy_rel_drift": float(abs(e[-1] - e[0]) / abs(e[0]))}
 
 
@@ -372,6 +377,7 @@ def main():
         result["speedup_vs_explicit"] = matched_l1_speedup(stream, torch, asd)
         extra["batched"] = batched(stream, torch, asd)
         extra["curl3d_256"] = three_d(stream, torch, asd)
+        extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
         result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()

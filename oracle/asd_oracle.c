@@ -378,11 +378,17 @@ static int grid_ok(const orc_grid *g)
 }
 
 /*
- * nsteps semi-implicit steps, in place on T.  Sweep order x, y (, z) every
- * step; each sweep takes its transverse differences from its own input
- * (T^n, then T*, then T**).  energy (nullable) receives nsteps+1 values.
+ * nsteps semi-implicit steps, in place on T.  Each sweep takes its
+ * transverse differences from its own input (T^n, then T*, then T**).
+ * flags: ORC_SI_FOUR_STEP for the 4-step scheme (Eq. 4step: per direction
+ * the transverse term at dt with a normal solve at dt/2, then a second
+ * normal solve at dt/2); ORC_SI_REVERSE for the reverse sweep order
+ * (y then x, or z, y, x), which section 2 allows in place of x then y.
+ * energy (nullable) receives nsteps+1 values.
  */
-int orc_step_si(const orc_grid *g, double dt, int nsteps, double *T, double *energy)
+#define ORC_SI_FOUR_STEP 1
+#define ORC_SI_REVERSE 2
+int orc_step_si_ex(const orc_grid *g, double dt, int nsteps, double *T, double *energy, int flags)
 {
     if (!grid_ok(g) || nsteps < 0 || !T) return -1;
     const long N = cell_count(g);
@@ -391,9 +397,15 @@ int orc_step_si(const orc_grid *g, double dt, int nsteps, double *T, double *ene
     int rc = 0;
     if (energy) energy[0] = orc_energy(g, T);
     for (int s = 0; rc == 0 && s < nsteps; ++s) {
-        for (int d = 0; rc == 0 && d < g->ndim; ++d) {
-            rc = orc_sweep(g, d, dt, T, tmp);
-            if (rc == 0) memcpy(T, tmp, sizeof(double) * (size_t)N);
+        for (int i = 0; rc == 0 && i < g->ndim; ++i) {
+            const int d = (flags & ORC_SI_REVERSE) ? g->ndim - 1 - i : i;
+            if (flags & ORC_SI_FOUR_STEP) {
+                rc = orc_sweep2(g, d, 0.5 * dt, dt, T, tmp);
+                if (rc == 0) rc = orc_sweep2(g, d, 0.5 * dt, 0.0, tmp, T);
+            } else {
+                rc = orc_sweep(g, d, dt, T, tmp);
+                if (rc == 0) memcpy(T, tmp, sizeof(double) * (size_t)N);
+            }
         }
         if (energy) energy[s + 1] = orc_energy(g, T);
     }
@@ -401,29 +413,16 @@ int orc_step_si(const orc_grid *g, double dt, int nsteps, double *T, double *ene
     return rc;
 }
 
-/*
- * nsteps steps of the 4-step scheme (Eq. 4step), in place on T.  For each
- * axis in the order x, y (, z): the transverse term at dt from the current
- * state with the first normal solve at dt/2, then a second normal solve at
- * dt/2 of that result.
- */
+/* The 2-step scheme in the order x, y (, z) (Eqs. xup / yup, op_2step). */
+int orc_step_si(const orc_grid *g, double dt, int nsteps, double *T, double *energy)
+{
+    return orc_step_si_ex(g, dt, nsteps, T, energy, 0);
+}
+
+/* The 4-step scheme (Eq. 4step) in the order x, y (, z). */
 int orc_step_si4(const orc_grid *g, double dt, int nsteps, double *T, double *energy)
 {
-    if (!grid_ok(g) || nsteps < 0 || !T) return -1;
-    const long N = cell_count(g);
-    double *tmp = (double *)malloc(sizeof(double) * (size_t)N);
-    if (!tmp) return -1;
-    int rc = 0;
-    if (energy) energy[0] = orc_energy(g, T);
-    for (int s = 0; rc == 0 && s < nsteps; ++s) {
-        for (int d = 0; rc == 0 && d < g->ndim; ++d) {
-            rc = orc_sweep2(g, d, 0.5 * dt, dt, T, tmp);
-            if (rc == 0) rc = orc_sweep2(g, d, 0.5 * dt, 0.0, tmp, T);
-        }
-        if (energy) energy[s + 1] = orc_energy(g, T);
-    }
-    free(tmp);
-    return rc;
+    return orc_step_si_ex(g, dt, nsteps, T, energy, ORC_SI_FOUR_STEP);
 }
 
 /*

@@ -57,6 +57,8 @@ def lib():
             f = getattr(L, name)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.orc_step_si_ex.restype = ctypes.c_int
+        L.orc_step_si_ex.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_int]
         L.orc_energy.restype = ctypes.c_double
         L.orc_energy.argtypes = [ctypes.POINTER(_OrcGrid), _dp]
         L.orc_dt_from_ncfl.restype = ctypes.c_double
@@ -142,13 +144,15 @@ class OracleGrid:
             raise RuntimeError(f"orc_sweep2 failed ({rc})")
         return out
 
-    def step_si(self, T, dt, nsteps=1, energy=False, four_step=False):
+    def step_si(self, T, dt, nsteps=1, energy=False, four_step=False, reverse=False):
         """nsteps semi-implicit steps (the 2-step scheme, or the 4-step
-        scheme of Eq. 4step); returns T (and energies if asked)."""
+        scheme of Eq. 4step; sweeps x, y (, z), or in reverse order);
+        returns T (and energies if asked)."""
         T = self._check(T).copy()
         e = np.empty(nsteps + 1) if energy else None
-        f = lib().orc_step_si4 if four_step else lib().orc_step_si
-        rc = f(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T), _ptr(e) if e is not None else _dp())
+        flags = (1 if four_step else 0) | (2 if reverse else 0)
+        rc = lib().orc_step_si_ex(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
+                                  _ptr(e) if e is not None else _dp(), flags)
         if rc != 0:
             raise RuntimeError(f"orc_step_si failed ({rc})")
         return (T, e) if energy else T
