@@ -72,6 +72,7 @@ extern "C" {
 #define ASD_FLAG_PER_CELL_CHI 1u   /* chi is a per-cell field, harmonic mean at faces */
 #define ASD_FLAG_ALLOW_UNSTABLE 2u /* skip the EUNSTABLE check */
 #define ASD_FLAG_FOUR_STEP 4u      /* asd_step_semi_implicit takes the 4-step scheme (section 2.1, Eq. 4step) */
+#define ASD_FLAG_REVERSE_ORDER 8u  /* 2-D: sweep y then x every step (section 2 allows either order) */
 
 /* asd_status flags */
 #define ASD_STATUS_NONFINITE 1u    /* NaN/Inf in energy or T */

@@ -51,6 +51,19 @@ int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t *best_mode, int32_t
 
 int asd_batch_destroy(asd_batch b);
 
+/* ------------------------------------------------------------ diagnostics
+ * nsteps steps of the semi-implicit scheme (ASD_SCHEME_SEMI_IMPLICIT, as
+ * asd_step_semi_implicit, with the grid's ASD_FLAG_FOUR_STEP and
+ * ASD_FLAG_REVERSE_ORDER) or of the explicit limited scheme
+ * (ASD_SCHEME_EXPLICIT, as asd_step_explicit_limited), recording for the
+ * initial state and after every step the FP64 energy sum T dV and the
+ * minimum and maximum of T (the monotonicity diagnostics of section 3.1).
+ * dev_series: device FP64 array of 3 (nsteps+1) entries, (E, Tmin, Tmax)
+ * per state.  Errors as for the two step calls. */
+#define ASD_SCHEME_SEMI_IMPLICIT 0
+#define ASD_SCHEME_EXPLICIT 1
+int asd_step_series(asd_grid g, int32_t scheme, double dt, int32_t nsteps, double *dev_series);
+
 /* ----------------------------------------------------------------- tuning
  * Launch shape of the sweep along `axis`: waves per line (wpl), lines per
  * work-group (lpw), segments per line (P) and per-lane capacity (mmax). */

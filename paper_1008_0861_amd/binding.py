@@ -26,12 +26,13 @@ FIELD = {"T": 0, "bx": 1, "by": 2, "bz": 3, "chi": 4}
 FLAG_PER_CELL_CHI = 1
 FLAG_ALLOW_UNSTABLE = 2
 FLAG_FOUR_STEP = 4
+FLAG_REVERSE_ORDER = 8
 STATUS_NONFINITE, STATUS_NEG_T, STATUS_ENERGY_DRIFT = 1, 2, 4
 
 # every entry point of include/asd.h and include/asd_extra.h
 EXPORTED = [
     "asd_last_error", "asd_workspace_bytes", "asd_init_grid", "asd_set_field",
-    "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_adjoint_workspace_bytes",
+    "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_step_series", "asd_adjoint_workspace_bytes",
     "asd_adjoint_step", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
     "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune",
@@ -81,6 +82,7 @@ def lib():
             "asd_set_field": (ctypes.c_int, [vp, i32, vp, i64, i32]),
             "asd_step_semi_implicit": (ctypes.c_int, [vp, dbl, i32, vp]),
             "asd_step_explicit_limited": (ctypes.c_int, [vp, dbl, i32, vp]),
+            "asd_step_series": (ctypes.c_int, [vp, i32, dbl, i32, vp]),
             "asd_adjoint_workspace_bytes": (ctypes.c_int, [vp, i32, i32, P(sz)]),
             "asd_adjoint_step": (ctypes.c_int, [vp, dbl, i32, i32, vp, vp, vp, vp, vp, sz]),
             "asd_status": (ctypes.c_int, [vp, P(ctypes.c_uint32), P(dbl)]),
@@ -126,7 +128,7 @@ def _dtype_code(dtype):
 
 
 def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0, chi_perp=0.0,
-              per_cell_chi=False, allow_unstable=False, four_step=False):
+              per_cell_chi=False, allow_unstable=False, four_step=False, reverse_order=False):
     """Build an asd_desc.  shape is (ny, nx) or (nz, ny, nx), h is (hx, hy[, hz])."""
     d = Desc()
     d.ndim = len(shape)
@@ -140,7 +142,7 @@ def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", c
     d.chi_par = float(chi_par)
     d.chi_perp = float(chi_perp)
     d.flags = ((FLAG_PER_CELL_CHI if per_cell_chi else 0) | (FLAG_ALLOW_UNSTABLE if allow_unstable else 0)
-               | (FLAG_FOUR_STEP if four_step else 0))
+               | (FLAG_FOUR_STEP if four_step else 0) | (FLAG_REVERSE_ORDER if reverse_order else 0))
     d.reserved = 0
     return d
 
@@ -166,12 +168,12 @@ class Grid:
 
     def __init__(self, shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0,
                  chi_perp=0.0, per_cell_chi=False, allow_unstable=False, device="cuda", stream=None,
-                 four_step=False):
+                 four_step=False, reverse_order=False):
         self.shape = tuple(int(s) for s in shape)
         self.dtype = dtype
         self.device = torch.device(device)
         self.desc = make_desc(self.shape, h, bc, dtype, limiter, chi_par, chi_perp, per_cell_chi, allow_unstable,
-                              four_step)
+                              four_step, reverse_order)
         nbytes = workspace_bytes(self.desc)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream_ptr, self.stream = _stream_handle(stream)
@@ -231,6 +233,15 @@ class Grid:
         check(lib().asd_step_explicit_limited(self.handle, float(dt), int(nsteps),
                                               ctypes.c_void_p(e.data_ptr()) if e is not None else None))
         return e
+
+    def step_series(self, scheme, dt, nsteps):
+        """nsteps steps of scheme "si" or "ex"; returns a device FP64 tensor
+        (nsteps+1, 3) of (energy, min T, max T) for the initial state and
+        after every step."""
+        s = torch.empty((int(nsteps) + 1, 3), dtype=torch.float64, device=self.device)
+        code = {"si": 0, "ex": 1}[scheme]
+        check(lib().asd_step_series(self.handle, code, float(dt), int(nsteps), ctypes.c_void_p(s.data_ptr())))
+        return s
 
     def status(self):
         f = ctypes.c_uint32()

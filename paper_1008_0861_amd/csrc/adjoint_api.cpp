@@ -54,23 +54,6 @@ extern "C" int asd_adjoint_workspace_bytes(asd_grid g, int32_t nsteps, int32_t c
     return ASD_OK;
 }
 
-template <typename T>
-static int permute_2d(asd_grid g, const void* in, void* out, bool a_to_b) {
-    const int nx = (int)g->d.n[0], ny = (int)g->d.n[1];
-    hipError_t e;
-    if (a_to_b) {
-        const int n[3] = {nx, ny, 1};
-        const int64_t ds[3] = {ny, 1, (int64_t)nx * ny};
-        e = launch_permute<T>((const T*)in, (T*)out, n, ds, g->st);
-    } else {
-        // a B array is a dense (nx, ny) array with y fastest
-        const int n[3] = {ny, nx, 1};
-        const int64_t ds[3] = {nx, 1, (int64_t)nx * ny};
-        e = launch_permute<T>((const T*)in, (T*)out, n, ds, g->st);
-    }
-    if (e != hipSuccess) return asd_fail(ASD_EHIP, "permute: %s", hipGetErrorString(e));
-    return ASD_OK;
-}
 
 template <typename T>
 static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, const void* X, void* lam_out,
@@ -157,14 +140,14 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
         for (int i = 0; i < len; ++i) {
             rc = enqueue_sweep(g, 0, dt, S[i], tB, 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
-            rc = permute_2d<T>(g, tB, TS[i], false);
+            rc = enqueue_permute_2d(g, tB, TS[i], false);
             if (rc) return rc;
             rc = enqueue_sweep(g, 1, dt, tB, S[i + 1], 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
         }
         for (int i = len - 1; i >= 0; --i) {
             // y sweep: T* -> T^{n+1}
-            rc = permute_2d<T>(g, lam, tB, true);
+            rc = enqueue_permute_2d(g, lam, tB, true);
             if (rc) return rc;
             rc = enqueue_sweep(g, 1, dt, tB, mu, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
@@ -173,7 +156,7 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
             // x sweep: T^n -> T*
             rc = enqueue_sweep(g, 0, dt, lam, tB, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
-            rc = permute_2d<T>(g, tB, mu, false);
+            rc = enqueue_permute_2d(g, tB, mu, false);
             if (rc) return rc;
             rc = stencil<T>(g, 0, dt, mu, S[i], TS[i], lam, gchi, W1, W2, GF);
             if (rc) return rc;
@@ -191,7 +174,8 @@ extern "C" int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t c
     if (!dev_T0 || !dev_lambda_final || !dev_grad_T0) return asd_fail(ASD_EINVAL, "NULL state pointer");
     if (dev_grad_chi && !(g->d.flags & ASD_FLAG_PER_CELL_CHI))
         return asd_fail(ASD_EINVAL, "grad_chi needs ASD_FLAG_PER_CELL_CHI");
-    if (g->d.flags & ASD_FLAG_FOUR_STEP) return asd_fail(ASD_EUNSUPPORTED, "the adjoint is of the 2-step scheme");
+    if (g->d.flags & (ASD_FLAG_FOUR_STEP | ASD_FLAG_REVERSE_ORDER))
+        return asd_fail(ASD_EUNSUPPORTED, "the adjoint is of the 2-step scheme in the order x, y");
     if (!dev_adj_ws) return asd_fail(ASD_EWORKSPACE, "adjoint workspace is NULL");
     if ((uintptr_t)dev_adj_ws & 255) return asd_fail(ASD_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
     const AdjPlan pl = adj_plan(g, nsteps, ckpt_every);

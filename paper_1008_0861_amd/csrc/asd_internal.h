@@ -123,6 +123,7 @@ struct asd_grid_s {
     double graph_dt = 0.0;
     int graph_nsteps = 0;
     double* graph_energy = nullptr;
+    double* graph_series = nullptr;
 };
 
 // capi.cpp
@@ -141,19 +142,28 @@ int check_fields(asd_grid g, bool need_T);
 int prepare(asd_grid g, double dt);  // dt > 0: face coefficients for dt
 int64_t layout_stride(const asd_grid g, int L, int a);
 asd::ReduceParams no_reduce();
-asd::FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, double* energy_out,
-                          const double* e0);
+// Per-step outputs of a step loop (each nullable): energies, FP64[nsteps+1];
+// series of (energy, min T, max T), FP64[3 (nsteps+1)].
+struct StepOut {
+    double* energy = nullptr;
+    double* series = nullptr;
+    bool any() const { return energy || series; }
+    const double* e0() const { return energy ? energy : series; }  // energy of the initial state
+};
+// Fold of count consecutive reductions into entries first .. first+count-1 of out.
+asd::FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, const StepOut& out, int first);
 inline double* ring_slot(asd_grid g, int i) { return g->ring + (size_t)i * g->max_blocks * 3; }
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
                   const asd::ReduceParams& red, const SweepCfg* cfg,
                   int* nblocks_out);
-int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy);
-int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy);
+int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& out);
+int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, const StepOut& out);
+int enqueue_permute_2d(asd_grid g, const void* in, void* out, bool a_to_b);
 int enqueue_explicit(asd_grid g, double dt, const void* src, void* dst, const asd::ReduceParams& red,
                      int* nblocks_out);
 int enqueue_copy(asd_grid g, const void* src, void* dst);
-int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0, asd::FoldParams* fold);
+int enqueue_reduce(asd_grid g, const void* x, const StepOut& out, asd::FoldParams* fold);
 int enqueue_fold(asd_grid g, const asd::FoldParams& f);
 // graph.cpp
-int run_si_graph(asd_grid g, double dt, int nsteps, double* energy);
-int run_explicit_graph(asd_grid g, double dt, int nsteps, double* energy);
+int run_si_graph(asd_grid g, double dt, int nsteps, const StepOut& out);
+int run_explicit_graph(asd_grid g, double dt, int nsteps, const StepOut& out);

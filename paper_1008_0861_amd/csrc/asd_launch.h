@@ -23,6 +23,7 @@ struct FoldParams {
     int count;           // reductions folded by this launch
     int slot_stride;     // doubles between the partials of consecutive reductions
     double* energy_out;  // nullable: receives sum * dV, one value per reduction
+    double* series_out;  // nullable: receives {sum * dV, min, max} per reduction
     double* stats_out;   // nullable: {sum * dV, min, max} of the last reduction
     unsigned* flags;     // nullable: ORed with status bits
     const double* e0;    // nullable: reference energy for the drift flag
@@ -216,6 +217,7 @@ __device__ __forceinline__ void fold_partials(const FoldParams& f) {
         }
         const double E = S * f.dV;
         if (f.energy_out) f.energy_out[b] = E;
+        if (f.series_out) { f.series_out[3 * b] = E; f.series_out[3 * b + 1] = MN; f.series_out[3 * b + 2] = MX; }
         if (f.stats_out && b == f.count - 1) { f.stats_out[0] = E; f.stats_out[1] = MN; f.stats_out[2] = MX; }
         if (f.flags) {
             unsigned fl = 0;

@@ -63,8 +63,8 @@ static int check_descs(const asd_desc* descs, int32_t nprob) {
             return asd_fail(ASD_EINVAL, "problem %d: bc, dtype and limiter must match problem 0", p);
         if (descs[p].flags & ASD_FLAG_PER_CELL_CHI)
             return asd_fail(ASD_EUNSUPPORTED, "batched problems take a constant chi_par");
-        if (descs[p].flags & ASD_FLAG_FOUR_STEP)
-            return asd_fail(ASD_EUNSUPPORTED, "batched problems take the 2-step scheme");
+        if (descs[p].flags & (ASD_FLAG_FOUR_STEP | ASD_FLAG_REVERSE_ORDER))
+            return asd_fail(ASD_EUNSUPPORTED, "batched problems take the 2-step scheme in the order x, y");
     }
     return ASD_OK;
 }
@@ -271,7 +271,7 @@ static int batch_step_t(asd_batch b, int nsteps, int mode) {
     }
     if (mode == 1) {
         for (int p = 0; p < b->nprob; ++p) {
-            int rc = enqueue_si_loop(b->sub[p], b->dt[p], nsteps, nullptr);
+            int rc = enqueue_si_loop(b->sub[p], b->dt[p], nsteps, StepOut{});
             if (rc) return rc;
         }
         return ASD_OK;

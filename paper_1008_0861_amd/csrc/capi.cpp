@@ -21,6 +21,7 @@
 #include <string>
 
 #include "../../include/asd.h"
+#include "../../include/asd_extra.h"
 #include "asd_launch.h"
 #include "asd_internal.h"
 
@@ -58,7 +59,7 @@ int validate_desc(const asd_desc* d) {
     if (d->limiter < ASD_LIM_VANLEER || d->limiter > ASD_LIM_LINEAR)
         return asd_fail(ASD_EINVAL, "bad limiter %d", d->limiter);
     if (d->reserved != 0) return asd_fail(ASD_EINVAL, "reserved must be 0");
-    if (d->flags & ~(ASD_FLAG_PER_CELL_CHI | ASD_FLAG_ALLOW_UNSTABLE | ASD_FLAG_FOUR_STEP))
+    if (d->flags & ~(ASD_FLAG_PER_CELL_CHI | ASD_FLAG_ALLOW_UNSTABLE | ASD_FLAG_FOUR_STEP | ASD_FLAG_REVERSE_ORDER))
         return asd_fail(ASD_EINVAL, "unknown flags 0x%x", d->flags);
     const int64_t nmin = d->bc == ASD_BC_PERIODIC ? 3 : 2;
     for (int q = 0; q < d->ndim; ++q) {
@@ -69,6 +70,8 @@ int validate_desc(const asd_desc* d) {
         if (!finite_pos(d->h[q])) return asd_fail(ASD_EINVAL, "h[%d] must be finite and > 0", q);
     }
     if (d->ndim == 2 && d->n[2] != 1) return asd_fail(ASD_ESHAPE, "n[2] must be 1 in 2-D");
+    if (d->ndim == 3 && (d->flags & ASD_FLAG_REVERSE_ORDER))
+        return asd_fail(ASD_EUNSUPPORTED, "the reverse sweep order is for 2-D grids");
     if (!finite_pos(d->chi_par)) return asd_fail(ASD_EINVAL, "chi_par must be finite and > 0");
     if (!std::isfinite(d->chi_perp) || d->chi_perp < 0.0 || d->chi_perp > d->chi_par)
         return asd_fail(ASD_EINVAL, "chi_perp must be in [0, chi_par]");
@@ -313,17 +316,17 @@ ReduceParams no_reduce() {
     return r;
 }
 
-FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, double* energy_out,
-                     const double* e0) {
+FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, const StepOut& out, int first) {
     FoldParams f{};
     f.partials = partials;
     f.nblocks = nblocks;
     f.count = count;
     f.slot_stride = (int)(g->max_blocks * 3);
-    f.energy_out = energy_out;
+    f.energy_out = out.energy ? out.energy + first : nullptr;
+    f.series_out = out.series ? out.series + 3 * first : nullptr;
     f.stats_out = g->stats;
     f.flags = g->flags;
-    f.e0 = e0;
+    f.e0 = first > 0 ? out.e0() : nullptr;
     double dv = 1.0;
     for (int q = 0; q < g->d.ndim; ++q) dv *= g->d.h[q];
     f.dV = dv;
@@ -397,14 +400,25 @@ int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int r
                       : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out);
 }
 
+// 2-D layout change A = [y][x] -> B = [x][y] (a_to_b) or back.
+int enqueue_permute_2d(asd_grid g, const void* in, void* out, bool a_to_b) {
+    const int nx = (int)g->d.n[0], ny = (int)g->d.n[1];
+    const int n[3] = {a_to_b ? nx : ny, a_to_b ? ny : nx, 1};
+    // a B array is a dense (nx, ny) array with y fastest
+    const int64_t ds[3] = {a_to_b ? ny : nx, 1, (int64_t)nx * ny};
+    hipError_t e = g->es == 8 ? launch_permute<double>((const double*)in, (double*)out, n, ds, g->st)
+                              : launch_permute<float>((const float*)in, (float*)out, n, ds, g->st);
+    return hip_check(e, "permute launch");
+}
+
 // Reduce a state into the standalone slot; returns the fold that finishes it.
-int enqueue_reduce(asd_grid g, const void* x, double* energy_out, const double* e0, FoldParams* fold) {
+int enqueue_reduce(asd_grid g, const void* x, const StepOut& out, FoldParams* fold) {
     const int nb = reduce_num_blocks(g->N);
     ReduceParams r{};
     r.partials = ring_slot(g, g->ring_slots);
     hipError_t e = g->es == 8 ? launch_reduce<double>((const double*)x, g->N, r, nb, g->st)
                               : launch_reduce<float>((const float*)x, g->N, r, nb, g->st);
-    *fold = make_fold(g, r.partials, nb, 1, energy_out, e0);
+    *fold = make_fold(g, r.partials, nb, 1, out, 0);
     return hip_check(e, "reduce launch");
 }
 
@@ -434,29 +448,44 @@ static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
 }
 
 // The whole multi-step call as a kernel sequence (used eagerly and under
-// graph capture).  Energy: the initial state is reduced and folded first;
+// graph capture).  Outputs: the initial state is reduced and folded first;
 // every step's last kernel writes per-block partials into the next ring
-// slot, and one fold launch turns a full ring (or the last steps) into
-// energy[s+1] for each of those steps, off the sweeps' critical path.
-int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy) {
+// slot, and one fold launch turns a full ring (or the last steps) into the
+// outputs of each of those steps, off the sweeps' critical path.
+int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     const int nd = g->d.ndim;
     const bool four = (g->d.flags & ASD_FLAG_FOUR_STEP) != 0;
+    const bool reverse = (g->d.flags & ASD_FLAG_REVERSE_ORDER) != 0;  // 2-D only
     int rc = ASD_OK;
-    if (energy) {
+    if (outs.any()) {
         FoldParams f0;
-        rc = enqueue_reduce(g, g->T, energy, nullptr, &f0);
+        rc = enqueue_reduce(g, g->T, outs, &f0);
         if (rc == ASD_OK) rc = enqueue_fold(g, f0);
     }
+    // Reverse order (y, x): the state lives in layout B between steps, in
+    // tmp1: T -> tmp1 before the first step, tmp1 -> T after the last.
+    if (reverse && nsteps > 0 && rc == ASD_OK) rc = enqueue_permute_2d(g, g->T, g->tmp[1], true);
     int used = 0;  // ring slots holding unfolded steps
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
-        const void* in = g->T;
-        for (int d = 0; d < nd && rc == ASD_OK; ++d) {
-            const bool produce = energy && d == nd - 1;
+        const void* in = reverse ? g->tmp[1] : g->T;
+        for (int i = 0; i < nd && rc == ASD_OK; ++i) {
+            const int d = reverse ? nd - 1 - i : i;
+            const bool produce = outs.any() && i == nd - 1;
             ReduceParams red = no_reduce();
             if (produce) red.partials = ring_slot(g, used);
             int nb = 0;
             void* out;
-            if (!four) {
+            if (reverse) {
+                // y: B (tmp1) -> A (tmp0); x: A (tmp0) -> B (tmp1).  The 4-step
+                // intermediate (input layout) goes to T, free meanwhile.
+                out = d == 1 ? g->tmp[0] : g->tmp[1];
+                if (!four) {
+                    rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
+                } else {
+                    rc = enqueue_sweep(g, d, dt, in, g->T, SWEEP_KEEP_LAYOUT, no_reduce(), nullptr, nullptr);
+                    if (rc == ASD_OK) rc = enqueue_sweep(g, d, dt, g->T, out, SWEEP_SOLVE_ONLY, red, nullptr, &nb);
+                }
+            } else if (!four) {
                 out = (d == nd - 1) ? g->T : g->tmp[d];
                 rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
             } else {
@@ -469,12 +498,13 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, double* energy) {
                 if (rc == ASD_OK) rc = enqueue_sweep(g, d, dt, g->tmp[1], out, SWEEP_SOLVE_ONLY, red, nullptr, &nb);
             }
             if (rc == ASD_OK && produce && (++used == g->ring_slots || s == nsteps - 1)) {
-                rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, energy + s + 2 - used, energy));
+                rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, outs, s + 2 - used));
                 used = 0;
             }
             in = out;
         }
     }
+    if (reverse && nsteps > 0 && rc == ASD_OK) rc = enqueue_permute_2d(g, g->tmp[1], g->T, false);
     return rc;
 }
 
@@ -488,8 +518,10 @@ extern "C" int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, dou
     rc = prepare(g, dt);
     if (rc) return rc;
     // the legacy default stream cannot be captured: launch eagerly there
-    if (g->use_graphs && g->st && nsteps >= 2) return run_si_graph(g, dt, nsteps, dev_energy);
-    return enqueue_si_loop(g, dt, nsteps, dev_energy);
+    StepOut o;
+    o.energy = dev_energy;
+    if (g->use_graphs && g->st && nsteps >= 2) return run_si_graph(g, dt, nsteps, o);
+    return enqueue_si_loop(g, dt, nsteps, o);
 }
 
 template <typename T>
@@ -533,11 +565,11 @@ int enqueue_copy(asd_grid g, const void* src, void* dst) {
 
 // Explicit steps ping-pong between T and tmp[0]; an odd count ends with a
 // copy.  Energy partials go through the ring as in the semi-implicit loop.
-int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy) {
+int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     int rc = ASD_OK;
-    if (energy) {
+    if (outs.any()) {
         FoldParams f0;
-        rc = enqueue_reduce(g, g->T, energy, nullptr, &f0);
+        rc = enqueue_reduce(g, g->T, outs, &f0);
         if (rc == ASD_OK) rc = enqueue_fold(g, f0);
     }
     void* a = g->T;
@@ -545,11 +577,11 @@ int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, double* energy) {
     int used = 0;
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
         ReduceParams red = no_reduce();
-        if (energy) red.partials = ring_slot(g, used);
+        if (outs.any()) red.partials = ring_slot(g, used);
         int nb = 0;
         rc = enqueue_explicit(g, dt, a, b, red, &nb);
-        if (rc == ASD_OK && energy && (++used == g->ring_slots || s == nsteps - 1)) {
-            rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, energy + s + 2 - used, energy));
+        if (rc == ASD_OK && outs.any() && (++used == g->ring_slots || s == nsteps - 1)) {
+            rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, outs, s + 2 - used));
             used = 0;
         }
         std::swap(a, b);
@@ -567,8 +599,30 @@ extern "C" int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, 
     if (rc) return rc;
     rc = prepare(g, 0.0);
     if (rc) return rc;
-    if (g->use_graphs && g->st && nsteps >= 2) return run_explicit_graph(g, dt, nsteps, dev_energy);
-    return enqueue_explicit_loop(g, dt, nsteps, dev_energy);
+    StepOut o;
+    o.energy = dev_energy;
+    if (g->use_graphs && g->st && nsteps >= 2) return run_explicit_graph(g, dt, nsteps, o);
+    return enqueue_explicit_loop(g, dt, nsteps, o);
+}
+
+extern "C" int asd_step_series(asd_grid g, int32_t scheme, double dt, int32_t nsteps, double* dev_series) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (scheme != ASD_SCHEME_SEMI_IMPLICIT && scheme != ASD_SCHEME_EXPLICIT)
+        return asd_fail(ASD_EINVAL, "bad scheme %d", scheme);
+    if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
+    if (!dev_series) return asd_fail(ASD_EINVAL, "series is NULL");
+    const bool ex = scheme == ASD_SCHEME_EXPLICIT;
+    int rc = check_dt(g, dt, ex);
+    if (rc) return rc;
+    rc = check_fields(g, true);
+    if (rc) return rc;
+    rc = prepare(g, ex ? 0.0 : dt);
+    if (rc) return rc;
+    StepOut o;
+    o.series = dev_series;
+    if (g->use_graphs && g->st && nsteps >= 2)
+        return ex ? run_explicit_graph(g, dt, nsteps, o) : run_si_graph(g, dt, nsteps, o);
+    return ex ? enqueue_explicit_loop(g, dt, nsteps, o) : enqueue_si_loop(g, dt, nsteps, o);
 }
 
 extern "C" int asd_status(asd_grid g, uint32_t* flags, double* stats) {
@@ -579,7 +633,7 @@ extern "C" int asd_status(asd_grid g, uint32_t* flags, double* stats) {
     rc = prepare(g, 0.0);
     if (rc) return rc;
     FoldParams f;
-    rc = enqueue_reduce(g, g->T, nullptr, nullptr, &f);
+    rc = enqueue_reduce(g, g->T, StepOut{}, &f);
     if (rc) return rc;
     rc = enqueue_fold(g, f);
     if (rc) return rc;

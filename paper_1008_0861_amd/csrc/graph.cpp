@@ -1,5 +1,5 @@
 // hipGraph capture of step loops.  A loop of nsteps steps is captured once
-// per (scheme, dt, nsteps, energy pointer, state pointer) and replayed, so a
+// per (scheme, dt, nsteps, output pointers) and replayed, so a
 // long run costs one graph launch instead of 2-3 kernel launches per step.
 // Only kernels are captured (no memset or memcpy nodes).
 #include <hip/hip_runtime.h>
@@ -8,10 +8,11 @@
 
 using namespace asd;
 
-static int run_graph(asd_grid g, int kind, double dt, int nsteps, double* energy) {
+static int run_graph(asd_grid g, int kind, double dt, int nsteps, const StepOut& out) {
     // callers only come here with a capturable (non-default) stream
     const bool hit = g->graph_valid && g->graph_kind == kind && g->graph_dt == dt &&
-                     g->graph_nsteps == nsteps && g->graph_energy == energy && g->graph_exec;
+                     g->graph_nsteps == nsteps && g->graph_energy == out.energy &&
+                     g->graph_series == out.series && g->graph_exec;
     if (!hit) {
         if (g->graph_exec) {
             (void)hipGraphExecDestroy(g->graph_exec);
@@ -20,7 +21,7 @@ static int run_graph(asd_grid g, int kind, double dt, int nsteps, double* energy
         g->graph_valid = false;
         hipError_t e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return asd_fail(ASD_EHIP, "begin capture: %s", hipGetErrorString(e));
-        const int rc = kind == 1 ? enqueue_si_loop(g, dt, nsteps, energy) : enqueue_explicit_loop(g, dt, nsteps, energy);
+        const int rc = kind == 1 ? enqueue_si_loop(g, dt, nsteps, out) : enqueue_explicit_loop(g, dt, nsteps, out);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(g->st, &graph);
         if (rc != ASD_OK) {
@@ -36,7 +37,8 @@ static int run_graph(asd_grid g, int kind, double dt, int nsteps, double* energy
         g->graph_kind = kind;
         g->graph_dt = dt;
         g->graph_nsteps = nsteps;
-        g->graph_energy = energy;
+        g->graph_energy = out.energy;
+        g->graph_series = out.series;
         g->graph_valid = true;
     }
     hipError_t e = hipGraphLaunch(g->graph_exec, g->st);
@@ -44,7 +46,7 @@ static int run_graph(asd_grid g, int kind, double dt, int nsteps, double* energy
     return ASD_OK;
 }
 
-int run_si_graph(asd_grid g, double dt, int nsteps, double* energy) { return run_graph(g, 1, dt, nsteps, energy); }
-int run_explicit_graph(asd_grid g, double dt, int nsteps, double* energy) {
-    return run_graph(g, 2, dt, nsteps, energy);
+int run_si_graph(asd_grid g, double dt, int nsteps, const StepOut& out) { return run_graph(g, 1, dt, nsteps, out); }
+int run_explicit_graph(asd_grid g, double dt, int nsteps, const StepOut& out) {
+    return run_graph(g, 2, dt, nsteps, out);
 }

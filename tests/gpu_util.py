@@ -20,20 +20,20 @@ def rounded(p, prec):
     return [r(c) for c in p.b], r(p.T0), r(p.chi)
 
 
-def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False, four_step=False):
+def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False, four_step=False, reverse=False):
     b, T0, chi = rounded(p, prec)
     g = oracle.OracleGrid(b, p.h, bc=p.bc, limiter=p.limiter, chi_par=p.chi_par, chi_perp=p.chi_perp, chi=chi)
     nsteps = p.nsteps if nsteps is None else nsteps
     dt = p.dt if dt is None else dt
     if scheme == "si":
-        return g.step_si(T0, dt, nsteps, energy=energy, four_step=four_step)
+        return g.step_si(T0, dt, nsteps, energy=energy, four_step=four_step, reverse=reverse)
     return g.step_explicit(T0, dt, nsteps, energy=energy)
 
 
 class GpuProblem:
     """A problem resident on the GPU, advanced on a private stream."""
 
-    def __init__(self, p, prec, stream=None, allow_unstable=False, four_step=False):
+    def __init__(self, p, prec, stream=None, allow_unstable=False, four_step=False, reverse_order=False):
         self.p = p
         self.prec = prec
         self.stream = stream or torch.cuda.Stream()
@@ -42,7 +42,7 @@ class GpuProblem:
         with torch.cuda.stream(self.stream):
             self.g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=dt, limiter=p.limiter, chi_par=chi_par,
                               chi_perp=p.chi_perp, per_cell_chi=p.chi is not None,
-                              allow_unstable=allow_unstable, four_step=four_step)
+                              allow_unstable=allow_unstable, four_step=four_step, reverse_order=reverse_order)
             self.b = [torch.from_numpy(c).to(dt).cuda() for c in p.b]
             self.T = torch.from_numpy(p.T0).to(dt).cuda()
             self.g.set_b(*self.b)
