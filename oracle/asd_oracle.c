@@ -40,7 +40,10 @@
  *   - 4-argument limiter L(a,b,c,d) = L(L(a,b),L(c,d)) for every limiter,
  *     (a,b) taken from the cell on the + side of the face;
  *   - the explicit limited step is forward Euler of the same unsplit
- *     operator, every face evaluated from T^n.
+ *     operator, every face evaluated from T^n;
+ *   - temperature-dependent chi_par (chi ~ T^(5/2), section 4): per-cell
+ *     values from the state the sweep reads (T^n, T*, ...), harmonic mean
+ *     at each face, as for a per-cell chi field.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -64,6 +67,8 @@ typedef struct {
     double chi_perp;  /* isotropic part of the tensor */
     const double *b[3]; /* cell-centred components of the unit vector b */
     const double *chi;  /* optional per-cell chi_par (NULL: constant) */
+    double chi_exp;     /* != 0: chi_par(T) = chi_par (T / chi_tref)^chi_exp, from the */
+    double chi_tref;    /*       state the sweep (or explicit step) reads (section 4)   */
 } orc_grid;
 
 /* ------------------------------------------------------------------ */
@@ -200,11 +205,26 @@ static double ghost_value(const orc_grid *g, const double *U, const long p[3], i
     return U[cell_index(g, q)];
 }
 
-/* Face diffusivity: chi_par, or the harmonic mean of the two cells. */
-static double face_chi(const orc_grid *g, long c0, long c1)
+/* Cell diffusivity from the state U: chi_par (T / chi_tref)^chi_exp. */
+static double cell_chi_of_T(const orc_grid *g, const double *U, long c)
 {
-    if (!g->chi) return g->chi_par;
-    const double a = g->chi[c0], b = g->chi[c1];
+    return g->chi_par * pow(U[c] / g->chi_tref, g->chi_exp);
+}
+
+/* Face diffusivity: chi_par, or the harmonic mean of the two cells' values
+ * (a per-cell field, or chi_par(T) of the state U). */
+static double face_chi(const orc_grid *g, const double *U, long c0, long c1)
+{
+    double a, b;
+    if (g->chi_exp != 0.0) {
+        a = cell_chi_of_T(g, U, c0);
+        b = cell_chi_of_T(g, U, c1);
+    } else if (g->chi) {
+        a = g->chi[c0];
+        b = g->chi[c1];
+    } else {
+        return g->chi_par;
+    }
     if (a + b == 0.0) return 0.0;
     return 2.0 * a * b / (a + b);
 }
@@ -216,13 +236,13 @@ static double face_chi(const orc_grid *g, long c0, long c1)
  * with b at the face the arithmetic mean of the two cells (dt_n = dt_t = dt
  * in the 2-step scheme).
  */
-static void face_coefficients(const orc_grid *g, int d, const long p0[3], const long p1[3],
+static void face_coefficients(const orc_grid *g, const double *U, int d, const long p0[3], const long p1[3],
                               double dt_n, double dt_t, double *alpha, double beta[3])
 {
     const long c0 = cell_index(g, p0), c1 = cell_index(g, p1);
     double bf[3] = {0.0, 0.0, 0.0};
     for (int q = 0; q < g->ndim; ++q) bf[q] = 0.5 * (g->b[q][c0] + g->b[q][c1]);
-    const double chif = face_chi(g, c0, c1);
+    const double chif = face_chi(g, U, c0, c1);
     const double dnn = g->chi_perp + (chif - g->chi_perp) * bf[d] * bf[d];
     *alpha = dt_n * dnn / (g->h[d] * g->h[d]);
     for (int t = 0; t < 3; ++t) beta[t] = 0.0;
@@ -272,7 +292,7 @@ static void line_face(const orc_grid *g, const double *U, int d, const long base
     p0[d] = k0;
     p1[d] = k1;
     double beta[3];
-    face_coefficients(g, d, p0, p1, dt_n, dt_t, alpha, beta);
+    face_coefficients(g, U, d, p0, p1, dt_n, dt_t, alpha, beta);
     double f = 0.0;
     for (int t = 0; t < g->ndim; ++t) {
         if (t == d) continue;
@@ -374,6 +394,7 @@ static int grid_ok(const orc_grid *g)
         if (g->n[q] < 2 || !(g->h[q] > 0.0) || !g->b[q]) return 0;
         if (g->bc == ORC_BC_PERIODIC && g->n[q] < 3) return 0;
     }
+    if (g->chi_exp != 0.0 && (!(g->chi_tref > 0.0) || g->chi)) return 0;
     return 1;
 }
 

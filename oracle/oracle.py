@@ -27,6 +27,8 @@ class _OrcGrid(ctypes.Structure):
         ("chi_perp", ctypes.c_double),
         ("b", _dp * 3),
         ("chi", _dp),
+        ("chi_exp", ctypes.c_double),
+        ("chi_tref", ctypes.c_double),
     ]
 
 
@@ -84,7 +86,10 @@ class OracleGrid:
        (ny, nx) or (nz, ny, nx).  h: cell widths (hx, hy[, hz]).
     """
 
-    def __init__(self, b, h, bc="periodic", limiter="vanleer", chi_par=1.0, chi_perp=0.0, chi=None):
+    def __init__(self, b, h, bc="periodic", limiter="vanleer", chi_par=1.0, chi_perp=0.0, chi=None,
+                 chi_exp=0.0, chi_tref=1.0):
+        """chi_exp != 0: temperature-dependent chi_par(T) = chi_par (T / chi_tref)^chi_exp
+        from the state each sweep (or explicit step) reads (chi must then be None)."""
         self.b = [_f64(c) for c in b]
         self.ndim = len(self.b)
         if self.ndim not in (2, 3):
@@ -112,6 +117,9 @@ class OracleGrid:
         s.chi_par = self.chi_par
         s.chi_perp = self.chi_perp
         s.chi = _ptr(self.chi) if self.chi is not None else _dp()
+        s.chi_exp = float(chi_exp)
+        s.chi_tref = float(chi_tref)
+        self.chi_exp, self.chi_tref = float(chi_exp), float(chi_tref)
         self._s = s
 
     @property
