@@ -60,6 +60,8 @@ class Desc(ctypes.Structure):
         ("chi_perp", ctypes.c_double),
         ("flags", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("chi_exp", ctypes.c_double),
+        ("chi_tref", ctypes.c_double),
     ]
 
 
@@ -128,8 +130,10 @@ def _dtype_code(dtype):
 
 
 def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0, chi_perp=0.0,
-              per_cell_chi=False, allow_unstable=False, four_step=False, reverse_order=False):
-    """Build an asd_desc.  shape is (ny, nx) or (nz, ny, nx), h is (hx, hy[, hz])."""
+              per_cell_chi=False, allow_unstable=False, four_step=False, reverse_order=False, chi_exp=0.0,
+              chi_tref=1.0):
+    """Build an asd_desc.  shape is (ny, nx) or (nz, ny, nx), h is (hx, hy[, hz]).
+    chi_exp != 0: chi_par(T) = chi_par (T / chi_tref)^chi_exp."""
     d = Desc()
     d.ndim = len(shape)
     d.bc = BC[bc]
@@ -144,6 +148,8 @@ def make_desc(shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", c
     d.flags = ((FLAG_PER_CELL_CHI if per_cell_chi else 0) | (FLAG_ALLOW_UNSTABLE if allow_unstable else 0)
                | (FLAG_FOUR_STEP if four_step else 0) | (FLAG_REVERSE_ORDER if reverse_order else 0))
     d.reserved = 0
+    d.chi_exp = float(chi_exp)
+    d.chi_tref = float(chi_tref)
     return d
 
 
@@ -168,12 +174,12 @@ class Grid:
 
     def __init__(self, shape, h, bc="periodic", dtype=torch.float32, limiter="vanleer", chi_par=1.0,
                  chi_perp=0.0, per_cell_chi=False, allow_unstable=False, device="cuda", stream=None,
-                 four_step=False, reverse_order=False):
+                 four_step=False, reverse_order=False, chi_exp=0.0, chi_tref=1.0):
         self.shape = tuple(int(s) for s in shape)
         self.dtype = dtype
         self.device = torch.device(device)
         self.desc = make_desc(self.shape, h, bc, dtype, limiter, chi_par, chi_perp, per_cell_chi, allow_unstable,
-                              four_step, reverse_order)
+                              four_step, reverse_order, chi_exp, chi_tref)
         nbytes = workspace_bytes(self.desc)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream_ptr, self.stream = _stream_handle(stream)

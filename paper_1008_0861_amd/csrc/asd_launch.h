@@ -61,6 +61,8 @@ template <typename T>
 struct CoefParams {
     const T* b[3];       // cell-centred b, x-fastest
     const T* chi;        // per-cell chi or nullptr
+    const T* U;          // chi from this state (sweep-input layout), or nullptr
+    double chi_exp, chi_tref;  // chi = chi_par (U / chi_tref)^chi_exp when U is set
     T* alpha;
     T* beta1;
     T* beta2;            // 3-D only
@@ -93,6 +95,7 @@ struct ExplicitParams {
     T* out;
     const T* b[3];
     const T* chi;
+    double chi_exp, chi_tref;  // != 0: per-cell chi = chi_par (U / chi_tref)^chi_exp
     int n[3];
     T cn[3];         // dt / h_d^2
     T ct[3][3];      // dt / (h_d h_t)

@@ -61,7 +61,7 @@ static int check_descs(const asd_desc* descs, int32_t nprob) {
         if (descs[p].ndim != 2) return asd_fail(ASD_EUNSUPPORTED, "batched problems must be 2-D");
         if (descs[p].bc != descs[0].bc || descs[p].dtype != descs[0].dtype || descs[p].limiter != descs[0].limiter)
             return asd_fail(ASD_EINVAL, "problem %d: bc, dtype and limiter must match problem 0", p);
-        if (descs[p].flags & ASD_FLAG_PER_CELL_CHI)
+        if ((descs[p].flags & ASD_FLAG_PER_CELL_CHI) || descs[p].chi_exp != 0.0)
             return asd_fail(ASD_EUNSUPPORTED, "batched problems take a constant chi_par");
         if (descs[p].flags & (ASD_FLAG_FOUR_STEP | ASD_FLAG_REVERSE_ORDER))
             return asd_fail(ASD_EUNSUPPORTED, "batched problems take the 2-step scheme in the order x, y");

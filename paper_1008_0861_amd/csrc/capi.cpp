@@ -75,6 +75,13 @@ int validate_desc(const asd_desc* d) {
     if (!finite_pos(d->chi_par)) return asd_fail(ASD_EINVAL, "chi_par must be finite and > 0");
     if (!std::isfinite(d->chi_perp) || d->chi_perp < 0.0 || d->chi_perp > d->chi_par)
         return asd_fail(ASD_EINVAL, "chi_perp must be in [0, chi_par]");
+    if (d->chi_exp != 0.0) {
+        if (!std::isfinite(d->chi_exp) || d->chi_exp < 0.0 || d->chi_exp > 8.0)
+            return asd_fail(ASD_EINVAL, "chi_exp must be in (0, 8]");
+        if (!finite_pos(d->chi_tref)) return asd_fail(ASD_EINVAL, "chi_tref must be finite and > 0");
+        if (d->flags & ASD_FLAG_PER_CELL_CHI)
+            return asd_fail(ASD_EINVAL, "chi_exp and ASD_FLAG_PER_CELL_CHI exclude each other");
+    }
     const int64_t N = d->n[0] * d->n[1] * (d->ndim == 3 ? d->n[2] : 1);
     if (N > (int64_t)INT32_MAX) return asd_fail(ASD_EUNSUPPORTED, "grid too large (more than 2^31-1 cells)");
     for (int q = 0; q < d->ndim; ++q) {
@@ -256,6 +263,48 @@ static SweepGeom sweep_geom(int ndim, int d) {
 static std::once_flag g_attr_once;
 static hipError_t g_attr_err = hipSuccess;
 
+// Face coefficients of sweep d for step dt into g->coef[d], in the sweep's
+// input layout.  U: chi(T) from this state (same layout), or nullptr for a
+// constant or per-cell chi.
+template <typename T>
+static int enqueue_coef_t(asd_grid g, int d, double dt, const void* U) {
+    const int nd = g->d.ndim;
+    const SweepGeom G = sweep_geom(nd, d);
+    CoefParams<T> C{};
+    for (int q = 0; q < 3; ++q) C.b[q] = q < nd ? (const T*)g->b[q] : nullptr;
+    C.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)g->chi : nullptr;
+    C.U = (const T*)U;
+    C.chi_exp = g->d.chi_exp;
+    C.chi_tref = g->d.chi_tref;
+    C.alpha = (T*)g->coef[d][0];
+    C.beta1 = (T*)g->coef[d][1];
+    C.beta2 = nd == 3 ? (T*)g->coef[d][2] : nullptr;
+    C.n[0] = (int)g->d.n[0];
+    C.n[1] = (int)g->d.n[1];
+    C.n[2] = nd == 3 ? (int)g->d.n[2] : 1;
+    C.d = G.d;
+    C.t1 = G.t1;
+    C.t2 = G.t2;
+    for (int a = 0; a < 3; ++a) C.so[a] = (int)layout_stride(g, G.Lin, a);
+    const double hd = g->d.h[G.d];
+    const double h1 = g->d.h[G.t1];
+    const double h2 = nd == 3 ? g->d.h[G.t2] : 1.0;
+    // the 4-step scheme solves its normal operator at dt/2 (Eq. 4step)
+    const double dt_n = (g->d.flags & ASD_FLAG_FOUR_STEP) ? 0.5 * dt : dt;
+    C.cnn = dt_n / (hd * hd);
+    C.ct1 = dt / (hd * h1);
+    C.ct2 = dt / (hd * h2);
+    C.chi_par = g->d.chi_par;
+    C.chi_perp = g->d.chi_perp;
+    C.periodic = g->d.bc == ASD_BC_PERIODIC;
+    C.ndim = nd;
+    return hip_check(launch_coef<T>(C, g->st), "coefficient launch");
+}
+
+static int enqueue_coef(asd_grid g, int d, double dt, const void* U) {
+    return g->es == 8 ? enqueue_coef_t<double>(g, d, dt, U) : enqueue_coef_t<float>(g, d, dt, U);
+}
+
 template <typename T>
 static int do_prepare(asd_grid g, double dt) {
     std::call_once(g_attr_once, [] {
@@ -269,35 +318,8 @@ static int do_prepare(asd_grid g, double dt) {
         g->ws_inited = true;
     }
     if (dt > 0.0 && !(g->coef_valid && g->coef_dt == dt)) {
-        const int nd = g->d.ndim;
-        for (int d = 0; d < nd; ++d) {
-            const SweepGeom G = sweep_geom(nd, d);
-            CoefParams<T> C{};
-            for (int q = 0; q < 3; ++q) C.b[q] = q < nd ? (const T*)g->b[q] : nullptr;
-            C.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)g->chi : nullptr;
-            C.alpha = (T*)g->coef[d][0];
-            C.beta1 = (T*)g->coef[d][1];
-            C.beta2 = nd == 3 ? (T*)g->coef[d][2] : nullptr;
-            C.n[0] = (int)g->d.n[0];
-            C.n[1] = (int)g->d.n[1];
-            C.n[2] = nd == 3 ? (int)g->d.n[2] : 1;
-            C.d = G.d;
-            C.t1 = G.t1;
-            C.t2 = G.t2;
-            for (int a = 0; a < 3; ++a) C.so[a] = (int)layout_stride(g, G.Lin, a);
-            const double hd = g->d.h[G.d];
-            const double h1 = g->d.h[G.t1];
-            const double h2 = nd == 3 ? g->d.h[G.t2] : 1.0;
-            // the 4-step scheme solves its normal operator at dt/2 (Eq. 4step)
-            const double dt_n = (g->d.flags & ASD_FLAG_FOUR_STEP) ? 0.5 * dt : dt;
-            C.cnn = dt_n / (hd * hd);
-            C.ct1 = dt / (hd * h1);
-            C.ct2 = dt / (hd * h2);
-            C.chi_par = g->d.chi_par;
-            C.chi_perp = g->d.chi_perp;
-            C.periodic = g->d.bc == ASD_BC_PERIODIC;
-            C.ndim = nd;
-            int rc = hip_check(launch_coef<T>(C, g->st), "coefficient launch");
+        for (int d = 0; d < g->d.ndim; ++d) {
+            int rc = enqueue_coef_t<T>(g, d, dt, nullptr);
             if (rc) return rc;
         }
         g->coef_valid = true;
@@ -429,7 +451,8 @@ int enqueue_fold(asd_grid g, const FoldParams& f) {
 
 static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
     if (!finite_pos(dt)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
-    if (g->d.flags & ASD_FLAG_ALLOW_UNSTABLE) return ASD_OK;
+    // chi(T): the diffusivity follows the state, the caller bounds dt
+    if ((g->d.flags & ASD_FLAG_ALLOW_UNSTABLE) || g->d.chi_exp != 0.0) return ASD_OK;
     const double chi = g->d.chi_par;
     double hmin2 = g->d.h[0] * g->d.h[0], sum_inv = 0.0;
     for (int q = 0; q < g->d.ndim; ++q) {
@@ -465,6 +488,13 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     // Reverse order (y, x): the state lives in layout B between steps, in
     // tmp1: T -> tmp1 before the first step, tmp1 -> T after the last.
     if (reverse && nsteps > 0 && rc == ASD_OK) rc = enqueue_permute_2d(g, g->T, g->tmp[1], true);
+    // chi(T) (section 4): each sweep's coefficients from that sweep's input
+    const bool chi_of_T = g->d.chi_exp != 0.0;
+    auto sweep = [&](int d, const void* src, void* dst, int mode, const ReduceParams& red, int* nb) {
+        int r = chi_of_T ? enqueue_coef(g, d, dt, src) : ASD_OK;
+        if (r == ASD_OK) r = enqueue_sweep(g, d, dt, src, dst, mode, red, nullptr, nb);
+        return r;
+    };
     int used = 0;  // ring slots holding unfolded steps
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
         const void* in = reverse ? g->tmp[1] : g->T;
@@ -480,22 +510,22 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
                 // intermediate (input layout) goes to T, free meanwhile.
                 out = d == 1 ? g->tmp[0] : g->tmp[1];
                 if (!four) {
-                    rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
+                    rc = sweep(d, in, out, 0, red, &nb);
                 } else {
-                    rc = enqueue_sweep(g, d, dt, in, g->T, SWEEP_KEEP_LAYOUT, no_reduce(), nullptr, nullptr);
-                    if (rc == ASD_OK) rc = enqueue_sweep(g, d, dt, g->T, out, SWEEP_SOLVE_ONLY, red, nullptr, &nb);
+                    rc = sweep(d, in, g->T, SWEEP_KEEP_LAYOUT, no_reduce(), nullptr);
+                    if (rc == ASD_OK) rc = sweep(d, g->T, out, SWEEP_SOLVE_ONLY, red, &nb);
                 }
             } else if (!four) {
                 out = (d == nd - 1) ? g->T : g->tmp[d];
-                rc = enqueue_sweep(g, d, dt, in, out, 0, red, nullptr, &nb);
+                rc = sweep(d, in, out, 0, red, &nb);
             } else {
                 // 4-step: transverse term at dt with the first half-step
                 // solve, written in the input layout, then the second
                 // half-step solve into the next sweep's layout.  States:
                 // T -> tmp0 (-> T in 3-D) -> T.
                 out = d == 0 ? g->tmp[0] : g->T;
-                rc = enqueue_sweep(g, d, dt, in, g->tmp[1], SWEEP_KEEP_LAYOUT, no_reduce(), nullptr, nullptr);
-                if (rc == ASD_OK) rc = enqueue_sweep(g, d, dt, g->tmp[1], out, SWEEP_SOLVE_ONLY, red, nullptr, &nb);
+                rc = sweep(d, in, g->tmp[1], SWEEP_KEEP_LAYOUT, no_reduce(), nullptr);
+                if (rc == ASD_OK) rc = sweep(d, g->tmp[1], out, SWEEP_SOLVE_ONLY, red, &nb);
             }
             if (rc == ASD_OK && produce && (++used == g->ring_slots || s == nsteps - 1)) {
                 rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, outs, s + 2 - used));
@@ -545,6 +575,8 @@ static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst,
     }
     P.chi_par = (T)g->d.chi_par;
     P.chi_perp = (T)g->d.chi_perp;
+    P.chi_exp = g->d.chi_exp;
+    P.chi_tref = g->d.chi_tref;
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
     P.limiter = g->d.limiter;
     P.red = red;

@@ -72,6 +72,8 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
 #pragma unroll
             for (int d = 0; d < NDIM; ++d) sB[d][i] = vb[d][j];
             if (P.chi) sChi[i] = vc[j];
+            // chi(T): the cell's value from T^n, in FP64 (section 4)
+            if (P.chi_exp != 0.0) sChi[i] = (T)((double)P.chi_par * pow((double)vu[j] / P.chi_tref, P.chi_exp));
         }
     }
     __syncthreads();
@@ -111,7 +113,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
                 if (wall) continue;
                 const T bnf = T(0.5) * (sB[d][i0] + sB[d][i1]);
                 T chif = P.chi_par;
-                if (P.chi) chif = harmonic<T>(sChi[i0], sChi[i1]);
+                if (P.chi || P.chi_exp != 0.0) chif = harmonic<T>(sChi[i0], sChi[i1]);
                 const T dpar = chif - P.chi_perp;
                 const T alpha = P.cn[d] * (P.chi_perp + dpar * bnf * bnf);
                 T tr = T(0);

@@ -20,9 +20,11 @@ def rounded(p, prec):
     return [r(c) for c in p.b], r(p.T0), r(p.chi)
 
 
-def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False, four_step=False, reverse=False):
+def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False, four_step=False, reverse=False,
+               chi_exp=0.0, chi_tref=1.0):
     b, T0, chi = rounded(p, prec)
-    g = oracle.OracleGrid(b, p.h, bc=p.bc, limiter=p.limiter, chi_par=p.chi_par, chi_perp=p.chi_perp, chi=chi)
+    g = oracle.OracleGrid(b, p.h, bc=p.bc, limiter=p.limiter, chi_par=p.chi_par, chi_perp=p.chi_perp, chi=chi,
+                          chi_exp=chi_exp, chi_tref=chi_tref)
     nsteps = p.nsteps if nsteps is None else nsteps
     dt = p.dt if dt is None else dt
     if scheme == "si":
@@ -33,7 +35,8 @@ def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False, four_st
 class GpuProblem:
     """A problem resident on the GPU, advanced on a private stream."""
 
-    def __init__(self, p, prec, stream=None, allow_unstable=False, four_step=False, reverse_order=False):
+    def __init__(self, p, prec, stream=None, allow_unstable=False, four_step=False, reverse_order=False,
+                 chi_exp=0.0, chi_tref=1.0):
         self.p = p
         self.prec = prec
         self.stream = stream or torch.cuda.Stream()
@@ -42,7 +45,8 @@ class GpuProblem:
         with torch.cuda.stream(self.stream):
             self.g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=dt, limiter=p.limiter, chi_par=chi_par,
                               chi_perp=p.chi_perp, per_cell_chi=p.chi is not None,
-                              allow_unstable=allow_unstable, four_step=four_step, reverse_order=reverse_order)
+                              allow_unstable=allow_unstable, four_step=four_step, reverse_order=reverse_order,
+                              chi_exp=chi_exp, chi_tref=chi_tref)
             self.b = [torch.from_numpy(c).to(dt).cuda() for c in p.b]
             self.T = torch.from_numpy(p.T0).to(dt).cuda()
             self.g.set_b(*self.b)

@@ -45,7 +45,7 @@ def test_header_constants_match_binding(asd):
     assert int(consts["ASD_FIELD_CHI"]) == asd.FIELD["chi"]
     for code, name in asd.ERRORS.items():
         assert int(consts["ASD_" + name]) == code
-    assert ctypes.sizeof(asd.Desc) == 4 * 4 + 8 * 3 + 8 * 3 + 8 * 2 + 4 * 2
+    assert ctypes.sizeof(asd.Desc) == 4 * 4 + 8 * 3 + 8 * 3 + 8 * 2 + 4 * 2 + 8 * 2
 
 
 def _desc(asd, **kw):
@@ -80,6 +80,11 @@ def test_workspace_bytes_valid(asd):
     (lambda d: d.n.__setitem__(0, 2), -2),     # periodic needs n >= 3
     (lambda d: d.n.__setitem__(2, 3), -2),     # 2-D needs n[2] == 1
     (lambda d: d.n.__setitem__(0, 200000), -8),  # line does not fit in LDS
+    (lambda d: setattr(d, "chi_exp", -1.0), -1),
+    (lambda d: setattr(d, "chi_exp", 9.0), -1),
+    (lambda d: setattr(d, "chi_exp", math.inf), -1),
+    (lambda d: (setattr(d, "chi_exp", 2.5), setattr(d, "chi_tref", 0.0)), -1),
+    (lambda d: (setattr(d, "chi_exp", 2.5), setattr(d, "flags", 1)), -1),  # with per-cell chi
 ])
 def test_bad_descriptions(asd, mutate, code):
     d = _desc(asd)
@@ -176,3 +181,12 @@ def test_sweep_config_api(asd):
     assert L.asd_set_sweep_config(h, 0, 1, 64) == -8
     assert L.asd_set_sweep_config(h, 5, 1, 1) == -1
     L.asd_destroy(h)
+
+
+def test_batch_refuses_chi_of_T(asd):
+    descs = (asd.Desc * 2)(_desc(asd), _desc(asd, chi_exp=2.5, chi_tref=1.0))
+    n = ctypes.c_size_t()
+    assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == -8
+    assert "constant chi_par" in asd.last_error()
+    rc, _ = _rc_ws(asd, _desc(asd, chi_exp=2.5, chi_tref=1.0))
+    assert rc == 0
