@@ -256,6 +256,41 @@ def three_d(stream, torch, asd, nsteps=50, ncfl=10.0, four_step=False):
             "energy_rel_drift": float(abs(e[-1] - e[0]) / abs(e[0]))}
 
 
+def ring512(stream, torch, asd):
+    """Ring diffusion of section 3.1 on 512^2 (T = 10 in the patch, 0.1
+    elsewhere, chi = 0.01, insulating) to t = 20, FP64: minimum temperature
+    over all steps for the semi-implicit scheme at ncfl = 1 .. 10^4 and for
+    the explicit scheme at ncfl = 1 with and without (linear averaging) the
+    van Leer limiter.  The paper's printed values: semi-implicit ncfl = 1000
+    about 0.08, positive up to ncfl = 10^4; unlimited explicit -0.41."""
+    import numpy as np
+    import synth
+
+    def run(ncfl, scheme, limiter):
+        p = synth.ring_problem(n=512, t_in=10.0, t_out=0.1, ncfl=ncfl, nsteps=0, limiter=limiter)
+        nsteps = int(np.ceil(20.0 / p.dt))
+        with torch.cuda.stream(stream):
+            g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=torch.float64, limiter=limiter, chi_par=p.chi_par)
+            b = [torch.from_numpy(c).cuda() for c in p.b]
+            T = torch.from_numpy(p.T0).cuda()
+            g.set_b(*b)
+            g.set_field("T", T)
+            g.set_graphs(False)
+            s = g.step_series(scheme, p.dt, nsteps)
+        stream.synchronize()
+        s = s.cpu().numpy()
+        return round(float(s[:, 1].min()), 5), nsteps
+
+    out = {"si_min_T": {}, "steps": {}}
+    for ncfl in (1, 10, 100, 1000, 10000):
+        m, n = run(float(ncfl), "si", "vanleer")
+        out["si_min_T"][str(ncfl)] = m
+        out["steps"][str(ncfl)] = n
+    out["explicit_vanleer_min_T"], _ = run(1.0, "ex", "vanleer")
+    out["explicit_unlimited_min_T"], _ = run(1.0, "ex", "linear")
+    return out
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle, serial on one host core, on the same 1024^2 workload:
     as many whole steps as fit in about budget_s seconds (at least 2)."""
@@ -378,6 +413,7 @@ def main():
         extra["batched"] = batched(stream, torch, asd)
         extra["curl3d_256"] = three_d(stream, torch, asd)
         extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
+        extra["ring512"] = ring512(stream, torch, asd)
         result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
