@@ -43,7 +43,15 @@
  *     operator, every face evaluated from T^n;
  *   - temperature-dependent chi_par (chi ~ T^(5/2), section 4): per-cell
  *     values from the state the sweep reads (T^n, T*, ...), harmonic mean
- *     at each face, as for a per-cell chi field.
+ *     at each face, as for a per-cell chi field;
+ *   - fixed-temperature walls (T = 0 on the boundary, the smooth test of
+ *     section 3.2): odd ghosts U[-1] = -U[0], U[n] = -U[n-1] (zero on the
+ *     wall face), the wall face's b and chi those of its cell, no
+ *     transverse flux through a wall face (the limited difference of a cell
+ *     and its odd ghost vanishes), normal flux alpha_w (U_ghost - U_cell)
+ *     taken implicitly: 2 alpha_w on the diagonal of the wall cell's row;
+ *   - source Q (same section): dt Q added to the right-hand side of the
+ *     first sweep of each step (forward Euler in the explicit scheme).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -51,6 +59,7 @@
 
 #define ORC_BC_PERIODIC 0
 #define ORC_BC_INSULATING 1
+#define ORC_BC_DIRICHLET 2
 
 #define ORC_LIM_VANLEER 0
 #define ORC_LIM_MINMOD 1
@@ -69,6 +78,7 @@ typedef struct {
     const double *chi;  /* optional per-cell chi_par (NULL: constant) */
     double chi_exp;     /* != 0: chi_par(T) = chi_par (T / chi_tref)^chi_exp, from the */
     double chi_tref;    /*       state the sweep (or explicit step) reads (section 4)   */
+    const double *src;  /* optional per-cell source Q (NULL: none) */
 } orc_grid;
 
 /* ------------------------------------------------------------------ */
@@ -193,22 +203,39 @@ static long cell_index(const orc_grid *g, const long p[3])
 /*
  * Value of U at cell p displaced by s (= +1 or -1) along axis t, with the
  * boundary rule: periodic wraps, insulating mirrors (U[-1] = U[0],
- * U[n] = U[n-1], which gives zero normal gradient at the wall).
+ * U[n] = U[n-1], which gives zero normal gradient at the wall), Dirichlet
+ * mirrors with the opposite sign (U[-1] = -U[0], U[n] = -U[n-1]: the
+ * linear interpolant vanishes on the wall face).
  */
 static double ghost_value(const orc_grid *g, const double *U, const long p[3], int t, int s)
 {
     long q[3] = {p[0], p[1], p[2]};
     long m = q[t] + s;
-    if (m < 0) m = (g->bc == ORC_BC_PERIODIC) ? g->n[t] - 1 : 0;
-    if (m >= g->n[t]) m = (g->bc == ORC_BC_PERIODIC) ? 0 : g->n[t] - 1;
+    double sign = 1.0;
+    if (m < 0 || m >= g->n[t]) {
+        if (g->bc == ORC_BC_PERIODIC) {
+            m = m < 0 ? g->n[t] - 1 : 0;
+        } else {
+            m = q[t];
+            if (g->bc == ORC_BC_DIRICHLET) sign = -1.0;
+        }
+    }
     q[t] = m;
-    return U[cell_index(g, q)];
+    return sign * U[cell_index(g, q)];
 }
 
 /* Cell diffusivity from the state U: chi_par (T / chi_tref)^chi_exp. */
 static double cell_chi_of_T(const orc_grid *g, const double *U, long c)
 {
     return g->chi_par * pow(U[c] / g->chi_tref, g->chi_exp);
+}
+
+/* Diffusivity of one cell: chi_par, the per-cell field, or chi_par(T). */
+static double cell_chi(const orc_grid *g, const double *U, long c)
+{
+    if (g->chi_exp != 0.0) return cell_chi_of_T(g, U, c);
+    if (g->chi) return g->chi[c];
+    return g->chi_par;
 }
 
 /* Face diffusivity: chi_par, or the harmonic mean of the two cells' values
@@ -273,10 +300,12 @@ static double transverse_difference(const orc_grid *g, const double *U, const lo
 /*
  * Normal coefficient alpha and transverse flux F of face "k + 1/2" of a line
  * along axis d (between line cell k and cell k+1, wrapping for periodic).
- * Wall faces (insulating, k = -1 or k = n-1) carry no flux.
+ * Wall faces (k = -1 or k = n-1 when not periodic) have F = 0; an
+ * insulating wall has alpha = 0, a Dirichlet wall the alpha of a face whose
+ * b and chi are those of its one cell.  Returns 1 for a wall face.
  */
-static void line_face(const orc_grid *g, const double *U, int d, const long base[3], long k,
-                      double dt_n, double dt_t, double *alpha, double *flux)
+static int line_face(const orc_grid *g, const double *U, int d, const long base[3], long k,
+                     double dt_n, double dt_t, double *alpha, double *flux)
 {
     const long n = g->n[d];
     *alpha = 0.0;
@@ -286,7 +315,15 @@ static void line_face(const orc_grid *g, const double *U, int d, const long base
         k0 = (k0 + n) % n;
         k1 = (k1 + n) % n;
     } else if (k0 < 0 || k1 > n - 1) {
-        return; /* wall face */
+        if (g->bc == ORC_BC_DIRICHLET) {
+            long p[3] = {base[0], base[1], base[2]};
+            p[d] = k0 < 0 ? k1 : k0; /* the wall's cell */
+            const long c = cell_index(g, p);
+            const double bd = g->b[d][c];
+            const double dnn = g->chi_perp + (cell_chi(g, U, c) - g->chi_perp) * bd * bd;
+            *alpha = dt_n * dnn / (g->h[d] * g->h[d]);
+        }
+        return 1;
     }
     long p0[3] = {base[0], base[1], base[2]}, p1[3] = {base[0], base[1], base[2]};
     p0[d] = k0;
@@ -299,6 +336,7 @@ static void line_face(const orc_grid *g, const double *U, int d, const long base
         f += beta[t] * transverse_difference(g, U, p0, p1, t);
     }
     *flux = f;
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -306,24 +344,26 @@ static void line_face(const orc_grid *g, const double *U, int d, const long base
 /* ------------------------------------------------------------------ */
 
 /*
- * out = (1 + dt_n D_dd)^-1 (U + transverse fluxes of U at dt_t) along axis
- * d.  Every coefficient is computed from the complete input U before out is
- * written (out must not alias U).  dt_t = 0 is a pure implicit solve.
+ * out = (1 + dt_n D_dd)^-1 (U + transverse fluxes of U at dt_t + dt_q Q)
+ * along axis d.  Every coefficient is computed from the complete input U
+ * before out is written (out must not alias U).  dt_t = 0 is a pure
+ * implicit solve; dt_q = 0 (or no source) adds nothing.
  */
-int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double *U, double *out)
+int orc_sweep3(const orc_grid *g, int d, double dt_n, double dt_t, double dt_q, const double *U, double *out)
 {
     const long n = g->n[d];
     if (g->bc == ORC_BC_PERIODIC && n < 3) return -1;
     if (n < 2) return -1;
     double *alpha = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     double *flux = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    int *wall = (int *)malloc(sizeof(int) * (size_t)(n + 1));
     double *lo = (double *)malloc(sizeof(double) * (size_t)n);
     double *di = (double *)malloc(sizeof(double) * (size_t)n);
     double *up = (double *)malloc(sizeof(double) * (size_t)n);
     double *r = (double *)malloc(sizeof(double) * (size_t)n);
     double *x = (double *)malloc(sizeof(double) * (size_t)n);
     int rc = 0;
-    if (!alpha || !flux || !lo || !di || !up || !r || !x) rc = -1;
+    if (!alpha || !flux || !wall || !lo || !di || !up || !r || !x) rc = -1;
 
     /* the two axes other than d enumerate the lines */
     int ax1 = (d + 1) % 3, ax2 = (d + 2) % 3;
@@ -335,7 +375,7 @@ int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double 
             base[ax2] = l2;
             /* faces k + 1/2 for k = -1 .. n-1; entry k+1 holds face k+1/2 */
             for (long k = -1; k < n; ++k)
-                line_face(g, U, d, base, k, dt_n, dt_t, &alpha[k + 1], &flux[k + 1]);
+                wall[k + 1] = line_face(g, U, d, base, k, dt_n, dt_t, &alpha[k + 1], &flux[k + 1]);
             for (long i = 0; i < n; ++i) {
                 const double am = alpha[i];     /* face i - 1/2 */
                 const double ap = alpha[i + 1]; /* face i + 1/2 */
@@ -344,7 +384,14 @@ int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double 
                 lo[i] = -am;
                 up[i] = -ap;
                 di[i] = 1.0 + am + ap;
-                r[i] = U[cell_index(g, p)] + flux[i + 1] - flux[i];
+                /* a Dirichlet wall face couples the cell to its odd ghost
+                   (x_ghost = -x_cell): 2 alpha on the diagonal, no
+                   off-diagonal entry (insulating walls have alpha = 0) */
+                if (wall[i]) { lo[i] = 0.0; di[i] += am; }
+                if (wall[i + 1]) { up[i] = 0.0; di[i] += ap; }
+                const long c = cell_index(g, p);
+                r[i] = U[c] + flux[i + 1] - flux[i];
+                if (g->src && dt_q != 0.0) r[i] += dt_q * g->src[c];
             }
             if (g->bc == ORC_BC_PERIODIC)
                 rc = orc_cyclic(n, lo, di, up, r, x);
@@ -359,12 +406,18 @@ int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double 
     }
     free(alpha);
     free(flux);
+    free(wall);
     free(lo);
     free(di);
     free(up);
     free(r);
     free(x);
     return rc;
+}
+
+int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double *U, double *out)
+{
+    return orc_sweep3(g, d, dt_n, dt_t, 0.0, U, out);
 }
 
 /* One sweep of the 2-step scheme (Eq. xup / yup): normal and transverse at dt. */
@@ -394,6 +447,7 @@ static int grid_ok(const orc_grid *g)
         if (g->n[q] < 2 || !(g->h[q] > 0.0) || !g->b[q]) return 0;
         if (g->bc == ORC_BC_PERIODIC && g->n[q] < 3) return 0;
     }
+    if (g->bc < ORC_BC_PERIODIC || g->bc > ORC_BC_DIRICHLET) return 0;
     if (g->chi_exp != 0.0 && (!(g->chi_tref > 0.0) || g->chi)) return 0;
     return 1;
 }
@@ -420,11 +474,12 @@ int orc_step_si_ex(const orc_grid *g, double dt, int nsteps, double *T, double *
     for (int s = 0; rc == 0 && s < nsteps; ++s) {
         for (int i = 0; rc == 0 && i < g->ndim; ++i) {
             const int d = (flags & ORC_SI_REVERSE) ? g->ndim - 1 - i : i;
+            const double dt_q = i == 0 ? dt : 0.0; /* the source enters the first sweep */
             if (flags & ORC_SI_FOUR_STEP) {
-                rc = orc_sweep2(g, d, 0.5 * dt, dt, T, tmp);
+                rc = orc_sweep3(g, d, 0.5 * dt, dt, dt_q, T, tmp);
                 if (rc == 0) rc = orc_sweep2(g, d, 0.5 * dt, 0.0, tmp, T);
             } else {
-                rc = orc_sweep(g, d, dt, T, tmp);
+                rc = orc_sweep3(g, d, dt, dt, dt_q, T, tmp);
                 if (rc == 0) memcpy(T, tmp, sizeof(double) * (size_t)N);
             }
         }
@@ -460,7 +515,7 @@ int orc_step_explicit(const orc_grid *g, double dt, int nsteps, double *T, doubl
     if (!nxt) return -1;
     if (energy) energy[0] = orc_energy(g, T);
     for (int s = 0; s < nsteps; ++s) {
-        for (long c = 0; c < N; ++c) nxt[c] = T[c];
+        for (long c = 0; c < N; ++c) nxt[c] = T[c] + (g->src ? dt * g->src[c] : 0.0);
         for (int d = 0; d < g->ndim; ++d) {
             const long n = g->n[d];
             int ax1 = (d + 1) % 3, ax2 = (d + 2) % 3;
@@ -477,7 +532,7 @@ int orc_step_explicit(const orc_grid *g, double dt, int nsteps, double *T, doubl
                         long p[3] = {base[0], base[1], base[2]};
                         p[d] = i;
                         const double tc = T[cell_index(g, p)];
-                        /* at a wall alpha = 0, so the mirrored neighbour adds nothing */
+                        /* at a wall: insulating alpha = 0; Dirichlet uses the odd ghost */
                         const double tp = ghost_value(g, T, p, d, +1);
                         const double tm = ghost_value(g, T, p, d, -1);
                         nxt[cell_index(g, p)] += ap * (tp - tc) - am * (tc - tm) + fp - fm;

@@ -10,7 +10,7 @@ import numpy as np
 
 from . import build as _build
 
-BC = {"periodic": 0, "insulating": 1}
+BC = {"periodic": 0, "insulating": 1, "dirichlet": 2}
 LIMITER = {"vanleer": 0, "minmod": 1, "mc": 2, "linear": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -29,6 +29,7 @@ class _OrcGrid(ctypes.Structure):
         ("chi", _dp),
         ("chi_exp", ctypes.c_double),
         ("chi_tref", ctypes.c_double),
+        ("src", _dp),
     ]
 
 
@@ -55,6 +56,8 @@ def lib():
         L.orc_sweep.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.orc_sweep2.restype = ctypes.c_int
         L.orc_sweep2.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        L.orc_sweep3.restype = ctypes.c_int
+        L.orc_sweep3.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_int] + [ctypes.c_double] * 3 + [_dp, _dp]
         for name in ("orc_step_si", "orc_step_si4", "orc_step_explicit"):
             f = getattr(L, name)
             f.restype = ctypes.c_int
@@ -87,9 +90,11 @@ class OracleGrid:
     """
 
     def __init__(self, b, h, bc="periodic", limiter="vanleer", chi_par=1.0, chi_perp=0.0, chi=None,
-                 chi_exp=0.0, chi_tref=1.0):
+                 chi_exp=0.0, chi_tref=1.0, src=None):
         """chi_exp != 0: temperature-dependent chi_par(T) = chi_par (T / chi_tref)^chi_exp
-        from the state each sweep (or explicit step) reads (chi must then be None)."""
+        from the state each sweep (or explicit step) reads (chi must then be None).
+        bc "dirichlet": T = 0 on the boundary faces.  src: per-cell source Q,
+        dt Q added to the first sweep of each step."""
         self.b = [_f64(c) for c in b]
         self.ndim = len(self.b)
         if self.ndim not in (2, 3):
@@ -105,6 +110,9 @@ class OracleGrid:
         self.chi = None if chi is None else _f64(chi)
         if self.chi is not None and self.chi.shape != self.shape:
             raise ValueError("chi must have the grid shape")
+        self.src = None if src is None else _f64(src)
+        if self.src is not None and self.src.shape != self.shape:
+            raise ValueError("src must have the grid shape")
         s = _OrcGrid()
         s.ndim = self.ndim
         nxyz = tuple(reversed(self.shape)) + (1,) * (3 - self.ndim)
@@ -119,6 +127,7 @@ class OracleGrid:
         s.chi = _ptr(self.chi) if self.chi is not None else _dp()
         s.chi_exp = float(chi_exp)
         s.chi_tref = float(chi_tref)
+        s.src = _ptr(self.src) if self.src is not None else _dp()
         self.chi_exp, self.chi_tref = float(chi_exp), float(chi_tref)
         self._s = s
 
@@ -150,6 +159,16 @@ class OracleGrid:
                               _ptr(U), _ptr(out))
         if rc != 0:
             raise RuntimeError(f"orc_sweep2 failed ({rc})")
+        return out
+
+    def sweep3(self, axis, dt_normal, dt_transverse, dt_source, U):
+        """sweep2 plus dt_source Q on the right-hand side."""
+        U = self._check(U)
+        out = np.empty_like(U)
+        rc = lib().orc_sweep3(ctypes.byref(self._s), int(axis), float(dt_normal), float(dt_transverse),
+                              float(dt_source), _ptr(U), _ptr(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_sweep3 failed ({rc})")
         return out
 
     def step_si(self, T, dt, nsteps=1, energy=False, four_step=False, reverse=False):

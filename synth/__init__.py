@@ -10,6 +10,8 @@ shape (ny, nx) in 2-D or (nz, ny, nx) in 3-D (x fastest).
 
 Workloads (the paper uses no dataset; these stand in for its test problems):
   ring      section 3.1 ring test: circular b on [-1,1]^2, hot patch
+  sovinec   section 3.2 smooth test: T = 0 walls on [-0.5,0.5]^2, source
+            Q = 2 pi^2 cos(pi x) cos(pi y), b along the contours of Q
   grf2d     periodic unit square, b from a Gaussian random vector potential
             A_z (flat spectrum over integer modes 1 <= |m|^2 <= kmax2),
             T = 1 + 0.5 * sum of 8 tanh-edged blobs
@@ -20,6 +22,7 @@ Workloads (the paper uses no dataset; these stand in for its test problems):
 """
 from .fields import (  # noqa: F401
     ring,
+    sovinec,
     grf_unit_field_2d,
     curl_unit_field_3d,
     blobs_2d,
@@ -31,6 +34,7 @@ from .fields import (  # noqa: F401
 from .configs import (  # noqa: F401
     Problem,
     ring_problem,
+    sovinec_problem,
     grf2d_problem,
     curl3d_problem,
     batch_problems,

@@ -14,11 +14,12 @@ class Problem:
     b: Tuple[np.ndarray, ...]
     T0: np.ndarray
     h: Tuple[float, ...]
-    bc: str = "periodic"             # "periodic" | "insulating"
+    bc: str = "periodic"             # "periodic" | "insulating" | "dirichlet"
     limiter: str = "vanleer"         # "vanleer" | "minmod" | "mc" | "linear"
     chi_par: float = 1.0
     chi_perp: float = 0.0
     chi: Optional[np.ndarray] = None  # per-cell chi_par (None: constant)
+    src: Optional[np.ndarray] = None  # per-cell source Q (None: none)
     dt: float = 0.0
     nsteps: int = 1
     meta: dict = field(default_factory=dict)
@@ -51,6 +52,17 @@ def ring_problem(n=64, t_in=12.0, t_out=10.0, ncfl=10.0, nsteps=200, chi_par=0.0
     return Problem("ring", (bx, by), T0, (h, h), bc="insulating", limiter=limiter,
                    chi_par=chi_par, dt=ncfl_dt(ncfl, (h, h), chi_par), nsteps=nsteps,
                    meta=dict(n=n, t_in=t_in, t_out=t_out, ncfl=ncfl))
+
+
+def sovinec_problem(n=64, ncfl=1000.0, nsteps=100, chi_par=1.0, limiter="vanleer"):
+    """Smooth test of section 3.2: [-0.5, 0.5]^2, T = 0 on the walls and at
+    t = 0, source Q = 2 pi^2 cos(pi x) cos(pi y), b along the contours of Q,
+    no explicit chi_perp, 1000x the Courant step.  meta["psi"] holds
+    cos(pi x) cos(pi y) at the cells (the shape of the steady state)."""
+    bx, by, Q, psi, h = fields.sovinec(n)
+    return Problem("sovinec", (bx, by), np.zeros((n, n)), (h, h), bc="dirichlet", limiter=limiter,
+                   chi_par=chi_par, src=Q, dt=ncfl_dt(ncfl, (h, h), chi_par), nsteps=nsteps,
+                   meta=dict(n=n, ncfl=ncfl, psi=psi))
 
 
 def grf2d_problem(nx=1024, ny=None, chi_perp=0.0, ncfl=20.0, nsteps=100, seed_b=20, seed_t=21,

@@ -31,6 +31,27 @@ def ring(n, t_in=10.0, t_out=0.1):
     return bx, by, T0, h
 
 
+def sovinec(n):
+    """Smooth test of section 3.2 on [-0.5, 0.5]^2 with n x n cells: flux
+    function psi = cos(pi x) cos(pi y), B = grad psi x z_hat =
+    (dpsi/dy, -dpsi/dx), b = B/|B| (b = 0 where |B| < 1e-12 max |B|, i.e. at
+    the centre for odd n), source Q = 2 pi^2 psi (so b lies along the
+    contours of Q), T0 = 0.  Returns (bx, by, Q, psi, h)."""
+    h = 1.0 / n
+    c = -0.5 + (np.arange(n) + 0.5) * h
+    x, y = np.meshgrid(c, c, indexing="xy")
+    psi = np.cos(np.pi * x) * np.cos(np.pi * y)
+    Bx = -np.pi * np.cos(np.pi * x) * np.sin(np.pi * y)
+    By = np.pi * np.sin(np.pi * x) * np.cos(np.pi * y)
+    m = np.hypot(Bx, By)
+    ok = m > 1e-12 * m.max()
+    safe = np.where(ok, m, 1.0)
+    bx = np.where(ok, Bx / safe, 0.0)
+    by = np.where(ok, By / safe, 0.0)
+    Q = 2.0 * np.pi ** 2 * psi
+    return bx, by, Q, psi, h
+
+
 def _modes(ndim, kmax2):
     """Integer wave vectors m with 1 <= |m|^2 <= kmax2, one of each +-m pair."""
     k = int(np.floor(np.sqrt(kmax2)))
