@@ -6,10 +6,10 @@
  * scheme beside it as the time-step-limited baseline.
  *
  * Equation solved (section 2, Eqs. aniso_cond and heat_flux, plus an
- * optional isotropic part):
- *     dT/dt = div( D grad T ),   D = chi_perp I + (chi - chi_perp) b b^T,
- * b a given cell-centred unit vector, chi = chi_par (constant) or a per-cell
- * field averaged harmonically at faces.
+ * optional isotropic part and an optional source, section 3.2):
+ *     dT/dt = div( D grad T ) + Q,   D = chi_perp I + (chi - chi_perp) b b^T,
+ * b a given cell-centred unit vector, chi = chi_par (constant), a per-cell
+ * field or chi_par (T / T_ref)^p, averaged harmonically at faces.
  *
  * Conventions shared by every entry point
  *   - Return value: ASD_OK (0) or a negative ASD_E* code.  Nothing throws or
@@ -50,6 +50,10 @@ extern "C" {
 /* boundary conditions (same on every axis) */
 #define ASD_BC_PERIODIC 0    /* periodic box (section 3.3); lines are cyclic tridiagonal systems */
 #define ASD_BC_INSULATING 1  /* reflective walls, dT/dn = 0 (section 3.1); zero flux through wall faces */
+#define ASD_BC_DIRICHLET 2   /* T = 0 on the walls (section 3.2): odd ghost cells (T_ghost = -T_cell),
+                                the wall face's b and chi those of its cell, its normal flux
+                                implicit in the sweeps, no transverse flux through it.  Not for
+                                the adjoint or batched problems */
 
 /* element types */
 #define ASD_F32 0
@@ -67,6 +71,10 @@ extern "C" {
 #define ASD_FIELD_BY 2
 #define ASD_FIELD_BZ 3
 #define ASD_FIELD_CHI 4      /* per-cell chi_par; needs ASD_FLAG_PER_CELL_CHI */
+#define ASD_FIELD_Q 5        /* optional source Q per cell (section 3.2): dt Q joins the right-hand
+                                side of the first sweep of each step (the x sweep; EUNSUPPORTED
+                                with ASD_FLAG_REVERSE_ORDER), forward Euler in the explicit
+                                scheme.  Read in place at every step.  Not for the adjoint */
 
 /* asd_desc.flags */
 #define ASD_FLAG_PER_CELL_CHI 1u   /* chi is a per-cell field, harmonic mean at faces */
@@ -77,7 +85,8 @@ extern "C" {
 /* asd_status flags */
 #define ASD_STATUS_NONFINITE 1u    /* NaN/Inf in energy or T */
 #define ASD_STATUS_NEG_T 2u        /* min T < 0 */
-#define ASD_STATUS_ENERGY_DRIFT 4u /* |E - E0| > 1e-6 |E0| (FP64 sums of the state) */
+#define ASD_STATUS_ENERGY_DRIFT 4u /* |E - E0| > 1e-6 |E0| (FP64 sums of the state); never
+                                      raised with T = 0 walls or a source */
 
 typedef struct asd_grid_s *asd_grid;
 

@@ -19,10 +19,10 @@ ERRORS = {
     -1: "EINVAL", -2: "ESHAPE", -3: "EDTYPE", -4: "ENOTSET", -5: "EWORKSPACE",
     -6: "EUNSTABLE", -7: "EHIP", -8: "EUNSUPPORTED",
 }
-BC = {"periodic": 0, "insulating": 1}
+BC = {"periodic": 0, "insulating": 1, "dirichlet": 2}
 LIMITER = {"vanleer": 0, "minmod": 1, "mc": 2, "linear": 3}
 F32, F64 = 0, 1
-FIELD = {"T": 0, "bx": 1, "by": 2, "bz": 3, "chi": 4}
+FIELD = {"T": 0, "bx": 1, "by": 2, "bz": 3, "chi": 4, "Q": 5}
 FLAG_PER_CELL_CHI = 1
 FLAG_ALLOW_UNSTABLE = 2
 FLAG_FOUR_STEP = 4

@@ -177,6 +177,8 @@ extern "C" int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t c
     if (g->d.flags & (ASD_FLAG_FOUR_STEP | ASD_FLAG_REVERSE_ORDER))
         return asd_fail(ASD_EUNSUPPORTED, "the adjoint is of the 2-step scheme in the order x, y");
     if (g->d.chi_exp != 0.0) return asd_fail(ASD_EUNSUPPORTED, "the adjoint takes a chi that does not depend on T");
+    if (g->d.bc == ASD_BC_DIRICHLET || g->src)
+        return asd_fail(ASD_EUNSUPPORTED, "the adjoint is for periodic or insulating grids without a source");
     if (!dev_adj_ws) return asd_fail(ASD_EWORKSPACE, "adjoint workspace is NULL");
     if ((uintptr_t)dev_adj_ws & 255) return asd_fail(ASD_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
     const AdjPlan pl = adj_plan(g, nsteps, ckpt_every);

@@ -104,6 +104,7 @@ struct asd_grid_s {
     void* T = nullptr;
     void* b[3] = {nullptr, nullptr, nullptr};
     void* chi = nullptr;
+    void* src = nullptr;       // source Q (optional), natural layout
     bool ws_inited = false;
     bool coef_valid = false;   // face coefficients computed for coef_dt
     double coef_dt = 0.0;
@@ -133,6 +134,7 @@ int validate_desc(const asd_desc* d);
 enum : int {
     SWEEP_SOLVE_ONLY = 1,   // right-hand side = U (no transverse term)
     SWEEP_KEEP_LAYOUT = 2,  // output in the input layout
+    SWEEP_SOURCE = 4,       // dt Q joins the right-hand side (input in the natural layout)
 };
 
 template <typename T>

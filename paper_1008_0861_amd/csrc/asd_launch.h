@@ -42,6 +42,10 @@ struct SweepParams {
     int si_n, si_t1, si_t2;  // input strides, elements
     int so_n, so_t1, so_t2;  // output strides, elements
     int periodic;
+    int dirichlet;    // T = 0 walls: odd ghosts; the wrap-face entries of alpha / beta1
+                      // hold the right / left wall coefficients of the line
+    const T* Q;       // source added to the right-hand side (nullptr: none), U's layout
+    T dtq;            // its factor (dt)
     int limiter;
     int wpl;          // waves per line
     int lpw;          // lines per workgroup
@@ -56,7 +60,10 @@ struct SweepParams {
 
 // Face coefficients of the sweep along axis d, written in that sweep's
 // input layout (out strides): for every cell c, the face between c and
-// c + e_d (wrapping when periodic; zero for a wall face).
+// c + e_d (wrapping when periodic; zero for an insulating wall face).  With
+// T = 0 walls the entry of the last cell of each line holds the two wall
+// coefficients: alpha = that of the right wall (from the last cell's b and
+// chi), beta1 = that of the left wall (from the first cell's), beta2 = 0.
 template <typename T>
 struct CoefParams {
     const T* b[3];       // cell-centred b, x-fastest
@@ -71,7 +78,7 @@ struct CoefParams {
     int so[3];           // output stride of axes x, y, z
     double cnn, ct1, ct2;  // dt/h_d^2, dt/(h_d h_t1), dt/(h_d h_t2)
     double chi_par, chi_perp;
-    int periodic, ndim;
+    int periodic, dirichlet, ndim;
 };
 template <typename T>
 hipError_t launch_coef(const CoefParams<T>& C, hipStream_t st);
@@ -101,6 +108,9 @@ struct ExplicitParams {
     T ct[3][3];      // dt / (h_d h_t)
     T chi_par, chi_perp;
     int periodic;
+    int dirichlet;   // T = 0 walls: odd ghosts, wall faces carry normal flux
+    const T* Q;      // source (nullptr: none): out += dtq Q
+    T dtq;
     int limiter;
     ReduceParams red;
 };

@@ -59,6 +59,8 @@ static int check_descs(const asd_desc* descs, int32_t nprob) {
         int rc = validate_desc(&descs[p]);
         if (rc) return rc;
         if (descs[p].ndim != 2) return asd_fail(ASD_EUNSUPPORTED, "batched problems must be 2-D");
+        if (descs[p].bc == ASD_BC_DIRICHLET)
+            return asd_fail(ASD_EUNSUPPORTED, "batched problems are periodic or insulating");
         if (descs[p].bc != descs[0].bc || descs[p].dtype != descs[0].dtype || descs[p].limiter != descs[0].limiter)
             return asd_fail(ASD_EINVAL, "problem %d: bc, dtype and limiter must match problem 0", p);
         if ((descs[p].flags & ASD_FLAG_PER_CELL_CHI) || descs[p].chi_exp != 0.0)

@@ -53,7 +53,7 @@ static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 int validate_desc(const asd_desc* d) {
     if (!d) return asd_fail(ASD_EINVAL, "desc is NULL");
     if (d->ndim != 2 && d->ndim != 3) return asd_fail(ASD_EINVAL, "ndim must be 2 or 3 (got %d)", d->ndim);
-    if (d->bc != ASD_BC_PERIODIC && d->bc != ASD_BC_INSULATING)
+    if (d->bc != ASD_BC_PERIODIC && d->bc != ASD_BC_INSULATING && d->bc != ASD_BC_DIRICHLET)
         return asd_fail(ASD_EINVAL, "bad boundary condition %d", d->bc);
     if (d->dtype != ASD_F32 && d->dtype != ASD_F64) return asd_fail(ASD_EINVAL, "bad dtype %d", d->dtype);
     if (d->limiter < ASD_LIM_VANLEER || d->limiter > ASD_LIM_LINEAR)
@@ -223,6 +223,7 @@ extern "C" int asd_set_field(asd_grid g, int32_t field, void* dev_ptr, int64_t n
             g->chi = dev_ptr;
             g->coef_valid = false;
             break;
+        case ASD_FIELD_Q: g->src = dev_ptr; break;
         default: return asd_fail(ASD_EINVAL, "unknown field %d", field);
     }
     g->graph_valid = false;
@@ -297,6 +298,7 @@ static int enqueue_coef_t(asd_grid g, int d, double dt, const void* U) {
     C.chi_par = g->d.chi_par;
     C.chi_perp = g->d.chi_perp;
     C.periodic = g->d.bc == ASD_BC_PERIODIC;
+    C.dirichlet = g->d.bc == ASD_BC_DIRICHLET;
     C.ndim = nd;
     return hip_check(launch_coef<T>(C, g->st), "coefficient launch");
 }
@@ -348,7 +350,8 @@ FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count,
     f.series_out = out.series ? out.series + 3 * first : nullptr;
     f.stats_out = g->stats;
     f.flags = g->flags;
-    f.e0 = first > 0 ? out.e0() : nullptr;
+    // the energy is conserved only without T = 0 walls and sources
+    f.e0 = first > 0 && g->d.bc != ASD_BC_DIRICHLET && !g->src ? out.e0() : nullptr;
     double dv = 1.0;
     for (int q = 0; q < g->d.ndim; ++q) dv *= g->d.h[q];
     f.dV = dv;
@@ -381,6 +384,7 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.so_t1 = (int)layout_stride(g, Lout, G.t1);
     P.so_t2 = (int)layout_stride(g, Lout, G.t2);
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
+    P.dirichlet = g->d.bc == ASD_BC_DIRICHLET;
     P.limiter = g->d.limiter;
     P.wpl = c.wpl;
     P.lpw = c.lpw;
@@ -400,11 +404,17 @@ template int fill_sweep_params<double>(asd_grid, int, const void*, void*, int, c
 template <typename T>
 static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
                            const ReduceParams& red, const SweepCfg* override_cfg, int* nblocks_out) {
-    (void)dt;  // the coefficients were computed for dt by prepare()
+    // the coefficients were computed for dt by prepare() (or enqueue_coef)
     const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
     SweepParams<T> P;
     int rc = fill_sweep_params<T>(g, d, in, out, rhs_mode, c, &P);
     if (rc) return rc;
+    if ((rhs_mode & SWEEP_SOURCE) && g->src) {
+        if (sweep_geom(g->d.ndim, d).Lin != 0)
+            return asd_fail(ASD_EUNSUPPORTED, "the source enters a sweep that reads the natural layout");
+        P.Q = (const T*)g->src;
+        P.dtq = (T)dt;
+    }
     P.red = red;
     const int nb1 = (P.nt1 + c.lpw - 1) / c.lpw;
     const int64_t nblocks = (int64_t)nb1 * P.nt2;
@@ -451,6 +461,9 @@ int enqueue_fold(asd_grid g, const FoldParams& f) {
 
 static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
     if (!finite_pos(dt)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
+    // the source enters the first sweep, which must read the natural layout
+    if (!explicit_scheme && g->src && (g->d.flags & ASD_FLAG_REVERSE_ORDER))
+        return asd_fail(ASD_EUNSUPPORTED, "a source term needs the sweep order x, y");
     // chi(T): the diffusivity follows the state, the caller bounds dt
     if ((g->d.flags & ASD_FLAG_ALLOW_UNSTABLE) || g->d.chi_exp != 0.0) return ASD_OK;
     const double chi = g->d.chi_par;
@@ -501,6 +514,7 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
         for (int i = 0; i < nd && rc == ASD_OK; ++i) {
             const int d = reverse ? nd - 1 - i : i;
             const bool produce = outs.any() && i == nd - 1;
+            const int src = i == 0 ? SWEEP_SOURCE : 0;  // dt Q joins the first sweep
             ReduceParams red = no_reduce();
             if (produce) red.partials = ring_slot(g, used);
             int nb = 0;
@@ -510,21 +524,21 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
                 // intermediate (input layout) goes to T, free meanwhile.
                 out = d == 1 ? g->tmp[0] : g->tmp[1];
                 if (!four) {
-                    rc = sweep(d, in, out, 0, red, &nb);
+                    rc = sweep(d, in, out, src, red, &nb);
                 } else {
-                    rc = sweep(d, in, g->T, SWEEP_KEEP_LAYOUT, no_reduce(), nullptr);
+                    rc = sweep(d, in, g->T, SWEEP_KEEP_LAYOUT | src, no_reduce(), nullptr);
                     if (rc == ASD_OK) rc = sweep(d, g->T, out, SWEEP_SOLVE_ONLY, red, &nb);
                 }
             } else if (!four) {
                 out = (d == nd - 1) ? g->T : g->tmp[d];
-                rc = sweep(d, in, out, 0, red, &nb);
+                rc = sweep(d, in, out, src, red, &nb);
             } else {
                 // 4-step: transverse term at dt with the first half-step
                 // solve, written in the input layout, then the second
                 // half-step solve into the next sweep's layout.  States:
                 // T -> tmp0 (-> T in 3-D) -> T.
                 out = d == 0 ? g->tmp[0] : g->T;
-                rc = sweep(d, in, g->tmp[1], SWEEP_KEEP_LAYOUT, no_reduce(), nullptr);
+                rc = sweep(d, in, g->tmp[1], SWEEP_KEEP_LAYOUT | src, no_reduce(), nullptr);
                 if (rc == ASD_OK) rc = sweep(d, g->tmp[1], out, SWEEP_SOLVE_ONLY, red, &nb);
             }
             if (rc == ASD_OK && produce && (++used == g->ring_slots || s == nsteps - 1)) {
@@ -578,6 +592,9 @@ static int enqueue_explicit_t(asd_grid g, double dt, const void* src, void* dst,
     P.chi_exp = g->d.chi_exp;
     P.chi_tref = g->d.chi_tref;
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
+    P.dirichlet = g->d.bc == ASD_BC_DIRICHLET;
+    P.Q = (const T*)g->src;
+    P.dtq = (T)dt;
     P.limiter = g->d.limiter;
     P.red = red;
     return hip_check(launch_explicit<T>(P, g->d.ndim, g->st, nblocks_out), "explicit launch");

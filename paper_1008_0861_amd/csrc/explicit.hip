@@ -4,7 +4,11 @@
 //   T^{n+1}_c = T^n_c + sum_d [ alpha_{c+1/2}(T_{c+e} - T_c) - alpha_{c-1/2}(T_c - T_{c-e})
 //                               + F_{c+1/2} - F_{c-1/2} ]
 //
-// with alpha_f and F_f defined exactly as in the semi-implicit sweep.
+// with alpha_f and F_f defined exactly as in the semi-implicit sweep (plus
+// dt Q with a source).  T = 0 walls stage odd ghosts (-U, with the cell's b
+// and chi) in the halo, so a wall face takes the normal flux
+// alpha_w (-U_c - U_c) and a transverse flux that vanishes (the limited
+// difference of a cell and its odd ghost is zero).
 //
 // gfx950 mapping: one workgroup per tile of TX x TY x TZ cells.  The tile
 // plus a one-cell halo of U, b (and chi) is staged through LDS with
@@ -41,6 +45,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     const int y0 = (blk % gy) * TL::TY;
     const int z0 = (blk / gy) * TL::TZ;
     const bool periodic = P.periodic != 0;
+    const bool dir = P.dirichlet != 0;
     const int lim = P.limiter;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
 
@@ -49,16 +54,21 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     constexpr int IT = (TL::NB + TL::NT - 1) / TL::NT;
     {
         T vu[IT], vb[NDIM][IT], vc[IT];
+        bool vneg[IT];
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
             const int i = threadIdx.x + j * TL::NT;
             const int ii = i < TL::NB ? i : 0;
             const int bx = ii % TL::BX, by = (ii / TL::BX) % TL::BY, bz = ii / (TL::BX * TL::BY);
             // cells beyond the far edge of a partial tile map to valid cells (never used)
-            const int64_t x = nb_coord(x0 - 1 + bx, nx, periodic);
-            const int64_t y = nb_coord(y0 - 1 + by, ny, periodic);
-            const int64_t z = NDIM == 3 ? nb_coord(z0 - 1 + bz, nz, periodic) : 0;
+            const int gx0 = x0 - 1 + bx, gy0 = y0 - 1 + by, gz0 = z0 - 1 + bz;
+            const int64_t x = nb_coord(gx0, nx, periodic);
+            const int64_t y = nb_coord(gy0, ny, periodic);
+            const int64_t z = NDIM == 3 ? nb_coord(gz0, nz, periodic) : 0;
             const int64_t c = x + y * sy + z * sz;
+            // odd ghost: one sign flip per axis on which the cell lies outside
+            const int nout = (x != gx0) + (y != gy0) + (NDIM == 3 && z != gz0);
+            vneg[j] = dir && (nout & 1);
             vu[j] = P.U[c];
 #pragma unroll
             for (int d = 0; d < NDIM; ++d) vb[d][j] = P.b[d][c];
@@ -68,7 +78,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
         for (int j = 0; j < IT; ++j) {
             const int i = threadIdx.x + j * TL::NT;
             if (i >= TL::NB) continue;
-            sU[i] = vu[j];
+            sU[i] = vneg[j] ? -vu[j] : vu[j];
 #pragma unroll
             for (int d = 0; d < NDIM; ++d) sB[d][i] = vb[d][j];
             if (P.chi) sChi[i] = vc[j];
@@ -109,7 +119,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
                 const int i0 = side ? bi : bi - bstr[d];
                 const int i1 = i0 + bstr[d];
                 const int g0 = side ? gc[d] : gc[d] - 1;
-                const bool wall = !periodic && (g0 < 0 || g0 + 1 > P.n[d] - 1);
+                const bool wall = !periodic && !dir && (g0 < 0 || g0 + 1 > P.n[d] - 1);
                 if (wall) continue;
                 const T bnf = T(0.5) * (sB[d][i0] + sB[d][i1]);
                 T chif = P.chi_par;
@@ -129,8 +139,9 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
                 acc += side ? (alpha * diff + flux) : -(alpha * diff + flux);
             }
         }
-        const T un = uc + acc;
-        P.out[(int64_t)x + y * sy + (int64_t)z * sz] = un;
+        const int64_t co = (int64_t)x + y * sy + (int64_t)z * sz;
+        const T un = P.Q ? (uc + P.dtq * P.Q[co]) + acc : uc + acc;
+        P.out[co] = un;
         lsum = (double)un;
         lmin = lmax = (double)un;
     }

@@ -5,7 +5,7 @@
 
 namespace asd {
 
-template <typename T, int NDIM, int MMAX, int LIMC>
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
 __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_kernel(SweepParams<T> P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // XCD-aware block order: consecutive logical blocks on the same XCD so
@@ -19,22 +19,26 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_ker
     const int l1_0 = (blk - l2 * nb1) * P.lpw;
     double lsum;
     T lmin, lmax;
-    sweep_tile<T, NDIM, MMAX, LIMC>(P, l1_0, l2, smem_raw, lsum, lmin, lmax);
+    sweep_tile<T, NDIM, MMAX, LIMC, EXT>(P, l1_0, l2, smem_raw, lsum, lmin, lmax);
     // FP64 energy / min / max partials (folded by a later launch)
     if (P.red.partials) block_partials<T>(P.red.partials, lsum, lmin, lmax);
 }
 
 // Van Leer (the default limiter) gets its own straight-line instantiation;
-// the other limiters share one that reads the limiter at run time.
+// the other limiters share one that reads the limiter at run time, and T = 0
+// walls or a source take a third that also reads those.
 template <typename T, int NDIM>
 static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid, dim3 block, size_t lds,
                                    hipStream_t st) {
-#define ASD_SWEEP_CASE(MM)                                                                     \
-    case MM:                                                                                   \
-        if (P.limiter == LIM_VANLEER)                                                          \
-            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, LIM_VANLEER>), grid, block, lds, st, P); \
-        else                                                                                   \
-            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1>), grid, block, lds, st, P);      \
+    const bool ext = P.dirichlet || P.Q;
+#define ASD_SWEEP_CASE(MM)                                                                          \
+    case MM:                                                                                        \
+        if (ext)                                                                                    \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1, true>), grid, block, lds, st, P);     \
+        else if (P.limiter == LIM_VANLEER)                                                          \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, LIM_VANLEER, false>), grid, block, lds, st, P); \
+        else                                                                                        \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1, false>), grid, block, lds, st, P);    \
         return hipGetLastError();
     switch (mmax) {
         ASD_SWEEP_CASE(1)
@@ -49,11 +53,11 @@ static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid,
 
 // Raise the dynamic-LDS limit of every sweep instantiation to the gfx950
 // maximum.  Called once per process, before any launch or stream capture.
-template <typename T, int NDIM, int LIMC>
+template <typename T, int NDIM, int LIMC, bool EXT>
 static hipError_t set_attrs_lim(int bytes) {
-    const void* fns[] = {(const void*)sweep_kernel<T, NDIM, 1, LIMC>, (const void*)sweep_kernel<T, NDIM, 2, LIMC>,
-                         (const void*)sweep_kernel<T, NDIM, 4, LIMC>, (const void*)sweep_kernel<T, NDIM, 8, LIMC>,
-                         (const void*)sweep_kernel<T, NDIM, 16, LIMC>};
+    const void* fns[] = {(const void*)sweep_kernel<T, NDIM, 1, LIMC, EXT>, (const void*)sweep_kernel<T, NDIM, 2, LIMC, EXT>,
+                         (const void*)sweep_kernel<T, NDIM, 4, LIMC, EXT>, (const void*)sweep_kernel<T, NDIM, 8, LIMC, EXT>,
+                         (const void*)sweep_kernel<T, NDIM, 16, LIMC, EXT>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -62,8 +66,9 @@ static hipError_t set_attrs_lim(int bytes) {
 }
 template <typename T, int NDIM>
 static hipError_t set_attrs_dim(int bytes) {
-    hipError_t e = set_attrs_lim<T, NDIM, LIM_VANLEER>(bytes);
-    if (e == hipSuccess) e = set_attrs_lim<T, NDIM, -1>(bytes);
+    hipError_t e = set_attrs_lim<T, NDIM, LIM_VANLEER, false>(bytes);
+    if (e == hipSuccess) e = set_attrs_lim<T, NDIM, -1, false>(bytes);
+    if (e == hipSuccess) e = set_attrs_lim<T, NDIM, -1, true>(bytes);
     return e;
 }
 

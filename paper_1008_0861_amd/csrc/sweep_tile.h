@@ -10,7 +10,12 @@
 //     F_f     = sum_t beta_t,f L(s_t(p+1), s_t(p))  beta_t,f = dt D_nt,f/(h_n h_t)
 //     s_t(c)  = L(U[c+e_t] - U[c], U[c] - U[c-e_t])  (limited cell slope)
 // Wall faces (insulating walls) have alpha = beta = 0 in the coefficient
-// arrays, so every line is handled as a cyclic system.
+// arrays, so every line is handled as a cyclic system.  T = 0 walls use odd
+// ghosts (U[-1] = -U[0]): the transverse neighbours of a wall line are
+// negated copies, and a wall face of cell c adds 2 alpha_w to its diagonal
+// and -2 alpha_w U_c to its right-hand side (no coupling across the wrap);
+// the two alpha_w of a line arrive in its wrap-face coefficient entry.  A
+// source adds dt Q to U in the right-hand side (not in the slopes).
 //
 // gfx950 mapping.  A workgroup owns `lpw` neighbouring lines; each line is
 // owned by `wpl` waves (a wave never spans two lines, so every per-line
@@ -33,7 +38,9 @@
 // dominant M-matrices: no pivoting anywhere.
 //
 // LIMC: the limiter as a compile-time constant (straight-line code), or -1
-// to read it from the parameters.
+// to read it from the parameters.  EXT: compile in T = 0 walls and the
+// source term (read from the parameters); without it that code is absent
+// and the host never passes either.
 #pragma once
 
 #include "asd_device.h"
@@ -53,12 +60,13 @@ struct TileCtx {
     unsigned char* buf;
     unsigned char* row1;
     unsigned char* row2;
-    const T *gU, *gU1m, *gU1p, *gU2m, *gU2p, *gA, *gB1, *gB2;
+    const T *gU, *gU1m, *gU1p, *gU2m, *gU2p, *gA, *gB1, *gB2, *gQ;
+    int neg1m, neg1p, neg2m, neg2p;  // T = 0 walls: that transverse neighbour is the odd ghost
     int ok1, ok2;        // LDS offsets of the thread's first cell (k) in its line's rows
     int ostep1, ostep2;  // LDS bytes between cells spl apart
 };
 
-template <typename T, int NDIM>
+template <typename T, int NDIM, bool EXT>
 __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0, int l2, unsigned char* buf) {
     constexpr int ES = (int)sizeof(T);
     const TileLayout& Lo = P.lds;
@@ -89,6 +97,11 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0
             base2p = base + (int)(nb_coord(l2 + 1, P.nt2, periodic) - l2) * P.si_t2;
         }
     }
+    const bool dir = EXT && P.dirichlet != 0;
+    c.neg1m = dir && l1 == 0;
+    c.neg1p = dir && l1 == P.nt1 - 1;
+    c.neg2m = dir && NDIM == 3 && l2 == 0;
+    c.neg2p = dir && NDIM == 3 && l2 == P.nt2 - 1;
     c.gU = P.U + base;
     c.gU1m = P.U + base1m;
     c.gU1p = P.U + base1p;
@@ -97,6 +110,7 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0
     c.gA = P.alpha + base;
     c.gB1 = P.beta1 + base;
     c.gB2 = NDIM == 3 ? P.beta2 + base : nullptr;
+    c.gQ = EXT && P.Q ? P.Q + base : nullptr;
     // spl is a multiple of the pad period, so cells spl apart are a fixed
     // number of bytes apart in LDS
     c.ok1 = cell_off1(c.k, ES, pad);
@@ -109,14 +123,14 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0
 // Global data of CH of the thread's cells (k + (it0 + j) spl, j < CH).
 template <typename T, int NDIM, int CH>
 struct CellLoads {
-    T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH];
+    T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH], q[CH];
 };
 
 // ---------------- phase 1a: coalesced loads of a chunk of cells.  Lane k of
 // the line takes cells k, k+spl, ... (at most MMAX of them: the host
 // guarantees n <= MMAX*spl).  All loads are issued before any is used; cells
 // past the line end are clamped to the line's last cell.
-template <typename T, int NDIM, int CH>
+template <typename T, int NDIM, int CH, bool EXT>
 __device__ __forceinline__ void load_cells(const SweepParams<T>& P, const TileCtx<T>& c, int it0,
                                            CellLoads<T, NDIM, CH>& r) {
     constexpr int ES = (int)sizeof(T);
@@ -127,6 +141,9 @@ __device__ __forceinline__ void load_cells(const SweepParams<T>& P, const TileCt
         const unsigned bo = min(p, (unsigned)(P.n - 1)) * (unsigned)ES;
         r.u[j] = ldg_off(c.gU, bo);
         r.va[j] = ldg_off(c.gA, bo);
+        // T = 0 walls need beta1 of the last cell (the left wall) in every sweep
+        if (EXT && solve_only && P.dirichlet) r.vb1[j] = ldg_off(c.gB1, bo);
+        if (EXT && P.Q) r.q[j] = ldg_off(c.gQ, bo);
         if (!solve_only) {
             r.u1m[j] = ldg_off(c.gU1m, bo);
             r.u1p[j] = ldg_off(c.gU1p, bo);
@@ -142,7 +159,7 @@ __device__ __forceinline__ void load_cells(const SweepParams<T>& P, const TileCt
 
 // ---------------- phase 1b: limited transverse slopes, packed into the
 // cells' LDS slots (and the copy of cell 0 after the last cell).
-template <typename T, int NDIM, int CH, int LIMC>
+template <typename T, int NDIM, int CH, int LIMC, bool EXT>
 __device__ __forceinline__ void stage_cells(const SweepParams<T>& P, const TileCtx<T>& c, int it0,
                                             const CellLoads<T, NDIM, CH>& r) {
     constexpr int ES = (int)sizeof(T);
@@ -157,18 +174,32 @@ __device__ __forceinline__ void stage_cells(const SweepParams<T>& P, const TileC
         // solve-only sweeps store zero slopes and transverse coefficients:
         // their transverse flux is then exactly zero
         T s1 = T(0), b1 = T(0), s2 = T(0), b2 = T(0);
+        const T u = r.u[j];
         if (!solve_only) {
-            s1 = cell_slope<T>(lim, r.u1m[j], r.u[j], r.u1p[j]);
+            s1 = EXT ? cell_slope<T>(lim, c.neg1m ? -u : r.u1m[j], u, c.neg1p ? -u : r.u1p[j])
+                     : cell_slope<T>(lim, r.u1m[j], u, r.u1p[j]);
             b1 = r.vb1[j];
             if (NDIM == 3) {
-                s2 = cell_slope<T>(lim, r.u2m[j], r.u[j], r.u2p[j]);
+                s2 = EXT ? cell_slope<T>(lim, c.neg2m ? -u : r.u2m[j], u, c.neg2p ? -u : r.u2p[j])
+                         : cell_slope<T>(lim, r.u2m[j], u, r.u2p[j]);
                 b2 = r.vb2[j];
             }
         }
-        lds_put4<T>(c.row1 + c.ok1 + (it0 + j) * c.ostep1, s1, r.va[j], b1, r.u[j]);
+        // the right-hand side's U (the slopes above use the state itself)
+        const T us = EXT && P.Q ? u + P.dtq * r.q[j] : u;
+        T a = r.va[j];
+        if (EXT && P.dirichlet && p == n - 1) {
+            // wrap face: no coupling and no transverse flux; its two wall
+            // coefficients and this cell's U go to the spare slot after the
+            // copy of cell 0
+            lds_put4<T>(c.row1 + cell_off1(n + 1, ES, P.lds.pad), r.vb1[j], a, us, T(0));
+            a = T(0);
+            b1 = T(0);
+        }
+        lds_put4<T>(c.row1 + c.ok1 + (it0 + j) * c.ostep1, s1, a, b1, us);
         if (NDIM == 3) lds_put2<T>(c.row2 + c.ok2 + (it0 + j) * c.ostep2, s2, b2);
         if (p == 0) {  // the copy of cell 0 after the last cell
-            lds_put4<T>(c.row1 + cell_off1(n, ES, P.lds.pad), s1, r.va[j], b1, r.u[j]);
+            lds_put4<T>(c.row1 + cell_off1(n, ES, P.lds.pad), s1, a, b1, us);
             if (NDIM == 3) lds_put2<T>(c.row2 + cell_off2(n, ES, P.lds.pad), s2, b2);
         }
     }
@@ -178,7 +209,7 @@ __device__ __forceinline__ void stage_cells(const SweepParams<T>& P, const TileC
 // ends with a barrier so that the tile's LDS buffer may be refilled.
 // smem: the block's LDS base (exchange buffers).  Returns the thread's FP64
 // sum and min / max of the values it wrote.
-template <typename T, int NDIM, int MMAX, int LIMC>
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
 __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileCtx<T>& ctx, unsigned char* smem,
                                             double& lsum, T& lmin, T& lmax) {
     constexpr int ES = (int)sizeof(T);
@@ -265,6 +296,26 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
             }
             alpha_prev = ca[f];
             phi_prev = phi;
+        }
+    }
+    // T = 0 walls: the wall faces of the line's first and last cells (the
+    // rows above saw zero coupling and flux across the wrap face)
+    if (EXT && P.dirichlet && active && (s0 == 0 || s0 + m == n)) {
+        T aL, aR, uR, unused;
+        lds_get4<T>(row1 + cell_off1(n + 1, ES, pad), aL, aR, uR, unused);
+        if (s0 == 0) {
+            const T e = T(2) * aL;
+            bv[0] += e;
+            rv[0] -= e * cu[1];
+            if (m == 1) {
+                be += e;
+                re -= e * cu[1];
+            }
+        }
+        if (s0 + m == n) {
+            const T e = T(2) * aR;
+            be += e;
+            re -= e * uR;
         }
     }
     // interior elimination: x_i = g_i - h_i x_{i+1} + w_i X_left, i = 0..m-2
@@ -457,20 +508,20 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
 
 // One whole tile (phases 1-3) in LDS buffer 0, loading in chunks of up to 8
 // cells per thread.
-template <typename T, int NDIM, int MMAX, int LIMC>
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT = false>
 __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem,
                                            double& lsum, T& lmin, T& lmax) {
-    const TileCtx<T> c = tile_ctx<T, NDIM>(P, l1_0, l2, smem);
+    const TileCtx<T> c = tile_ctx<T, NDIM, EXT>(P, l1_0, l2, smem);
     constexpr int CH = MMAX < 8 ? MMAX : 8;
 #pragma unroll
     for (int it0 = 0; it0 < MMAX; it0 += CH) {
         if ((it0 << P.spl_log2) >= P.n) break;
         CellLoads<T, NDIM, CH> r;
-        load_cells<T, NDIM, CH>(P, c, it0, r);
-        stage_cells<T, NDIM, CH, LIMC>(P, c, it0, r);
+        load_cells<T, NDIM, CH, EXT>(P, c, it0, r);
+        stage_cells<T, NDIM, CH, LIMC, EXT>(P, c, it0, r);
     }
     __syncthreads();
-    solve_store<T, NDIM, MMAX, LIMC>(P, c, smem, lsum, lmin, lmax);
+    solve_store<T, NDIM, MMAX, LIMC, EXT>(P, c, smem, lsum, lmin, lmax);
 }
 
 }  // namespace asd

@@ -41,6 +41,8 @@ def test_header_constants_match_binding(asd):
     consts = dict(re.findall(r"#define (ASD_\w+) \(?(-?\d+)u?\)?", src))
     assert int(consts["ASD_BC_PERIODIC"]) == asd.BC["periodic"]
     assert int(consts["ASD_BC_INSULATING"]) == asd.BC["insulating"]
+    assert int(consts["ASD_BC_DIRICHLET"]) == asd.BC["dirichlet"]
+    assert int(consts["ASD_FIELD_Q"]) == asd.FIELD["Q"]
     assert int(consts["ASD_LIM_MC"]) == asd.LIMITER["mc"]
     assert int(consts["ASD_FIELD_CHI"]) == asd.FIELD["chi"]
     for code, name in asd.ERRORS.items():
@@ -189,4 +191,13 @@ def test_batch_refuses_chi_of_T(asd):
     assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == -8
     assert "constant chi_par" in asd.last_error()
     rc, _ = _rc_ws(asd, _desc(asd, chi_exp=2.5, chi_tref=1.0))
+    assert rc == 0
+
+
+def test_batch_refuses_dirichlet(asd):
+    descs = (asd.Desc * 2)(_desc(asd), _desc(asd, bc="dirichlet"))
+    n = ctypes.c_size_t()
+    assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == -8
+    assert "periodic or insulating" in asd.last_error()
+    rc, _ = _rc_ws(asd, _desc(asd, bc="dirichlet", shape=(2, 2), h=(1.0, 1.0)))
     assert rc == 0
