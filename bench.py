@@ -291,6 +291,66 @@ def ring512(stream, torch, asd):
     return out
 
 
+def sovinec(stream, torch, asd):
+    """Smooth test of section 3.2 (T = 0 walls on [-0.5, 0.5]^2, source
+    2 pi^2 cos(pi x) cos(pi y), b along its contours, no explicit chi_perp),
+    FP64, run to steady state: chi_perp,num / chi_par = psi / T at the hottest
+    cell, psi = cos(pi x) cos(pi y).  The approach to steady state is
+    dominated by the slowest mode, T_max(t) = T_inf - A exp(-lambda t), so
+    T_inf is extrapolated from three equally spaced maxima (Aitken's delta^2)
+    once successive estimates agree to 1e-7.  ncfl = 1000 at n = 16 .. 128
+    (the paper reports close to second-order convergence at ncfl = 1000) and
+    n = 256 at ncfl = 10^4 (the paper finds chi_perp,num nearly independent
+    of ncfl there; n = 256 at ncfl = 1000 needs about 1.6 million steps, too
+    many for this run)."""
+    import math
+
+    import numpy as np
+    import synth
+
+    def run(n, ncfl):
+        p = synth.sovinec_problem(n, ncfl=ncfl)
+        with torch.cuda.stream(stream):
+            g = asd.Grid(p.shape, p.h, bc="dirichlet", dtype=torch.float64, chi_par=p.chi_par)
+            b = [torch.from_numpy(c).cuda() for c in p.b]
+            T = torch.zeros(p.shape, dtype=torch.float64, device="cuda")
+            Q = torch.from_numpy(p.src).cuda()
+            g.set_b(*b)
+            g.set_field("T", T)
+            g.set_field("Q", Q)
+        # chunk: about 1/20 of the slowest mode's decay time for a second-order
+        # guess of chi_perp,num, at least 200 steps
+        lam_dt = 2 * math.pi ** 2 * 0.25 / n ** 2 * p.dt
+        chunk = max(200, int(0.05 / lam_dt))
+        print(f"bench: sovinec n={n} ncfl={ncfl:g} chunk={chunk}", file=sys.stderr, flush=True)
+        maxima, est, steps, t0 = [], [], 0, time.perf_counter()
+        for _ in range(4000):
+            with torch.cuda.stream(stream):
+                g.step_semi_implicit(p.dt, chunk)
+                _, (_, _, tmax) = g.status()
+            steps += chunk
+            maxima.append(tmax)
+            if len(maxima) >= 3:
+                d1, d2 = maxima[-2] - maxima[-3], maxima[-1] - maxima[-2]
+                inf = maxima[-1] - d2 * d2 / (d2 - d1) if d2 != d1 else maxima[-1]
+                est.append(inf)
+                if abs(d2) < 1e-12 * tmax or (len(est) >= 2 and abs(est[-1] - est[-2]) < 1e-7 * abs(est[-1])):
+                    break
+        ms = (time.perf_counter() - t0) * 1e3
+        Th = T.cpu().numpy()
+        i = np.unravel_index(np.argmax(Th), Th.shape)
+        t_inf = est[-1] if est else maxima[-1]
+        return dict(n=n, ncfl=ncfl, steps=steps, chi_perp_num=float(p.meta["psi"][i] / t_inf),
+                    ms=round(ms, 1))
+
+    rows = [run(n, 1000.0) for n in (16, 32, 64, 128)]
+    for lo, hi in zip(rows, rows[1:]):
+        hi["order_vs_previous"] = round(math.log2(lo["chi_perp_num"] / hi["chi_perp_num"]), 3)
+    r256 = run(256, 1e4)
+    r256["order_vs_previous"] = round(math.log2(rows[-1]["chi_perp_num"] / r256["chi_perp_num"]), 3)
+    return dict(ncfl1000=rows, n256_ncfl1e4=r256)
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle, serial on one host core, on the same 1024^2 workload:
     as many whole steps as fit in about budget_s seconds (at least 2)."""
@@ -414,6 +474,7 @@ def main():
         extra["curl3d_256"] = three_d(stream, torch, asd)
         extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
         extra["ring512"] = ring512(stream, torch, asd)
+        extra["sovinec"] = sovinec(stream, torch, asd)
         result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()

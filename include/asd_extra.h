@@ -78,7 +78,10 @@ int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw);
  * fastest.  Needs T and b set.  Synchronises the stream. */
 int asd_tune(asd_grid g, double dt, int32_t reps);
 
-/* Enable (1) or disable (0) hipGraph capture of multi-step calls. */
+/* Enable (1) or disable (0) hipGraph capture of multi-step calls (on by
+ * default; used only with a non-default stream).  A graph holds at most 2048
+ * steps: longer calls replay it and launch the remainder directly, or, when
+ * they produce per-step outputs, launch every step directly. */
 int asd_set_graphs(asd_grid g, int32_t on);
 
 /* ------------------------------------------------------------ measurement

@@ -1,7 +1,11 @@
 // hipGraph capture of step loops.  A loop of nsteps steps is captured once
 // per (scheme, dt, nsteps, output pointers) and replayed, so a
 // long run costs one graph launch instead of 2-3 kernel launches per step.
-// Only kernels are captured (no memset or memcpy nodes).
+// Only kernels are captured (no memset or memcpy nodes).  One graph holds
+// at most kGraphMaxSteps steps: a longer call without per-step outputs
+// replays a graph of that many steps and launches the remainder directly;
+// a longer call with per-step outputs (every step writes its own entry, so
+// no graph can be replayed) is launched directly.
 #include <hip/hip_runtime.h>
 
 #include "asd_internal.h"
@@ -46,7 +50,24 @@ static int run_graph(asd_grid g, int kind, double dt, int nsteps, const StepOut&
     return ASD_OK;
 }
 
-int run_si_graph(asd_grid g, double dt, int nsteps, const StepOut& out) { return run_graph(g, 1, dt, nsteps, out); }
+static constexpr int kGraphMaxSteps = 2048;
+
+static int run_graph_chunked(asd_grid g, int kind, double dt, int nsteps, const StepOut& out) {
+    auto direct = [&](int n) {
+        return kind == 1 ? enqueue_si_loop(g, dt, n, out) : enqueue_explicit_loop(g, dt, n, out);
+    };
+    if (nsteps <= kGraphMaxSteps) return run_graph(g, kind, dt, nsteps, out);
+    if (out.any()) return direct(nsteps);
+    int rc = ASD_OK, done = 0;
+    for (; rc == ASD_OK && nsteps - done >= kGraphMaxSteps; done += kGraphMaxSteps)
+        rc = run_graph(g, kind, dt, kGraphMaxSteps, out);
+    if (rc == ASD_OK && done < nsteps) rc = direct(nsteps - done);
+    return rc;
+}
+
+int run_si_graph(asd_grid g, double dt, int nsteps, const StepOut& out) {
+    return run_graph_chunked(g, 1, dt, nsteps, out);
+}
 int run_explicit_graph(asd_grid g, double dt, int nsteps, const StepOut& out) {
-    return run_graph(g, 2, dt, nsteps, out);
+    return run_graph_chunked(g, 2, dt, nsteps, out);
 }
