@@ -105,7 +105,7 @@ typedef struct {
     uint32_t reserved; /* must be 0 */
     double chi_exp;   /* 0: chi_par constant (or per cell).  != 0: temperature-dependent
                          chi_par(T) = chi_par (T / chi_tref)^chi_exp (chi ~ T^(5/2) in the
-                         paper's application, section 4), per cell from the state each sweep
+                         paper's application, section 3.3), per cell from the state each sweep
                          (or explicit step) reads, harmonic mean at faces; 0 < chi_exp <= 8,
                          T > 0, no per-cell chi, no EUNSTABLE checks (the caller picks dt),
                          not for the adjoint or batched problems */

@@ -41,7 +41,7 @@
  *     (a,b) taken from the cell on the + side of the face;
  *   - the explicit limited step is forward Euler of the same unsplit
  *     operator, every face evaluated from T^n;
- *   - temperature-dependent chi_par (chi ~ T^(5/2), section 4): per-cell
+ *   - temperature-dependent chi_par (chi ~ T^(5/2), section 3.3): per-cell
  *     values from the state the sweep reads (T^n, T*, ...), harmonic mean
  *     at each face, as for a per-cell chi field;
  *   - fixed-temperature walls (T = 0 on the boundary, the smooth test of
@@ -77,7 +77,7 @@ typedef struct {
     const double *b[3]; /* cell-centred components of the unit vector b */
     const double *chi;  /* optional per-cell chi_par (NULL: constant) */
     double chi_exp;     /* != 0: chi_par(T) = chi_par (T / chi_tref)^chi_exp, from the */
-    double chi_tref;    /*       state the sweep (or explicit step) reads (section 4)   */
+    double chi_tref;    /*       state the sweep (or explicit step) reads (section 3.3)   */
     const double *src;  /* optional per-cell source Q (NULL: none) */
 } orc_grid;
 

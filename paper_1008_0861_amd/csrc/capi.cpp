@@ -501,7 +501,7 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     // Reverse order (y, x): the state lives in layout B between steps, in
     // tmp1: T -> tmp1 before the first step, tmp1 -> T after the last.
     if (reverse && nsteps > 0 && rc == ASD_OK) rc = enqueue_permute_2d(g, g->T, g->tmp[1], true);
-    // chi(T) (section 4): each sweep's coefficients from that sweep's input
+    // chi(T) (section 3.3): each sweep's coefficients from that sweep's input
     const bool chi_of_T = g->d.chi_exp != 0.0;
     auto sweep = [&](int d, const void* src, void* dst, int mode, const ReduceParams& red, int* nb) {
         int r = chi_of_T ? enqueue_coef(g, d, dt, src) : ASD_OK;

@@ -2,7 +2,7 @@
 // cell c and c + e_d,
 //     b_f     = (b_c + b_{c+e_d}) / 2      (arithmetic mean, not renormalised)
 //     chi_f   = chi_par, or the harmonic mean of the two cells' chi (a per-cell
-//               field, or chi_par (U / T_ref)^p of a state U, section 4)
+//               field, or chi_par (U / T_ref)^p of a state U, section 3.3)
 //     alpha_f = dt (chi_perp + (chi_f - chi_perp) b_d,f^2) / h_d^2
 //     beta_t  = dt (chi_f - chi_perp) b_d,f b_t,f / (h_d h_t)
 // A wall face (c on the last plane) gets zeros, except with T = 0 walls:

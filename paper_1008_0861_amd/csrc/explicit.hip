@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
 #pragma unroll
             for (int d = 0; d < NDIM; ++d) sB[d][i] = vb[d][j];
             if (P.chi) sChi[i] = vc[j];
-            // chi(T): the cell's value from T^n, in FP64 (section 4)
+            // chi(T): the cell's value from T^n, in FP64 (section 3.3)
             if (P.chi_exp != 0.0) sChi[i] = (T)((double)P.chi_par * pow((double)vu[j] / P.chi_tref, P.chi_exp));
         }
     }

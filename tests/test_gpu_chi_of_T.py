@@ -1,5 +1,5 @@
 """Temperature-dependent diffusivity chi_par(T) = chi_par (T / T_ref)^p on
-the GPU (chi ~ T^(5/2), section 4) against the oracle: per cell from the
+the GPU (chi ~ T^(5/2), section 3.3) against the oracle: per cell from the
 state each sweep (or explicit step) reads, harmonic mean at faces."""
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
 """Pins of the oracle's temperature-dependent diffusivity chi_par(T) =
-chi_par (T / T_ref)^p (p = 5/2 in the paper's application, section 4),
+chi_par (T / T_ref)^p (p = 5/2 in the paper's application, section 3.3),
 taken per cell from the state each sweep reads and averaged harmonically at
 faces (the per-cell rule of section 2)."""
 import itertools
