@@ -208,8 +208,10 @@ __device__ __forceinline__ void stage_cells(const SweepParams<T>& P, const TileC
 // Phases 2-3 of a staged tile: every thread of the block must call it; it
 // ends with a barrier so that the tile's LDS buffer may be refilled.
 // smem: the block's LDS base (exchange buffers).  Returns the thread's FP64
-// sum and min / max of the values it wrote.
-template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
+// sum and min / max of the values it wrote.  FULL: every segment holds
+// exactly MMAX cells (an aligned tile layout), so the segment length is a
+// compile-time constant and the per-cell bounds tests vanish.
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT, bool FULL>
 __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileCtx<T>& ctx, unsigned char* smem,
                                             double& lsum, T& lmin, T& lmax) {
     constexpr int ES = (int)sizeof(T);
@@ -238,7 +240,7 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
     const int kseg = ((k & 63) << wpl_log2) | (k >> 6);
     const bool active = line_ok && kseg < nseg;
     const int s0 = active ? (kseg * n) >> P.nseg_log2 : 0;
-    const int m = active ? (((kseg + 1) * n) >> P.nseg_log2) - s0 : 1;
+    const int m = FULL ? MMAX : (active ? (((kseg + 1) * n) >> P.nseg_log2) - s0 : 1);
     const int os0 = cell_off1(s0, ES, pad);  // the segment's first slot
 
     // The segment's slots: index 0 is the left neighbour cell s0-1 (mod n),
@@ -521,7 +523,10 @@ __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, in
         stage_cells<T, NDIM, CH, LIMC, EXT>(P, c, it0, r);
     }
     __syncthreads();
-    solve_store<T, NDIM, MMAX, LIMC, EXT>(P, c, smem, lsum, lmin, lmax);
+    if (P.lds.aligned)
+        solve_store<T, NDIM, MMAX, LIMC, EXT, true>(P, c, smem, lsum, lmin, lmax);
+    else
+        solve_store<T, NDIM, MMAX, LIMC, EXT, false>(P, c, smem, lsum, lmin, lmax);
 }
 
 }  // namespace asd
