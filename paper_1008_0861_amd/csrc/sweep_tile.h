@@ -395,12 +395,64 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
             return Lo.pcr1_at < 0 ? row1 + cell_off1(t, ES, pad) : smem + Lo.pcr1_at + (lb + t) * SLOT;
         };
         int cur = 0;
-        // right neighbour's first-cell expression -> this segment's reduced
-        // row (buffer 0 has its own area: other waves may still be reading
-        // the slot rows)
-        lds_put3<T>(slot(0, kseg), Y, Uc, V);
-        __syncthreads();
-        {
+        // Segments of at least 4 cells (MMAX >= 8, or a full tile with
+        // MMAX >= 4): one exchange gives every segment its reduced row and
+        // the stride-1 reduction step.  Segment k publishes the four numbers
+        // that define its row given the first-cell expression (Y', U', V') of
+        // segment k+1,
+        //   ib = 1 / (A1 + A2 U'),  Ra = A3 ib,  Rc = A2 V' ib,  Rd = (A4 - A2 Y') ib,
+        // and its own first-cell expression, in its second and third slots
+        // (read by no other lane, and dead once the lane has read its
+        // segment; the back substitution rewrites their U words only after
+        // further barriers); a lane then forms rows k-1, k and k+1 itself.
+        // Shorter segments exchange the first-cell expressions through
+        // buffer 0 (its own area: other waves may still be reading the slot
+        // rows) and take the stride-1 step in the loop below.
+        constexpr bool MERGED = MMAX >= 8 || (FULL && MMAX >= 4);
+        int s_first = 1;
+        if constexpr (MERGED) {
+            const T A1 = be - ae * hp, A2 = ce, A3 = ae * wp, A4 = re - ae * gp;
+            if (active) {
+                lds_put4<T>(row1 + cell_off1(s0 + 1, ES, pad), A1, A2, A3, A4);
+                lds_put3<T>(row1 + cell_off1(s0 + 2, ES, pad), Y, Uc, V);
+            }
+            __syncthreads();
+            if (active) {
+                auto row = [](T a1, T a2, T a3, T a4, T yp, T up, T vp, T& ra, T& rc, T& rd) {
+                    const T ib = fast_rcp<T>(a1 + a2 * up);
+                    ra = a3 * ib;
+                    rc = a2 * vp * ib;
+                    rd = (a4 - a2 * yp) * ib;
+                };
+                auto seg_start = [&](int j) { return FULL ? j * MMAX : (j * n) >> P.nseg_log2; };
+                const int sm = seg_start((kseg - 1) & (nseg - 1));
+                const int sp1 = seg_start((kseg + 1) & (nseg - 1));
+                const int sp2 = seg_start((kseg + 2) & (nseg - 1));
+                T m1, m2, m3, m4, q1, q2, q3, q4, y1, u1, v1, y2, u2, v2, unused;
+                lds_get4<T>(row1 + cell_off1(sm + 1, ES, pad), m1, m2, m3, m4);
+                lds_get4<T>(row1 + cell_off1(sp1 + 1, ES, pad), q1, q2, q3, q4);
+                lds_get4<T>(row1 + cell_off1(sp1 + 2, ES, pad), y1, u1, v1, unused);
+                lds_get4<T>(row1 + cell_off1(sp2 + 2, ES, pad), y2, u2, v2, unused);
+                T am, cm, dm, a0, c0, d0, ap, cp, dp;
+                row(m1, m2, m3, m4, Y, Uc, V, am, cm, dm);   // row k-1 (its right neighbour is k)
+                row(A1, A2, A3, A4, y1, u1, v1, a0, c0, d0);  // row k
+                row(q1, q2, q3, q4, y2, u2, v2, ap, cp, dp);  // row k+1
+                const T ib = fast_rcp<T>(T(1) - a0 * cm - c0 * ap);
+                Ra = -a0 * am * ib;
+                Rc = -c0 * cp * ib;
+                Rd = (d0 - a0 * dm - c0 * dp) * ib;
+            } else {
+                Ra = T(0); Rc = T(0); Rd = T(0);
+            }
+            s_first = 2;
+            // the next exchange takes buffer 0: buffer 1 may lie in the slot
+            // rows, whose private slots other lanes may not have read yet
+            // (no barrier separates those reads from the next exchange's
+            // writes); buffer 1 is used only after that exchange's barrier
+            cur = 1;
+        } else {
+            lds_put3<T>(slot(0, kseg), Y, Uc, V);
+            __syncthreads();
             T Yp, Up, Vp, unused;
             lds_get4<T>(slot(0, (kseg + 1) & (nseg - 1)), Yp, Up, Vp, unused);
             if (active) {
@@ -412,8 +464,8 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
                 Ra = T(0); Rc = T(0); Rd = T(0);
             }
         }
-        // strides below wpl: partners in other waves
-        for (int s = 1; s < nseg && s < P.wpl; s <<= 1) {
+        // (further) strides below wpl: partners in other waves
+        for (int s = s_first; s < nseg && s < P.wpl; s <<= 1) {
             cur ^= 1;
             lds_put3<T>(slot(cur, kseg), Ra, Rc, Rd);
             __syncthreads();
