@@ -27,3 +27,20 @@ def test_long_call_chunked_graph_equals_direct(scheme, energy):
         np.testing.assert_array_equal(outs[0][1], outs[1][1])
     else:
         np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape,bc", [((64, 96), "periodic"), ((40, 24), "insulating"), ((37, 50), "periodic")])
+def test_one_call_equals_single_step_calls(prec, shape, bc):
+    """A multi-step call keeps its intermediate states in the workspace
+    between steps; single-step calls start from and end in T.  The
+    arithmetic is the same, so the states agree bit for bit."""
+    p = _random_problem(shape, bc, seed=sum(shape), ncfl=10.0, nsteps=9)
+    a = GpuProblem(p, prec)
+    a.g.set_graphs(False)
+    one = a.run(nsteps=9)
+    b = GpuProblem(p, prec)
+    b.g.set_graphs(False)
+    for _ in range(9):
+        many = b.run(nsteps=1)
+    np.testing.assert_array_equal(one, many)
