@@ -82,7 +82,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) adj_face_kernel(AdjParams<T> P) {
     const AdjGeom<T> G{P.nx, P.ny, P.d, 1 - P.d, P.periodic != 0};
     const int N = P.nx * P.ny;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+    for (int64_t c64 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c64 < N; c64 += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)c64;
         const int x = c % P.nx, y = c / P.nx;
         const int cp = moved(G, x, y, G.d, +1);
         if (cp < 0) {  // wall face
@@ -127,7 +128,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) adj_cell_kernel(AdjParams<T> P) {
     const AdjGeom<T> G{P.nx, P.ny, P.d, 1 - P.d, P.periodic != 0};
     const int N = P.nx * P.ny;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    for (int64_t j64 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j64 < N; j64 += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)j64;
         const int x = j % P.nx, y = j / P.nx;
         // psi(c) = sum over the two faces of c of w dG/dsigma_c
         auto psi = [&](int cx, int cy, int cc) {

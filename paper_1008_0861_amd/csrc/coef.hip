@@ -33,7 +33,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) coef_kernel(CoefParams<T> C) {
     const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
     const int N = nx * ny * nz;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    // 64-bit loop index: the stride would overflow int near N = 2^31 (each i < N fits an int)
+    for (int64_t i64 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i64 < N; i64 += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)i64;
         const int xyz[3] = {i % nx, (i / nx) % ny, i / (nx * ny)};
         int nbr[3] = {xyz[0], xyz[1], xyz[2]};
         nbr[C.d] += 1;

@@ -19,19 +19,26 @@
 
 namespace asd {
 
-template <int NDIM>
+// Tile of TX x TY (x TZ) cells with a one-cell halo, NT threads; each thread
+// updates NC / NT cells.  2-D: 64 x 16 in FP32 (halo overhead 1.16, 4 cells
+// per thread), 64 x 8 in FP64 (32 KB of LDS, several tiles per CU); 3-D:
+// 32 x 4 x 2, which keeps the FP64 tile within 64 KB of LDS.
+template <typename T, int NDIM>
 struct ExTile {
     static constexpr int TX = NDIM == 2 ? 64 : 32;
-    static constexpr int TY = NDIM == 2 ? 4 : 4;
+    static constexpr int TY = NDIM == 2 ? (sizeof(T) == 4 ? 16 : 8) : 4;
     static constexpr int TZ = NDIM == 2 ? 1 : 2;
     static constexpr int BX = TX + 2, BY = TY + 2, BZ = NDIM == 2 ? 1 : TZ + 2;
     static constexpr int NB = BX * BY * BZ;
-    static constexpr int NT = TX * TY * TZ;
+    static constexpr int NC = TX * TY * TZ;
+    static constexpr int NT = 256;
 };
 
-template <typename T, int NDIM>
+// LIMC: the limiter as a compile-time constant (van Leer, the default), or -1
+// to read it from the parameters.
+template <typename T, int NDIM, int LIMC>
 __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
-    using TL = ExTile<NDIM>;
+    using TL = ExTile<T, NDIM>;
     __shared__ T sU[TL::NB];
     __shared__ T sB[NDIM][TL::NB];
     __shared__ T sS[NDIM][TL::NB];  // limited slope along each axis
@@ -46,7 +53,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     const int z0 = (blk / gy) * TL::TZ;
     const bool periodic = P.periodic != 0;
     const bool dir = P.dirichlet != 0;
-    const int lim = P.limiter;
+    const int lim = LIMC >= 0 ? LIMC : P.limiter;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
 
     // stage the box [x0-1, x0+TX] x [y0-1, y0+TY] (x [z0-1, z0+TZ]); all of a
@@ -101,11 +108,12 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     }
     __syncthreads();
 
-    const int tx = threadIdx.x % TL::TX, ty = (threadIdx.x / TL::TX) % TL::TY,
-              tz = threadIdx.x / (TL::TX * TL::TY);
+    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
+#pragma unroll
+    for (int cc = threadIdx.x; cc < TL::NC; cc += TL::NT) {
+    const int tx = cc % TL::TX, ty = (cc / TL::TX) % TL::TY, tz = cc / (TL::TX * TL::TY);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool inside = x < nx && y < ny && (NDIM == 2 || z < nz);
-    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
     if (inside) {
         const int bi = (tx + 1) + (ty + 1) * TL::BX + (NDIM == 3 ? (tz + 1) * TL::BX * TL::BY : 0);
         const int gc[3] = {x, y, z};
@@ -142,30 +150,44 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
         const int64_t co = (int64_t)x + y * sy + (int64_t)z * sz;
         const T un = P.Q ? (uc + P.dtq * P.Q[co]) + acc : uc + acc;
         P.out[co] = un;
-        lsum = (double)un;
-        lmin = lmax = (double)un;
+        lsum += (double)un;
+        lmin = fmin(lmin, (double)un);
+        lmax = fmax(lmax, (double)un);
+    }
     }
     if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
 }
 
-int explicit_num_blocks(int ndim, const int n[3]) {
+template <typename T>
+int explicit_num_blocks_t(int ndim, const int n[3]) {
     if (ndim == 2) {
-        using TL = ExTile<2>;
+        using TL = ExTile<T, 2>;
         return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY);
     }
-    using TL = ExTile<3>;
+    using TL = ExTile<T, 3>;
     return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY) *
            ((n[2] + TL::TZ - 1) / TL::TZ);
 }
 
+// Blocks of an explicit launch, the larger of the two precisions' tilings
+// (sizes the reduction scratch).
+int explicit_num_blocks(int ndim, const int n[3]) {
+    const int a = explicit_num_blocks_t<float>(ndim, n), b = explicit_num_blocks_t<double>(ndim, n);
+    return a > b ? a : b;
+}
+
 template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out) {
-    const int nb = explicit_num_blocks(ndim, P.n);
+    const int nb = explicit_num_blocks_t<T>(ndim, P.n);
     if (nblocks_out) *nblocks_out = nb;
-    if (ndim == 2)
-        hipLaunchKernelGGL((explicit_kernel<T, 2>), dim3(nb), dim3(ExTile<2>::NT), 0, st, P);
-    else
-        hipLaunchKernelGGL((explicit_kernel<T, 3>), dim3(nb), dim3(ExTile<3>::NT), 0, st, P);
+    const bool vl = P.limiter == LIM_VANLEER;
+    if (ndim == 2) {
+        if (vl) hipLaunchKernelGGL((explicit_kernel<T, 2, LIM_VANLEER>), dim3(nb), dim3(ExTile<T, 2>::NT), 0, st, P);
+        else hipLaunchKernelGGL((explicit_kernel<T, 2, -1>), dim3(nb), dim3(ExTile<T, 2>::NT), 0, st, P);
+    } else {
+        if (vl) hipLaunchKernelGGL((explicit_kernel<T, 3, LIM_VANLEER>), dim3(nb), dim3(ExTile<T, 3>::NT), 0, st, P);
+        else hipLaunchKernelGGL((explicit_kernel<T, 3, -1>), dim3(nb), dim3(ExTile<T, 3>::NT), 0, st, P);
+    }
     return hipGetLastError();
 }
 
