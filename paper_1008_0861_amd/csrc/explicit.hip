@@ -19,6 +19,14 @@
 
 namespace asd {
 
+// Neighbour coordinate with the boundary rule, in 32 bits (periodic wraps,
+// walls clamp; the odd ghost's sign is applied by the caller).
+__device__ __forceinline__ int nb_coord32(int c, int n, bool periodic) {
+    if (c < 0) return periodic ? n - 1 : 0;
+    if (c >= n) return periodic ? 0 : n - 1;
+    return c;
+}
+
 // Tile of TX x TY (x TZ) cells with a one-cell halo, NT threads; each thread
 // updates NC / NT cells.  2-D: 64 x 16 in FP32 (halo overhead 1.16, 4 cells
 // per thread), 64 x 8 in FP64 (32 KB of LDS, several tiles per CU); 3-D:
@@ -54,7 +62,8 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     const bool periodic = P.periodic != 0;
     const bool dir = P.dirichlet != 0;
     const int lim = LIMC >= 0 ? LIMC : P.limiter;
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    // cell indices fit 32 bits (grids hold fewer than 2^31 cells)
+    const unsigned sy = (unsigned)nx, sz = (unsigned)nx * (unsigned)ny;
 
     // stage the box [x0-1, x0+TX] x [y0-1, y0+TY] (x [z0-1, z0+TZ]); all of a
     // thread's loads are issued before any is stored to LDS
@@ -69,10 +78,10 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
             const int bx = ii % TL::BX, by = (ii / TL::BX) % TL::BY, bz = ii / (TL::BX * TL::BY);
             // cells beyond the far edge of a partial tile map to valid cells (never used)
             const int gx0 = x0 - 1 + bx, gy0 = y0 - 1 + by, gz0 = z0 - 1 + bz;
-            const int64_t x = nb_coord(gx0, nx, periodic);
-            const int64_t y = nb_coord(gy0, ny, periodic);
-            const int64_t z = NDIM == 3 ? nb_coord(gz0, nz, periodic) : 0;
-            const int64_t c = x + y * sy + z * sz;
+            const int x = nb_coord32(gx0, nx, periodic);
+            const int y = nb_coord32(gy0, ny, periodic);
+            const int z = NDIM == 3 ? nb_coord32(gz0, nz, periodic) : 0;
+            const unsigned c = (unsigned)x + (unsigned)y * sy + (unsigned)z * sz;
             // odd ghost: one sign flip per axis on which the cell lies outside
             const int nout = (x != gx0) + (y != gy0) + (NDIM == 3 && z != gz0);
             vneg[j] = dir && (nout & 1);
@@ -147,7 +156,7 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
                 acc += side ? (alpha * diff + flux) : -(alpha * diff + flux);
             }
         }
-        const int64_t co = (int64_t)x + y * sy + (int64_t)z * sz;
+        const unsigned co = (unsigned)x + (unsigned)y * sy + (unsigned)z * sz;
         const T un = P.Q ? (uc + P.dtq * P.Q[co]) + acc : uc + acc;
         P.out[co] = un;
         lsum += (double)un;
