@@ -382,8 +382,8 @@ def cpu_baseline(budget_s=12.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "see DESIGN.md for how the path would shard", file=sys.stderr)
+        print(f"bench.py: the semi-implicit path runs on one GPU; multi-GPU sharding of the "
+              f"line sweeps is not implemented (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -45,7 +45,7 @@ extern "C" {
 #define ASD_EWORKSPACE (-5)  /* workspace missing, misaligned or too small */
 #define ASD_EUNSTABLE (-6)   /* dt beyond the scheme's stability limit (see below) */
 #define ASD_EHIP (-7)        /* the HIP runtime reported an error */
-#define ASD_EUNSUPPORTED (-8) /* valid but not supported by this build (e.g. line too long for LDS) */
+#define ASD_EUNSUPPORTED (-8) /* valid but not supported by this library (e.g. line too long for LDS) */
 
 /* boundary conditions (same on every axis) */
 #define ASD_BC_PERIODIC 0    /* periodic box (section 3.3); lines are cyclic tridiagonal systems */
