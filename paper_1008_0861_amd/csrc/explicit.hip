@@ -167,11 +167,129 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
     if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
 }
 
+// 2-D: one wave streams down a band of ExStream::TY rows of 64 columns
+// (lane = column).  Lanes 0 and 63 hold the halo columns, so a wave updates
+// the 62 columns between them; the row above and the row below the band
+// are halo rows.  All loads of the band are issued first, in row order, so
+// the first rows are updated while the later ones are still arriving.
+// Every face is evaluated once: a cell's left x face is its left lane's
+// right x face (a lane shift), its lower y face the upper y face of the
+// previous row (kept in a register).  No LDS and no barrier (except the
+// block's final reduction).
+struct ExStream {
+    static constexpr int COLS = 62;  // updated columns per wave
+    static constexpr int TY = 8;     // rows per wave
+    static constexpr int WAVES = 4;  // waves per block
+};
+
+// Values of lane+1 (left) and lane-1 (right); the edge lanes receive values
+// they never use.
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, 64); }
+
+template <typename T, int LIMC>
+__global__ void __launch_bounds__(256) explicit_stream2d_kernel(ExplicitParams<T> P) {
+    constexpr int TY = ExStream::TY, NR = TY + 2;  // rows y0-1 .. y0+TY
+    const int nx = P.n[0], ny = P.n[1];
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * ExStream::WAVES + (threadIdx.x >> 6);
+    const int ncb = (nx + ExStream::COLS - 1) / ExStream::COLS;
+    const int nrb = (ny + TY - 1) / TY;
+    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
+    if (wave < ncb * nrb) {  // wave-uniform
+        const int cb = wave % ncb, rb = wave / ncb;
+        const int x = cb * ExStream::COLS - 1 + lane;  // this lane's column (halo lanes may lie outside)
+        const int y0 = rb * TY;
+        const bool periodic = P.periodic != 0;
+        const bool dir = P.dirichlet != 0;
+        const int lim = LIMC >= 0 ? LIMC : P.limiter;
+        const bool pchi = P.chi != nullptr || P.chi_exp != 0.0;
+        const int xc = nb_coord32(x, nx, periodic);
+        const bool xout = xc != x;
+        // the band's rows: state (odd ghosts negated), b and chi
+        T u[NR], bx[NR], by[NR], ch[NR], q[TY];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int y = y0 - 1 + r;
+            const int yc = nb_coord32(y, ny, periodic);
+            const unsigned c = (unsigned)xc + (unsigned)yc * (unsigned)nx;
+            const T v = P.U[c];
+            // odd ghost: one sign flip per axis on which the cell lies outside
+            u[r] = dir && (xout != (yc != y)) ? -v : v;
+            bx[r] = P.b[0][c];
+            by[r] = P.b[1][c];
+            ch[r] = P.chi ? P.chi[c] : P.chi_par;
+            // chi(T): the cell's value from T^n, in FP64 (section 3.3)
+            if (P.chi_exp != 0.0) ch[r] = (T)((double)P.chi_par * pow((double)v / P.chi_tref, P.chi_exp));
+            if (r >= 1 && r <= TY && P.Q) q[r - 1] = P.Q[c];
+        }
+        const T cn0 = P.cn[0], cn1 = P.cn[1], ct01 = P.ct[0][1], ct10 = P.ct[1][0];
+        const T chi_par = P.chi_par, chi_perp = P.chi_perp;
+        auto face = [&](T u0, T u1, T bn0, T bn1, T bt0, T bt1, T c0, T c1, T s0, T s1, T cn, T ct) {
+            // face between cells 0 and 1 along the normal axis: bn = normal
+            // component of b, bt = transverse component, s = transverse slopes
+            const T bnf = T(0.5) * (bn0 + bn1);
+            const T chif = pchi ? harmonic<T>(c0, c1) : chi_par;
+            const T dpar = chif - chi_perp;
+            const T alpha = cn * (chi_perp + dpar * bnf * bnf);
+            const T btf = T(0.5) * (bt0 + bt1);
+            const T flux = dpar * bnf * (ct * btf * limit2<T>(lim, s1, s0));
+            return alpha * (u1 - u0) + flux;
+        };
+        // slopes along x of a row (lane shifts), along y of a row (registers)
+        auto slope_x = [&](T uc) { return cell_slope<T>(lim, from_left(uc), uc, from_right(uc)); };
+        const bool xwall = !periodic && !dir && (x < 0 || x + 1 > nx - 1);  // this lane's right x face
+        const bool out_col = lane >= 1 && lane <= ExStream::COLS && x < nx;
+        // upper y face of row y0-1 (the lower face of the first row)
+        T sx_prev = slope_x(u[0]);
+        T sx_cur = slope_x(u[1]);
+        T fy_low;
+        {
+            const bool ywall = !periodic && !dir && (y0 - 1 < 0 || y0 > ny - 1);
+            fy_low = ywall ? T(0) : face(u[0], u[1], by[0], by[1], bx[0], bx[1], ch[0], ch[1], sx_prev, sx_cur, cn1, ct10);
+        }
+#pragma unroll
+        for (int r = 1; r <= TY; ++r) {
+            const int y = y0 - 1 + r;
+            // x faces of row r: this lane's right face, and its left face from the left lane
+            const T sy = cell_slope<T>(lim, u[r - 1], u[r], u[r + 1]);
+            T fxr = face(u[r], from_right(u[r]), bx[r], from_right(bx[r]), by[r], from_right(by[r]), ch[r],
+                         from_right(ch[r]), sy, from_right(sy), cn0, ct01);
+            fxr = xwall ? T(0) : fxr;
+            const T fxl = from_left(fxr);
+            // upper y face of row r
+            const T sx_next = slope_x(u[r + 1]);
+            const bool ywall = !periodic && !dir && (y < 0 || y + 1 > ny - 1);
+            T fyh = face(u[r], u[r + 1], by[r], by[r + 1], bx[r], bx[r + 1], ch[r], ch[r + 1], sx_cur, sx_next,
+                         cn1, ct10);
+            fyh = ywall ? T(0) : fyh;
+            T acc = T(0);
+            acc += -fxl;
+            acc += fxr;
+            acc += -fy_low;
+            acc += fyh;
+            if (out_col && y < ny) {
+                const T uc = u[r];
+                const T un = P.Q ? (uc + P.dtq * q[r - 1]) + acc : uc + acc;
+                P.out[(unsigned)x + (unsigned)y * (unsigned)nx] = un;
+                lsum += (double)un;
+                lmin = fmin(lmin, (double)un);
+                lmax = fmax(lmax, (double)un);
+            }
+            fy_low = fyh;
+            sx_cur = sx_next;
+        }
+    }
+    if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
+}
+
 template <typename T>
 int explicit_num_blocks_t(int ndim, const int n[3]) {
     if (ndim == 2) {
-        using TL = ExTile<T, 2>;
-        return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY);
+        const int waves = ((n[0] + ExStream::COLS - 1) / ExStream::COLS) * ((n[1] + ExStream::TY - 1) / ExStream::TY);
+        return (waves + ExStream::WAVES - 1) / ExStream::WAVES;
     }
     using TL = ExTile<T, 3>;
     return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY) *
@@ -191,8 +309,9 @@ hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st,
     if (nblocks_out) *nblocks_out = nb;
     const bool vl = P.limiter == LIM_VANLEER;
     if (ndim == 2) {
-        if (vl) hipLaunchKernelGGL((explicit_kernel<T, 2, LIM_VANLEER>), dim3(nb), dim3(ExTile<T, 2>::NT), 0, st, P);
-        else hipLaunchKernelGGL((explicit_kernel<T, 2, -1>), dim3(nb), dim3(ExTile<T, 2>::NT), 0, st, P);
+        constexpr int NT = 64 * ExStream::WAVES;
+        if (vl) hipLaunchKernelGGL((explicit_stream2d_kernel<T, LIM_VANLEER>), dim3(nb), dim3(NT), 0, st, P);
+        else hipLaunchKernelGGL((explicit_stream2d_kernel<T, -1>), dim3(nb), dim3(NT), 0, st, P);
     } else {
         if (vl) hipLaunchKernelGGL((explicit_kernel<T, 3, LIM_VANLEER>), dim3(nb), dim3(ExTile<T, 3>::NT), 0, st, P);
         else hipLaunchKernelGGL((explicit_kernel<T, 3, -1>), dim3(nb), dim3(ExTile<T, 3>::NT), 0, st, P);

@@ -96,6 +96,21 @@ def test_bad_descriptions(asd, mutate, code):
     assert asd.last_error()
 
 
+@pytest.mark.parametrize("ndim,dtype,nmax", [(2, "float32", 4096), (3, "float32", 4096),
+                                             (2, "float64", 4096), (3, "float64", 3181)])
+def test_longest_line(asd, ndim, dtype, nmax):
+    """The documented maximum line length is accepted on every axis and one
+    more cell is refused with EUNSUPPORTED (the line no longer fits in LDS)."""
+    import torch
+    dt = getattr(torch, dtype)
+    for axis in range(ndim):
+        for n, code in ((nmax, 0), (nmax + 1, -8)):
+            shape = [4] * ndim
+            shape[ndim - 1 - axis] = n
+            rc, _ = _rc_ws(asd, _desc(asd, shape=tuple(shape), h=(1.0,) * ndim, dtype=dt))
+            assert rc == code, (axis, n, asd.last_error())
+
+
 def test_insulating_allows_two_cells(asd):
     rc, _ = _rc_ws(asd, _desc(asd, shape=(2, 2), h=(1.0, 1.0), bc="insulating"))
     assert rc == 0

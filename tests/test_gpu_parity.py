@@ -85,6 +85,39 @@ def test_si_line_lengths(n):
         assert max_rel_err(got, ref) <= TOL["f64"], (shape, max_rel_err(got, ref))
 
 
+@pytest.mark.parametrize("prec,shape", [("f32", (5, 4096)), ("f32", (4096, 5)), ("f64", (3, 4, 3181)),
+                                        ("f64", (3181, 3, 4)), ("f32", (3, 4096, 4))])
+def test_si_longest_lines(prec, shape):
+    """The longest lines the LDS holds (4096 cells; 3181 in 3-D FP64), on
+    each axis in turn."""
+    p = _random_problem(shape, "periodic", ncfl=10.0, seed=sum(shape), nsteps=2)
+    ref = oracle_run(p, prec)
+    got = GpuProblem(p, prec).run()
+    assert max_rel_err(got, ref) <= TOL[prec], (shape, max_rel_err(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["si", "ex"])
+def test_zero_steps(prec, scheme):
+    """nsteps = 0 leaves T bit for bit and reports the initial energy (the
+    oracle's FP64 sum of the same rounded state); the series call returns
+    the one row (E0, min T, max T)."""
+    p = _random_problem((40, 50), "periodic", seed=9)
+    dt = p.dt if scheme == "si" else p.dt / 40
+    ref, eref = oracle_run(p, prec, nsteps=0, scheme=scheme, dt=dt, energy=True)
+    gp = GpuProblem(p, prec)
+    got, e = gp.run(nsteps=0, scheme=scheme, dt=dt, energy=True)
+    assert np.array_equal(got, ref)
+    assert e.shape == (1,)
+    np.testing.assert_allclose(e, eref, rtol=1e-13, atol=0)
+    with torch.cuda.stream(gp.stream):
+        ser = gp.g.step_series(scheme, dt, 0)
+    gp.stream.synchronize()
+    ser = ser.cpu().numpy()
+    assert ser.shape == (1, 3)
+    np.testing.assert_allclose(ser[0], [eref[0], ref.min(), ref.max()], rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(9, 13, 21), (20, 24, 17), (3, 40, 5)])
 @pytest.mark.parametrize("bc", ["periodic", "insulating"])
