@@ -10,10 +10,12 @@
 // alpha_w (-U_c - U_c) and a transverse flux that vanishes (the limited
 // difference of a cell and its odd ghost is zero).
 //
-// gfx950 mapping: one workgroup per tile of TX x TY x TZ cells.  The tile
-// plus a one-cell halo of U, b (and chi) is staged through LDS with
-// coalesced loads; the limited cell slopes along every axis are computed
-// once per staged cell; each thread then updates one cell.
+// gfx950 mapping.  2-D: each wave streams down a short band of rows, one
+// column per lane, with every face evaluated once (explicit_stream2d_kernel).
+// 3-D: one workgroup per tile of TX x TY x TZ cells; the tile plus a
+// one-cell halo of U, b (and chi) is staged through LDS with coalesced loads,
+// the limited cell slopes along every axis are computed once per staged cell,
+// and each thread then updates its cells.
 #include "asd_device.h"
 #include "asd_launch.h"
 
@@ -28,9 +30,9 @@ __device__ __forceinline__ int nb_coord32(int c, int n, bool periodic) {
 }
 
 // Tile of TX x TY (x TZ) cells with a one-cell halo, NT threads; each thread
-// updates NC / NT cells.  2-D: 64 x 16 in FP32 (halo overhead 1.16, 4 cells
-// per thread), 64 x 8 in FP64 (32 KB of LDS, several tiles per CU); 3-D:
-// 32 x 4 x 2, which keeps the FP64 tile within 64 KB of LDS.
+// updates NC / NT cells.  3-D: 32 x 4 x 2, which keeps the FP64 tile within
+// 64 KB of LDS.  (The 2-D shape is unused: 2-D grids take the streaming
+// kernel.)
 template <typename T, int NDIM>
 struct ExTile {
     static constexpr int TX = NDIM == 2 ? 64 : 32;
@@ -178,12 +180,12 @@ __global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
 // block's final reduction).
 struct ExStream {
     static constexpr int COLS = 62;  // updated columns per wave
-    static constexpr int TY = 8;     // rows per wave
+    static constexpr int TY = 4;     // rows per wave
     static constexpr int WAVES = 4;  // waves per block
 };
 
-// Values of lane+1 (left) and lane-1 (right); the edge lanes receive values
-// they never use.
+// from_right: the value of lane+1 (the column to the right); from_left: that
+// of lane-1.  The edge lanes receive values they never use.
 template <typename T>
 __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
 template <typename T>
@@ -194,7 +196,10 @@ __global__ void __launch_bounds__(256) explicit_stream2d_kernel(ExplicitParams<T
     constexpr int TY = ExStream::TY, NR = TY + 2;  // rows y0-1 .. y0+TY
     const int nx = P.n[0], ny = P.n[1];
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * ExStream::WAVES + (threadIdx.x >> 6);
+    // XCD-aware block order (the grid is a multiple of 8 blocks): bands that
+    // share halo rows run on one XCD and share its L2
+    const int blk = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int wave = blk * ExStream::WAVES + (threadIdx.x >> 6);
     const int ncb = (nx + ExStream::COLS - 1) / ExStream::COLS;
     const int nrb = (ny + TY - 1) / TY;
     double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
@@ -289,7 +294,8 @@ template <typename T>
 int explicit_num_blocks_t(int ndim, const int n[3]) {
     if (ndim == 2) {
         const int waves = ((n[0] + ExStream::COLS - 1) / ExStream::COLS) * ((n[1] + ExStream::TY - 1) / ExStream::TY);
-        return (waves + ExStream::WAVES - 1) / ExStream::WAVES;
+        const int blocks = (waves + ExStream::WAVES - 1) / ExStream::WAVES;
+        return (blocks + 7) & ~7;  // a multiple of 8 for the XCD-aware order
     }
     using TL = ExTile<T, 3>;
     return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY) *
