@@ -256,6 +256,44 @@ def three_d(stream, torch, asd, nsteps=50, ncfl=10.0, four_step=False):
             "energy_rel_drift": float(abs(e[-1] - e[0]) / abs(e[0]))}
 
 
+def adjoint_1024(stream, torch, asd, n=1024, nsteps=50, ckpt_every=10):
+    """The adjoint workload: 1024^2 FP32, per-cell chi, 50 semi-implicit
+    steps with checkpoints every 10.  Times the forward steps and the
+    backward pass (checkpointed recomputation plus the reverse sweeps,
+    gradients with respect to T0 and chi) separately, medians of 3."""
+    import numpy as np
+    import synth
+
+    p = synth.adjoint_problem(n=n, nsteps=nsteps)
+    with torch.cuda.stream(stream):
+        g = asd.Grid(p.shape, p.h, bc=p.bc, dtype=torch.float32, chi_par=float(p.chi.max()), per_cell_chi=True)
+        b = [torch.from_numpy(c).float().cuda() for c in p.b]
+        chi = torch.from_numpy(p.chi).float().cuda()
+        g.set_b(*b)
+        g.set_field("chi", chi)
+        T0 = torch.from_numpy(p.T0).float().cuda()
+        T = T0.clone()
+        g.set_field("T", T)
+        lam = torch.from_numpy(np.random.default_rng(7).standard_normal(p.T0.shape)).float().cuda()
+
+    def fwd():
+        T.copy_(T0)
+        g.step_semi_implicit(p.dt, nsteps)
+
+    def bwd():
+        g.adjoint(p.dt, nsteps, ckpt_every, T0, lam)
+
+    with torch.cuda.stream(stream):
+        fwd()
+        bwd()
+        tf = sorted(timed(fwd, stream, torch) for _ in range(3))[1]
+        tb = sorted(timed(bwd, stream, torch) for _ in range(3))[1]
+    N = n * n
+    return {"cells": N, "steps": nsteps, "ckpt_every": ckpt_every, "forward_ms": round(tf, 3),
+            "backward_ms": round(tb, 3), "backward_over_forward": round(tb / tf, 2),
+            "backward_Gcells": round(N * nsteps / (tb * 1e-3) / 1e9, 3)}
+
+
 def ring512(stream, torch, asd):
     """Ring diffusion of section 3.1 on 512^2 (T = 10 in the patch, 0.1
     elsewhere, chi = 0.01, insulating) to t = 20, FP64: minimum temperature
@@ -473,6 +511,7 @@ def main():
         extra["batched"] = batched(stream, torch, asd)
         extra["curl3d_256"] = three_d(stream, torch, asd)
         extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
+        extra["adjoint_1024"] = adjoint_1024(stream, torch, asd)
         extra["ring512"] = ring512(stream, torch, asd)
         extra["sovinec"] = sovinec(stream, torch, asd)
         result["extra"] = extra
