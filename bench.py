@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip secondary measurements")
+    ap.add_argument("--extra", default="all",
+                    help="comma-separated secondary measurements to run: copy, fp64, explicit, speedup, "
+                         "batched, 3d, adjoint, ring, sovinec (default all)")
     ap.add_argument("--tune", type=int, default=1, help="run the launch-shape autotuner first")
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain copy of 64 MiB (calibrates rocprofv3 byte counters)")
@@ -490,30 +493,42 @@ def main():
         },
         "energy_rel_drift": drift,
     }
-    if not args.no_extra:
+    names = set() if args.no_extra else (
+        {"copy", "fp64", "explicit", "speedup", "batched", "3d", "adjoint", "ring", "sovinec"}
+        if args.extra == "all" else set(args.extra.split(",")))
+    if names:
         extra = {}
-        extra["copy_kernel_GBs"] = round(copy_bandwidth(stream, torch, asd), 1)
-        p64 = synth.grf2d_problem(NX, nsteps=200)
-        g64 = make_grid(p64, "f64", stream, torch, asd)
-        with torch.cuda.stream(stream):
-            g64.tune(p64.dt, reps=10)
-        ms64, _ = run_si(g64, p64, 200, 200, stream, torch)
-        extra["fp64_si_Gcells"] = round(N / (ms64 * 1e-3) / 1e9, 3)
-        gx = make_grid(p, "f32", stream, torch, asd)
-        dtx = synth.ncfl_dt(1.0, p.h, 1.0)
-        ebx = torch.empty(2001, dtype=torch.float64, device="cuda")
-        with torch.cuda.stream(stream):
-            gx.step_explicit(dtx, 2000, out=ebx)
-            msx = timed(lambda: gx.step_explicit(dtx, 2000, out=ebx), stream, torch) / 2000
-        extra["explicit_fp32_Gcells"] = round(N / (msx * 1e-3) / 1e9, 3)
-        extra["explicit_ms_per_step"] = round(msx, 6)
-        result["speedup_vs_explicit"] = matched_l1_speedup(stream, torch, asd)
-        extra["batched"] = batched(stream, torch, asd)
-        extra["curl3d_256"] = three_d(stream, torch, asd)
-        extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
-        extra["adjoint_1024"] = adjoint_1024(stream, torch, asd)
-        extra["ring512"] = ring512(stream, torch, asd)
-        extra["sovinec"] = sovinec(stream, torch, asd)
+        if "copy" in names:
+            extra["copy_kernel_GBs"] = round(copy_bandwidth(stream, torch, asd), 1)
+        if "fp64" in names:
+            p64 = synth.grf2d_problem(NX, nsteps=200)
+            g64 = make_grid(p64, "f64", stream, torch, asd)
+            with torch.cuda.stream(stream):
+                g64.tune(p64.dt, reps=10)
+            ms64, _ = run_si(g64, p64, 200, 200, stream, torch)
+            extra["fp64_si_Gcells"] = round(N / (ms64 * 1e-3) / 1e9, 3)
+        if "explicit" in names:
+            gx = make_grid(p, "f32", stream, torch, asd)
+            dtx = synth.ncfl_dt(1.0, p.h, 1.0)
+            ebx = torch.empty(2001, dtype=torch.float64, device="cuda")
+            with torch.cuda.stream(stream):
+                gx.step_explicit(dtx, 2000, out=ebx)
+                msx = timed(lambda: gx.step_explicit(dtx, 2000, out=ebx), stream, torch) / 2000
+            extra["explicit_fp32_Gcells"] = round(N / (msx * 1e-3) / 1e9, 3)
+            extra["explicit_ms_per_step"] = round(msx, 6)
+        if "speedup" in names:
+            result["speedup_vs_explicit"] = matched_l1_speedup(stream, torch, asd)
+        if "batched" in names:
+            extra["batched"] = batched(stream, torch, asd)
+        if "3d" in names:
+            extra["curl3d_256"] = three_d(stream, torch, asd)
+            extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
+        if "adjoint" in names:
+            extra["adjoint_1024"] = adjoint_1024(stream, torch, asd)
+        if "ring" in names:
+            extra["ring512"] = ring512(stream, torch, asd)
+        if "sovinec" in names:
+            extra["sovinec"] = sovinec(stream, torch, asd)
         result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
