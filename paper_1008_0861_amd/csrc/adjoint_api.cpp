@@ -33,8 +33,8 @@ static AdjPlan adj_plan(asd_grid g, int nsteps, int k) {
     p.nck = nsteps > 0 ? (nsteps + k - 1) / k : 1;
     p.field = align256((size_t)g->N * g->es);
     // checkpoints + (k+1) recomputed states + k T* + transposed scratch +
-    // lambda + mu + three face scratch arrays
-    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k + 1) + 1 + 2 + 3);
+    // lambda + mu
+    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k + 1) + 1 + 2);
     return p;
 }
 
@@ -57,7 +57,7 @@ extern "C" int asd_adjoint_workspace_bytes(asd_grid g, int32_t nsteps, int32_t c
 
 template <typename T>
 static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, const void* X, void* lam_out,
-                   void* gchi, void* W1, void* W2, void* GF) {
+                   void* gchi) {
     AdjParams<T> P{};
     P.mu = (const T*)mu;
     P.U = (const T*)U;
@@ -65,9 +65,6 @@ static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, 
     P.b[0] = (const T*)g->b[0];
     P.b[1] = (const T*)g->b[1];
     P.chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) ? (const T*)g->chi : nullptr;
-    P.W1 = (T*)W1;
-    P.W2 = (T*)W2;
-    P.GF = (T*)GF;
     P.lam_out = (T*)lam_out;
     P.gchi = (T*)gchi;
     P.nx = (int)g->d.n[0];
@@ -107,9 +104,6 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
     void* tB = take();
     void* lam = take();
     void* mu = take();
-    void* W1 = take();
-    void* W2 = take();
-    void* GF = take();
     int rc;
     // forward pass: checkpoints at steps 0, k, 2k, ...
     rc = enqueue_copy(g, T0, ck[0]);
@@ -151,14 +145,14 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
             if (rc) return rc;
             rc = enqueue_sweep(g, 1, dt, tB, mu, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
-            rc = stencil<T>(g, 1, dt, mu, TS[i], S[i + 1], lam, gchi, W1, W2, GF);
+            rc = stencil<T>(g, 1, dt, mu, TS[i], S[i + 1], lam, gchi);
             if (rc) return rc;
             // x sweep: T^n -> T*
             rc = enqueue_sweep(g, 0, dt, lam, tB, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             rc = enqueue_permute_2d(g, tB, mu, false);
             if (rc) return rc;
-            rc = stencil<T>(g, 0, dt, mu, S[i], TS[i], lam, gchi, W1, W2, GF);
+            rc = stencil<T>(g, 0, dt, mu, S[i], TS[i], lam, gchi);
             if (rc) return rc;
         }
     }

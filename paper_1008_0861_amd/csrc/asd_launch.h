@@ -143,9 +143,6 @@ struct AdjParams {
     const T* X;       // the sweep's output state
     const T* b[2];
     const T* chi;     // per-cell chi or nullptr (then chi_par)
-    T* W1;            // face scratch: w dG/d(right slope)
-    T* W2;            // face scratch: w dG/d(left slope)
-    T* GF;            // face scratch: dL/dchi_f
     T* lam_out;       // mu + J_S^T mu
     T* gchi;          // nullable: += dL/dchi per cell
     int nx, ny, d;
