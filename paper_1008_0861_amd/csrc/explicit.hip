@@ -12,7 +12,7 @@
 //
 // gfx950 mapping.  2-D: each wave streams down a short band of rows, one
 // column per lane, with every face evaluated once (explicit_stream2d_kernel).
-// 3-D: one workgroup per tile of TX x TY x TZ cells; the tile plus a
+// 3-D (explicit3d_kernel): one workgroup per tile of TX x TY x TZ cells; the tile plus a
 // one-cell halo of U, b (and chi) is staged through LDS with coalesced loads,
 // the limited cell slopes along every axis are computed once per staged cell,
 // and each thread then updates its cells.
@@ -29,26 +29,23 @@ __device__ __forceinline__ int nb_coord32(int c, int n, bool periodic) {
     return c;
 }
 
-// Tile of TX x TY (x TZ) cells with a one-cell halo, NT threads; each thread
-// updates NC / NT cells.  3-D: 32 x 4 x 2, which keeps the FP64 tile within
-// 64 KB of LDS.  (The 2-D shape is unused: 2-D grids take the streaming
-// kernel.)
-template <typename T, int NDIM>
+// 3-D tile of TX x TY x TZ cells with a one-cell halo, NT threads; each
+// thread updates NC / NT cells.  32 x 4 x 2 keeps the FP64 tile within 64 KB
+// of LDS.
 struct ExTile {
-    static constexpr int TX = NDIM == 2 ? 64 : 32;
-    static constexpr int TY = NDIM == 2 ? (sizeof(T) == 4 ? 16 : 8) : 4;
-    static constexpr int TZ = NDIM == 2 ? 1 : 2;
-    static constexpr int BX = TX + 2, BY = TY + 2, BZ = NDIM == 2 ? 1 : TZ + 2;
+    static constexpr int TX = 32, TY = 4, TZ = 2;
+    static constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2;
     static constexpr int NB = BX * BY * BZ;
     static constexpr int NC = TX * TY * TZ;
     static constexpr int NT = 256;
 };
 
-// LIMC: the limiter as a compile-time constant (van Leer, the default), or -1
-// to read it from the parameters.
-template <typename T, int NDIM, int LIMC>
-__global__ void __launch_bounds__(256) explicit_kernel(ExplicitParams<T> P) {
-    using TL = ExTile<T, NDIM>;
+// 3-D grids.  LIMC: the limiter as a compile-time constant (van Leer, the
+// default), or -1 to read it from the parameters.
+template <typename T, int LIMC>
+__global__ void __launch_bounds__(256) explicit3d_kernel(ExplicitParams<T> P) {
+    constexpr int NDIM = 3;
+    using TL = ExTile;
     __shared__ T sU[TL::NB];
     __shared__ T sB[NDIM][TL::NB];
     __shared__ T sS[NDIM][TL::NB];  // limited slope along each axis
@@ -290,28 +287,21 @@ __global__ void __launch_bounds__(256) explicit_stream2d_kernel(ExplicitParams<T
     if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
 }
 
-template <typename T>
-int explicit_num_blocks_t(int ndim, const int n[3]) {
+// Blocks of an explicit launch (also sizes the reduction scratch).
+int explicit_num_blocks(int ndim, const int n[3]) {
     if (ndim == 2) {
         const int waves = ((n[0] + ExStream::COLS - 1) / ExStream::COLS) * ((n[1] + ExStream::TY - 1) / ExStream::TY);
         const int blocks = (waves + ExStream::WAVES - 1) / ExStream::WAVES;
         return (blocks + 7) & ~7;  // a multiple of 8 for the XCD-aware order
     }
-    using TL = ExTile<T, 3>;
+    using TL = ExTile;
     return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY) *
            ((n[2] + TL::TZ - 1) / TL::TZ);
 }
 
-// Blocks of an explicit launch, the larger of the two precisions' tilings
-// (sizes the reduction scratch).
-int explicit_num_blocks(int ndim, const int n[3]) {
-    const int a = explicit_num_blocks_t<float>(ndim, n), b = explicit_num_blocks_t<double>(ndim, n);
-    return a > b ? a : b;
-}
-
 template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out) {
-    const int nb = explicit_num_blocks_t<T>(ndim, P.n);
+    const int nb = explicit_num_blocks(ndim, P.n);
     if (nblocks_out) *nblocks_out = nb;
     const bool vl = P.limiter == LIM_VANLEER;
     if (ndim == 2) {
@@ -319,8 +309,8 @@ hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st,
         if (vl) hipLaunchKernelGGL((explicit_stream2d_kernel<T, LIM_VANLEER>), dim3(nb), dim3(NT), 0, st, P);
         else hipLaunchKernelGGL((explicit_stream2d_kernel<T, -1>), dim3(nb), dim3(NT), 0, st, P);
     } else {
-        if (vl) hipLaunchKernelGGL((explicit_kernel<T, 3, LIM_VANLEER>), dim3(nb), dim3(ExTile<T, 3>::NT), 0, st, P);
-        else hipLaunchKernelGGL((explicit_kernel<T, 3, -1>), dim3(nb), dim3(ExTile<T, 3>::NT), 0, st, P);
+        if (vl) hipLaunchKernelGGL((explicit3d_kernel<T, LIM_VANLEER>), dim3(nb), dim3(ExTile::NT), 0, st, P);
+        else hipLaunchKernelGGL((explicit3d_kernel<T, -1>), dim3(nb), dim3(ExTile::NT), 0, st, P);
     }
     return hipGetLastError();
 }
