@@ -173,12 +173,35 @@ def test_explicit_limiters_per_cell_chi(limiter):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_grf_1024_full_size(prec):
-    """The 1024^2 periodic random-field workload at full size, in the launch
-    configuration the benchmark uses, against the oracle for 30 steps."""
+    """The 1024^2 periodic random-field workload at full size against the
+    oracle for 30 steps, in the default launch shape and in the shapes the
+    autotuner picks for the benchmark (2 waves per line, 4 lines per block in
+    FP32; 2 and 2 in FP64)."""
     p = synth.grf2d_problem(1024, nsteps=30)
     ref = oracle_run(p, prec)
-    got = GpuProblem(p, prec).run()
-    assert max_rel_err(got, ref) <= TOL[prec]
+    shapes = [None, (2, 4) if prec == "f32" else (2, 2)]
+    for shape in shapes:
+        gp = GpuProblem(p, prec)
+        if shape is not None:
+            for axis in range(2):
+                gp.g.set_sweep_config(axis, *shape)
+            assert gp.g.sweep_config(0)["wpl"] == shape[0] and gp.g.sweep_config(0)["lpw"] == shape[1]
+        got = gp.run()
+        assert max_rel_err(got, ref) <= TOL[prec], (shape, max_rel_err(got, ref))
+
+
+def test_curl3d_256_full_size_tuned():
+    """The 256^3 FP32 3-D workload at full size, 2 steps, in the launch shapes
+    the autotuner picks (as the benchmark does), against the oracle."""
+    p = synth.curl3d_problem(256, nsteps=2, ncfl=10.0)
+    ref = oracle_run(p, "f32")
+    gp = GpuProblem(p, "f32")
+    with torch.cuda.stream(gp.stream):
+        gp.g.tune(p.dt, reps=2)
+        gp.T.copy_(torch.from_numpy(p.T0).float())
+    gp.stream.synchronize()
+    got = gp.run()
+    assert max_rel_err(got, ref) <= TOL["f32"], max_rel_err(got, ref)
 
 
 def test_grf_1024_chi_perp_fp32():
@@ -189,11 +212,17 @@ def test_grf_1024_chi_perp_fp32():
 
 
 def test_energy_conserved_and_deterministic_100_steps():
-    """FP32 state, 100 steps at 1024^2: the FP64 energy series stays at its
+    """FP32 state, 100 steps at 1024^2 in the benchmark's launch shape (2
+    waves per line, 4 lines per block): the FP64 energy series stays at its
     initial value to FP32 rounding, and two runs are bitwise equal."""
     p = synth.grf2d_problem(1024, nsteps=100)
-    a, ea = GpuProblem(p, "f32").run(energy=True)
-    b, eb = GpuProblem(p, "f32").run(energy=True)
+    runs = []
+    for _ in range(2):
+        gp = GpuProblem(p, "f32")
+        for axis in range(2):
+            gp.g.set_sweep_config(axis, 2, 4)
+        runs.append(gp.run(energy=True))
+    (a, ea), (b, eb) = runs
     assert np.array_equal(a, b) and np.array_equal(ea, eb)
     assert np.max(np.abs(ea - ea[0])) <= 2e-6 * abs(ea[0])
 
