@@ -190,6 +190,17 @@ def test_grf_1024_full_size(prec):
         assert max_rel_err(got, ref) <= TOL[prec], (shape, max_rel_err(got, ref))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_explicit_1024_full_size(prec):
+    """The explicit limited step on the 1024^2 workload at ncfl = 1, as the
+    benchmark runs it, against the oracle for 20 steps."""
+    p = synth.grf2d_problem(1024, nsteps=20)
+    dt = synth.ncfl_dt(1.0, p.h, 1.0)
+    ref = oracle_run(p, prec, scheme="ex", dt=dt)
+    got = GpuProblem(p, prec).run(scheme="ex", dt=dt)
+    assert max_rel_err(got, ref) <= TOL[prec], max_rel_err(got, ref)
+
+
 def test_curl3d_256_full_size_tuned():
     """The 256^3 FP32 3-D workload at full size, 2 steps, in the launch shapes
     the autotuner picks (as the benchmark does), against the oracle."""
