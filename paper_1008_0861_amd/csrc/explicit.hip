@@ -10,12 +10,10 @@
 // alpha_w (-U_c - U_c) and a transverse flux that vanishes (the limited
 // difference of a cell and its odd ghost is zero).
 //
-// gfx950 mapping.  2-D: each wave streams down a short band of rows, one
-// column per lane, with every face evaluated once (explicit_stream2d_kernel).
-// 3-D (explicit3d_kernel): one workgroup per tile of TX x TY x TZ cells; the tile plus a
-// one-cell halo of U, b (and chi) is staged through LDS with coalesced loads,
-// the limited cell slopes along every axis are computed once per staged cell,
-// and each thread then updates its cells.
+// gfx950 mapping: each wave owns a small block of cells, one column per
+// lane (2-D: a band of rows; 3-D: rows x planes), loads it with a one-cell
+// halo, and evaluates every face once (lane shifts across columns,
+// registers across rows and planes).  No LDS staging.
 #include "asd_device.h"
 #include "asd_launch.h"
 
@@ -27,143 +25,6 @@ __device__ __forceinline__ int nb_coord32(int c, int n, bool periodic) {
     if (c < 0) return periodic ? n - 1 : 0;
     if (c >= n) return periodic ? 0 : n - 1;
     return c;
-}
-
-// 3-D tile of TX x TY x TZ cells with a one-cell halo, NT threads; each
-// thread updates NC / NT cells.  32 x 4 x 2 keeps the FP64 tile within 64 KB
-// of LDS.
-struct ExTile {
-    static constexpr int TX = 32, TY = 4, TZ = 2;
-    static constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2;
-    static constexpr int NB = BX * BY * BZ;
-    static constexpr int NC = TX * TY * TZ;
-    static constexpr int NT = 256;
-};
-
-// 3-D grids.  LIMC: the limiter as a compile-time constant (van Leer, the
-// default), or -1 to read it from the parameters.
-template <typename T, int LIMC>
-__global__ void __launch_bounds__(256) explicit3d_kernel(ExplicitParams<T> P) {
-    constexpr int NDIM = 3;
-    using TL = ExTile;
-    __shared__ T sU[TL::NB];
-    __shared__ T sB[NDIM][TL::NB];
-    __shared__ T sS[NDIM][TL::NB];  // limited slope along each axis
-    __shared__ T sChi[TL::NB];
-
-    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-    const int gx = (nx + TL::TX - 1) / TL::TX, gy = (ny + TL::TY - 1) / TL::TY;
-    int blk = blockIdx.x;
-    const int x0 = (blk % gx) * TL::TX;
-    blk /= gx;
-    const int y0 = (blk % gy) * TL::TY;
-    const int z0 = (blk / gy) * TL::TZ;
-    const bool periodic = P.periodic != 0;
-    const bool dir = P.dirichlet != 0;
-    const int lim = LIMC >= 0 ? LIMC : P.limiter;
-    // cell indices fit 32 bits (grids hold fewer than 2^31 cells)
-    const unsigned sy = (unsigned)nx, sz = (unsigned)nx * (unsigned)ny;
-
-    // stage the box [x0-1, x0+TX] x [y0-1, y0+TY] (x [z0-1, z0+TZ]); all of a
-    // thread's loads are issued before any is stored to LDS
-    constexpr int IT = (TL::NB + TL::NT - 1) / TL::NT;
-    {
-        T vu[IT], vb[NDIM][IT], vc[IT];
-        bool vneg[IT];
-#pragma unroll
-        for (int j = 0; j < IT; ++j) {
-            const int i = threadIdx.x + j * TL::NT;
-            const int ii = i < TL::NB ? i : 0;
-            const int bx = ii % TL::BX, by = (ii / TL::BX) % TL::BY, bz = ii / (TL::BX * TL::BY);
-            // cells beyond the far edge of a partial tile map to valid cells (never used)
-            const int gx0 = x0 - 1 + bx, gy0 = y0 - 1 + by, gz0 = z0 - 1 + bz;
-            const int x = nb_coord32(gx0, nx, periodic);
-            const int y = nb_coord32(gy0, ny, periodic);
-            const int z = NDIM == 3 ? nb_coord32(gz0, nz, periodic) : 0;
-            const unsigned c = (unsigned)x + (unsigned)y * sy + (unsigned)z * sz;
-            // odd ghost: one sign flip per axis on which the cell lies outside
-            const int nout = (x != gx0) + (y != gy0) + (NDIM == 3 && z != gz0);
-            vneg[j] = dir && (nout & 1);
-            vu[j] = P.U[c];
-#pragma unroll
-            for (int d = 0; d < NDIM; ++d) vb[d][j] = P.b[d][c];
-            if (P.chi) vc[j] = P.chi[c];
-        }
-#pragma unroll
-        for (int j = 0; j < IT; ++j) {
-            const int i = threadIdx.x + j * TL::NT;
-            if (i >= TL::NB) continue;
-            sU[i] = vneg[j] ? -vu[j] : vu[j];
-#pragma unroll
-            for (int d = 0; d < NDIM; ++d) sB[d][i] = vb[d][j];
-            if (P.chi) sChi[i] = vc[j];
-            // chi(T): the cell's value from T^n, in FP64 (section 3.3)
-            if (P.chi_exp != 0.0) sChi[i] = (T)((double)P.chi_par * pow((double)vu[j] / P.chi_tref, P.chi_exp));
-        }
-    }
-    __syncthreads();
-    const int bstr[3] = {1, TL::BX, TL::BX * TL::BY};
-    const int bdim[3] = {TL::BX, TL::BY, TL::BZ};
-    for (int i = threadIdx.x; i < TL::NB; i += blockDim.x) {
-        const int bc[3] = {i % TL::BX, (i / TL::BX) % TL::BY, i / (TL::BX * TL::BY)};
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d) {
-            T s = T(0);
-            if (bc[d] > 0 && bc[d] < bdim[d] - 1)
-                s = cell_slope<T>(lim, sU[i - bstr[d]], sU[i], sU[i + bstr[d]]);
-            sS[d][i] = s;
-        }
-    }
-    __syncthreads();
-
-    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
-#pragma unroll
-    for (int cc = threadIdx.x; cc < TL::NC; cc += TL::NT) {
-    const int tx = cc % TL::TX, ty = (cc / TL::TX) % TL::TY, tz = cc / (TL::TX * TL::TY);
-    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-    const bool inside = x < nx && y < ny && (NDIM == 2 || z < nz);
-    if (inside) {
-        const int bi = (tx + 1) + (ty + 1) * TL::BX + (NDIM == 3 ? (tz + 1) * TL::BX * TL::BY : 0);
-        const int gc[3] = {x, y, z};
-        const T uc = sU[bi];
-        T acc = T(0);
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d) {
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                // face between cells c0 = (side ? c : c - e_d) and c1 = c0 + e_d
-                const int i0 = side ? bi : bi - bstr[d];
-                const int i1 = i0 + bstr[d];
-                const int g0 = side ? gc[d] : gc[d] - 1;
-                const bool wall = !periodic && !dir && (g0 < 0 || g0 + 1 > P.n[d] - 1);
-                if (wall) continue;
-                const T bnf = T(0.5) * (sB[d][i0] + sB[d][i1]);
-                T chif = P.chi_par;
-                if (P.chi || P.chi_exp != 0.0) chif = harmonic<T>(sChi[i0], sChi[i1]);
-                const T dpar = chif - P.chi_perp;
-                const T alpha = P.cn[d] * (P.chi_perp + dpar * bnf * bnf);
-                T tr = T(0);
-#pragma unroll
-                for (int t = 0; t < NDIM; ++t) {
-                    if (t == d) continue;
-                    const T btf = T(0.5) * (sB[t][i0] + sB[t][i1]);
-                    tr += P.ct[d][t] * btf * limit2<T>(lim, sS[t][i1], sS[t][i0]);
-                }
-                const T flux = dpar * bnf * tr;
-                const T diff = sU[i1] - sU[i0];
-                // the face adds +(alpha diff + F) to c0 and -(..) to c1
-                acc += side ? (alpha * diff + flux) : -(alpha * diff + flux);
-            }
-        }
-        const unsigned co = (unsigned)x + (unsigned)y * sy + (unsigned)z * sz;
-        const T un = P.Q ? (uc + P.dtq * P.Q[co]) + acc : uc + acc;
-        P.out[co] = un;
-        lsum += (double)un;
-        lmin = fmin(lmin, (double)un);
-        lmax = fmax(lmax, (double)un);
-    }
-    }
-    if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
 }
 
 // 2-D: one wave streams down a band of ExStream::TY rows of 64 columns
@@ -287,21 +148,181 @@ __global__ void __launch_bounds__(256) explicit_stream2d_kernel(ExplicitParams<T
     if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
 }
 
-// Blocks of an explicit launch (also sizes the reduction scratch).
-int explicit_num_blocks(int ndim, const int n[3]) {
-    if (ndim == 2) {
-        const int waves = ((n[0] + ExStream::COLS - 1) / ExStream::COLS) * ((n[1] + ExStream::TY - 1) / ExStream::TY);
-        const int blocks = (waves + ExStream::WAVES - 1) / ExStream::WAVES;
-        return (blocks + 7) & ~7;  // a multiple of 8 for the XCD-aware order
+// 3-D: the same scheme as the 2-D streaming kernel, one wave per block of
+// 62 columns x ExStream3<T>::TY rows x ExStream3<T>::TZ planes (lane =
+// column).  A wave loads its block plus a one-cell halo on every side (all
+// loads first, in plane order), evaluates every face once (x faces by a lane
+// shift, y faces between rows and z faces between planes in registers) and
+// updates its cells.  No LDS and no barrier apart from the final reduction.
+template <typename T>
+struct ExStream3 {
+    static constexpr int COLS = 62;
+    static constexpr int TY = 2;  // rows per wave
+    static constexpr int TZ = 2;  // planes per wave
+    static constexpr int WAVES = 4;
+};
+
+template <typename T, int LIMC>
+__global__ void __launch_bounds__(256) explicit_stream3d_kernel(ExplicitParams<T> P) {
+    using S = ExStream3<T>;
+    constexpr int TY = S::TY, TZ = S::TZ, NR = TY + 2, NP = TZ + 2;
+    const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+    const int lane = threadIdx.x & 63;
+    const int blk = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);  // XCD-aware order
+    const int wave = blk * S::WAVES + (threadIdx.x >> 6);
+    const int ncb = (nx + S::COLS - 1) / S::COLS, nrb = (ny + TY - 1) / TY, nzb = (nz + TZ - 1) / TZ;
+    double lsum = 0.0, lmin = __builtin_huge_val(), lmax = -__builtin_huge_val();
+    if (wave < ncb * nrb * nzb) {  // wave-uniform
+        const int cb = wave % ncb, rb = (wave / ncb) % nrb, zb = wave / (ncb * nrb);
+        const int x = cb * S::COLS - 1 + lane;
+        const int y0 = rb * TY, z0 = zb * TZ;
+        const bool periodic = P.periodic != 0;
+        const bool dir = P.dirichlet != 0;
+        const int lim = LIMC >= 0 ? LIMC : P.limiter;
+        const bool pchi = P.chi != nullptr || P.chi_exp != 0.0;
+        const int xc = nb_coord32(x, nx, periodic);
+        const bool xout = xc != x;
+        const unsigned sy = (unsigned)nx, sz = (unsigned)nx * (unsigned)ny;
+        // the block and its halo: plane q is z0-1+q, row r is y0-1+r
+        T u[NP][NR], bx[NP][NR], by[NP][NR], bz[NP][NR], ch[NP][NR], q[TZ][TY];
+#pragma unroll
+        for (int pq = 0; pq < NP; ++pq) {
+            const int z = z0 - 1 + pq;
+            const int zc = nb_coord32(z, nz, periodic);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int y = y0 - 1 + r;
+                const int yc = nb_coord32(y, ny, periodic);
+                const unsigned c = (unsigned)xc + (unsigned)yc * sy + (unsigned)zc * sz;
+                const T v = P.U[c];
+                // odd ghost: one sign flip per axis on which the cell lies outside
+                const int nout = (int)xout + (int)(yc != y) + (int)(zc != z);
+                u[pq][r] = dir && (nout & 1) ? -v : v;
+                bx[pq][r] = P.b[0][c];
+                by[pq][r] = P.b[1][c];
+                bz[pq][r] = P.b[2][c];
+                ch[pq][r] = P.chi ? P.chi[c] : P.chi_par;
+                // chi(T): the cell's value from T^n, in FP64 (section 3.3)
+                if (P.chi_exp != 0.0) ch[pq][r] = (T)((double)P.chi_par * pow((double)v / P.chi_tref, P.chi_exp));
+                if (P.Q && pq >= 1 && pq <= TZ && r >= 1 && r <= TY) q[pq - 1][r - 1] = P.Q[c];
+            }
+        }
+        const T chi_par = P.chi_par, chi_perp = P.chi_perp;
+        // face between cells 0 and 1 along the normal axis n; a and b are the
+        // two transverse axes in increasing order (components ta, tb of b,
+        // limited slopes sa, sb)
+        auto face = [&](T u0, T u1, T bn0, T bn1, T ta0, T ta1, T tb0, T tb1, T c0, T c1, T sa0, T sa1, T sb0,
+                        T sb1, T cn, T cta, T ctb) {
+            const T bnf = T(0.5) * (bn0 + bn1);
+            const T chif = pchi ? harmonic<T>(c0, c1) : chi_par;
+            const T dpar = chif - chi_perp;
+            const T alpha = cn * (chi_perp + dpar * bnf * bnf);
+            T tr = T(0);
+            tr += cta * (T(0.5) * (ta0 + ta1)) * limit2<T>(lim, sa1, sa0);
+            tr += ctb * (T(0.5) * (tb0 + tb1)) * limit2<T>(lim, sb1, sb0);
+            const T flux = dpar * bnf * tr;
+            return alpha * (u1 - u0) + flux;
+        };
+        // limited slopes: along x for every loaded cell (lane shifts), along
+        // y for the inner rows, along z for the inner planes
+        T sxs[NP][NR], sys[NP][NR], szs[NP][NR];
+#pragma unroll
+        for (int pq = 0; pq < NP; ++pq) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                sxs[pq][r] = cell_slope<T>(lim, from_left(u[pq][r]), u[pq][r], from_right(u[pq][r]));
+                sys[pq][r] = (r >= 1 && r <= TY) ? cell_slope<T>(lim, u[pq][r - 1], u[pq][r], u[pq][r + 1]) : T(0);
+                szs[pq][r] = (pq >= 1 && pq <= TZ) ? cell_slope<T>(lim, u[pq - 1][r], u[pq][r], u[pq + 1][r]) : T(0);
+            }
+        }
+        const bool xwall = !periodic && !dir && (x < 0 || x + 1 > nx - 1);
+        const bool out_col = lane >= 1 && lane <= S::COLS && x < nx;
+        // lower z faces of the first plane
+        T fz_lo[TY];
+        {
+            const bool zwall = !periodic && !dir && (z0 - 1 < 0 || z0 > nz - 1);
+#pragma unroll
+            for (int r = 1; r <= TY; ++r) {
+                const T f = face(u[0][r], u[1][r], bz[0][r], bz[1][r], bx[0][r], bx[1][r], by[0][r], by[1][r], ch[0][r],
+                                 ch[1][r], sxs[0][r], sxs[1][r], sys[0][r], sys[1][r], P.cn[2], P.ct[2][0], P.ct[2][1]);
+                fz_lo[r - 1] = zwall ? T(0) : f;
+            }
+        }
+#pragma unroll
+        for (int pq = 1; pq <= TZ; ++pq) {
+            const int z = z0 - 1 + pq;
+            // y faces of this plane, rows r and r+1, r = 0 .. TY
+            T fy[TY + 1];
+#pragma unroll
+            for (int r = 0; r <= TY; ++r) {
+                const int y = y0 - 1 + r;
+                const bool ywall = !periodic && !dir && (y < 0 || y + 1 > ny - 1);
+                const T f = face(u[pq][r], u[pq][r + 1], by[pq][r], by[pq][r + 1], bx[pq][r], bx[pq][r + 1], bz[pq][r],
+                                 bz[pq][r + 1], ch[pq][r], ch[pq][r + 1], sxs[pq][r], sxs[pq][r + 1], szs[pq][r],
+                                 szs[pq][r + 1], P.cn[1], P.ct[1][0], P.ct[1][2]);
+                fy[r] = ywall ? T(0) : f;
+            }
+            const bool zwall = !periodic && !dir && (z < 0 || z + 1 > nz - 1);
+#pragma unroll
+            for (int r = 1; r <= TY; ++r) {
+                const int y = y0 - 1 + r;
+                T fxr = face(u[pq][r], from_right(u[pq][r]), bx[pq][r], from_right(bx[pq][r]), by[pq][r],
+                             from_right(by[pq][r]), bz[pq][r], from_right(bz[pq][r]), ch[pq][r], from_right(ch[pq][r]),
+                             sys[pq][r], from_right(sys[pq][r]), szs[pq][r], from_right(szs[pq][r]), P.cn[0],
+                             P.ct[0][1], P.ct[0][2]);
+                fxr = xwall ? T(0) : fxr;
+                const T fxl = from_left(fxr);
+                T fzh = face(u[pq][r], u[pq + 1][r], bz[pq][r], bz[pq + 1][r], bx[pq][r], bx[pq + 1][r], by[pq][r],
+                             by[pq + 1][r], ch[pq][r], ch[pq + 1][r], sxs[pq][r], sxs[pq + 1][r], sys[pq][r],
+                             sys[pq + 1][r], P.cn[2], P.ct[2][0], P.ct[2][1]);
+                fzh = zwall ? T(0) : fzh;
+                T acc = T(0);
+                acc += -fxl;
+                acc += fxr;
+                acc += -fy[r - 1];
+                acc += fy[r];
+                acc += -fz_lo[r - 1];
+                acc += fzh;
+                if (out_col && y < ny && z < nz) {
+                    const T uc = u[pq][r];
+                    const T un = P.Q ? (uc + P.dtq * q[pq - 1][r - 1]) + acc : uc + acc;
+                    P.out[(unsigned)x + (unsigned)y * sy + (unsigned)z * sz] = un;
+                    lsum += (double)un;
+                    lmin = fmin(lmin, (double)un);
+                    lmax = fmax(lmax, (double)un);
+                }
+                fz_lo[r - 1] = fzh;
+            }
+        }
     }
-    using TL = ExTile;
-    return ((n[0] + TL::TX - 1) / TL::TX) * ((n[1] + TL::TY - 1) / TL::TY) *
-           ((n[2] + TL::TZ - 1) / TL::TZ);
+    if (P.red.partials) block_partials(P.red.partials, lsum, lmin, lmax);
+}
+
+// Blocks of an explicit launch: a multiple of 8 for the XCD-aware order.
+template <typename T>
+static int explicit_blocks_t(int ndim, const int n[3]) {
+    int waves, per_block;
+    if (ndim == 2) {
+        waves = ((n[0] + ExStream::COLS - 1) / ExStream::COLS) * ((n[1] + ExStream::TY - 1) / ExStream::TY);
+        per_block = ExStream::WAVES;
+    } else {
+        using S = ExStream3<T>;
+        waves = ((n[0] + S::COLS - 1) / S::COLS) * ((n[1] + S::TY - 1) / S::TY) * ((n[2] + S::TZ - 1) / S::TZ);
+        per_block = S::WAVES;
+    }
+    const int blocks = (waves + per_block - 1) / per_block;
+    return (blocks + 7) & ~7;
+}
+
+// The larger of the two precisions' block counts (sizes the reduction scratch).
+int explicit_num_blocks(int ndim, const int n[3]) {
+    const int a = explicit_blocks_t<float>(ndim, n), b = explicit_blocks_t<double>(ndim, n);
+    return a > b ? a : b;
 }
 
 template <typename T>
 hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st, int* nblocks_out) {
-    const int nb = explicit_num_blocks(ndim, P.n);
+    const int nb = explicit_blocks_t<T>(ndim, P.n);
     if (nblocks_out) *nblocks_out = nb;
     const bool vl = P.limiter == LIM_VANLEER;
     if (ndim == 2) {
@@ -309,8 +330,9 @@ hipError_t launch_explicit(const ExplicitParams<T>& P, int ndim, hipStream_t st,
         if (vl) hipLaunchKernelGGL((explicit_stream2d_kernel<T, LIM_VANLEER>), dim3(nb), dim3(NT), 0, st, P);
         else hipLaunchKernelGGL((explicit_stream2d_kernel<T, -1>), dim3(nb), dim3(NT), 0, st, P);
     } else {
-        if (vl) hipLaunchKernelGGL((explicit3d_kernel<T, LIM_VANLEER>), dim3(nb), dim3(ExTile::NT), 0, st, P);
-        else hipLaunchKernelGGL((explicit3d_kernel<T, -1>), dim3(nb), dim3(ExTile::NT), 0, st, P);
+        constexpr int NT = 64 * ExStream3<T>::WAVES;
+        if (vl) hipLaunchKernelGGL((explicit_stream3d_kernel<T, LIM_VANLEER>), dim3(nb), dim3(NT), 0, st, P);
+        else hipLaunchKernelGGL((explicit_stream3d_kernel<T, -1>), dim3(nb), dim3(NT), 0, st, P);
     }
     return hipGetLastError();
 }
