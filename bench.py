@@ -259,6 +259,23 @@ def three_d(stream, torch, asd, nsteps=50, ncfl=10.0, four_step=False):
             "energy_rel_drift": float(abs(e[-1] - e[0]) / abs(e[0]))}
 
 
+def explicit_3d(stream, torch, asd, nsteps=50):
+    """The explicit limited step on the 256^3 FP32 problem at ncfl = 1
+    (chi dt/h^2 = 0.25, inside the 3-D limit of 0.444)."""
+    import synth
+    p = synth.curl3d_problem(256, nsteps=nsteps)
+    g = make_grid(p, "f32", stream, torch, asd)
+    dt = synth.ncfl_dt(1.0, p.h, 1.0)
+    ebuf = torch.empty(nsteps + 1, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        g.step_explicit(dt, nsteps, out=ebuf)
+        ms = timed(lambda: g.step_explicit(dt, nsteps, out=ebuf), stream, torch)
+    return {"cells": p.ncells, "steps": nsteps, "ms_per_step": round(ms / nsteps, 4),
+            "Gcells": round(p.ncells * nsteps / (ms * 1e-3) / 1e9, 3),
+            # 4 B in + 12 B b + 4 B out per cell
+            "algorithmic_GBs": round(p.ncells * 20 * nsteps / (ms * 1e-3) / 1e9, 1)}
+
+
 def adjoint_1024(stream, torch, asd, n=1024, nsteps=50, ckpt_every=10):
     """The adjoint workload: 1024^2 FP32, per-cell chi, 50 semi-implicit
     steps with checkpoints every 10.  Times the forward steps and the
@@ -523,6 +540,7 @@ def main():
         if "3d" in names:
             extra["curl3d_256"] = three_d(stream, torch, asd)
             extra["curl3d_256_four_step"] = three_d(stream, torch, asd, ncfl=40.0, four_step=True)
+            extra["curl3d_256_explicit"] = explicit_3d(stream, torch, asd)
         if "adjoint" in names:
             extra["adjoint_1024"] = adjoint_1024(stream, torch, asd)
         if "ring" in names:
