@@ -113,3 +113,23 @@ def test_ring_512_explicit_min_temperature():
     assert m_vl >= 0.1 * (1 - 1e-12), m_vl
     m_lin, _ = _ring512_min(1.0, scheme="ex", limiter="linear")
     assert m_lin < -0.05, m_lin
+
+
+def test_matched_l1_reference_against_oracle_128():
+    """The fine-step reference of the matched-L1 speed-up protocol (the
+    explicit limited scheme in FP64 at ncfl = 0.25, to 100 semi-implicit
+    steps at ncfl = 20: 8000 steps), on a 128^2 variant of the 1024^2
+    workload, against the oracle; and the L1 error of the semi-implicit run
+    at ncfl = 20 measured against it, GPU and oracle alike."""
+    base = synth.grf2d_problem(128, nsteps=1)
+    dt_si = synth.ncfl_dt(20.0, base.h, 1.0)
+    dt_f = synth.ncfl_dt(0.25, base.h, 1.0)
+    n_f = int(round(100 * dt_si / dt_f))
+    ref_o = oracle_run(base, "f64", nsteps=n_f, scheme="ex", dt=dt_f)
+    ref_g = GpuProblem(base, "f64").run(nsteps=n_f, scheme="ex", dt=dt_f)
+    assert max_rel_err(ref_g, ref_o) <= TOL["f64"], max_rel_err(ref_g, ref_o)
+    si_o = oracle_run(base, "f64", nsteps=100, scheme="si", dt=dt_si)
+    si_g = GpuProblem(base, "f64").run(nsteps=100, scheme="si", dt=dt_si)
+    l1_o = float(np.abs(si_o - ref_o).mean())
+    l1_g = float(np.abs(si_g - ref_g).mean())
+    assert l1_g > 0.0 and abs(l1_g - l1_o) <= 1e-9 * l1_o, (l1_g, l1_o)
