@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip secondary measurements")
     ap.add_argument("--extra", default="all",
                     help="comma-separated secondary measurements to run: copy, fp64, explicit, speedup, "
-                         "batched, 3d, adjoint, ring, sovinec (default all)")
+                         "batched, 3d, adjoint, ring, sovinec, slab (default all)")
     ap.add_argument("--tune", type=int, default=1, help="run the launch-shape autotuner first")
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain copy of 64 MiB (calibrates rocprofv3 byte counters)")
@@ -257,6 +257,24 @@ def three_d(stream, torch, asd, nsteps=50, ncfl=10.0, four_step=False):
             # 4-step scheme adds per direction a solve (4 B in + 4 B alpha + 4 B out)
             "algorithmic_GBs": round(p.ncells * (96 if four_step else 60) * nsteps / (ms * 1e-3) / 1e9, 1),
             "energy_rel_drift": float(abs(e[-1] - e[0]) / abs(e[0]))}
+
+
+def slab_shares(stream, torch, asd, nsteps=200):
+    """One GPU's share of the 1024^2 FP32 workload sliced into G slabs along
+    y: the semi-implicit step on 1024 x (1024 / G) cells, autotuned.  The y
+    sweep runs on periodic lines of 1024 / G cells, standing in for the local
+    part of the partitioned solve that would span the GPUs."""
+    import synth
+    out = []
+    for G in (2, 4, 8):
+        p = synth.grf2d_problem(NX, NX // G, nsteps=nsteps)
+        g = make_grid(p, "f32", stream, torch, asd)
+        with torch.cuda.stream(stream):
+            g.tune(p.dt, reps=10)
+        ms, _ = run_si(g, p, nsteps, nsteps, stream, torch)
+        out.append({"gpus": G, "cells_per_gpu": p.ncells, "ms_per_step": round(ms, 6),
+                    "Gcells_per_gpu": round(p.ncells / (ms * 1e-3) / 1e9, 3)})
+    return out
 
 
 def explicit_3d(stream, torch, asd, nsteps=50):
@@ -511,7 +529,7 @@ def main():
         "energy_rel_drift": drift,
     }
     names = set() if args.no_extra else (
-        {"copy", "fp64", "explicit", "speedup", "batched", "3d", "adjoint", "ring", "sovinec"}
+        {"copy", "fp64", "explicit", "speedup", "batched", "3d", "adjoint", "ring", "sovinec", "slab"}
         if args.extra == "all" else set(args.extra.split(",")))
     if names:
         extra = {}
@@ -547,6 +565,8 @@ def main():
             extra["ring512"] = ring512(stream, torch, asd)
         if "sovinec" in names:
             extra["sovinec"] = sovinec(stream, torch, asd)
+        if "slab" in names:
+            extra["slab_shares"] = slab_shares(stream, torch, asd)
         result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
