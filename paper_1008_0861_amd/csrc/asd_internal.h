@@ -42,7 +42,7 @@ inline size_t sweep_lds(int es, int ndim, int n, int lpw, int nthreads, int mmax
 
 inline int sweep_threads_cap(int es, int mmax) {
     const int bytes = es * mmax;
-    return bytes >= 64 ? 256 : (bytes >= 32 ? 512 : 1024);
+    return bytes >= 128 ? 256 : (bytes >= 32 ? 512 : 1024);
 }
 
 // Fill *out for a line of n cells.  want_wpl / want_lpw: 0 = heuristic.

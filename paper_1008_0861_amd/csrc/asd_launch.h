@@ -88,7 +88,7 @@ hipError_t launch_coef(const CoefParams<T>& C, hipStream_t st);
 template <typename T, int MMAX>
 struct SweepBounds {
     static constexpr int bytes = (int)sizeof(T) * MMAX;
-    static constexpr int max_threads = bytes >= 64 ? 256 : (bytes >= 32 ? 512 : 1024);
+    static constexpr int max_threads = bytes >= 128 ? 256 : (bytes >= 32 ? 512 : 1024);
 };
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block,

@@ -96,7 +96,7 @@ def test_bad_descriptions(asd, mutate, code):
     assert asd.last_error()
 
 
-@pytest.mark.parametrize("ndim,dtype,nmax", [(2, "float32", 4096), (3, "float32", 4096),
+@pytest.mark.parametrize("ndim,dtype,nmax", [(2, "float32", 8192), (3, "float32", 6381),
                                              (2, "float64", 4096), (3, "float64", 3181)])
 def test_longest_line(asd, ndim, dtype, nmax):
     """The documented maximum line length is accepted on every axis and one
