@@ -130,11 +130,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_grf2d1024_fp32.json
 
 
 def kernel_source_digest():
-    """Digest of the sources that define the timed sweep kernel."""
+    """Digest of the sources and build flags that define the timed sweep kernel."""
     import hashlib
     h = hashlib.sha256()
     for f in ("sweep.hip", "sweep_tile.h", "asd_device.h", "asd_launch.h"):
         h.update(open(os.path.join(ROOT, "paper_1008_0861_amd", "csrc", f), "rb").read())
+    from paper_1008_0861_amd import build as _build
+    h.update(repr((_build.FLAGS, _build.SOURCE_FLAGS.get("sweep.hip", []))).encode())
     return h.hexdigest()[:16]
 
 

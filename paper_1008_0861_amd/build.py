@@ -24,12 +24,16 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
+# Per-source additions.  sweep.hip: gfx950 kernel-argument preloading of the
+# sweep kernel's leading scalar arguments (the compiler preloads at most 14
+# dwords; the kernel's argument list is laid out for that).
+SOURCE_FLAGS = {"sweep.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=16"]}
 
 
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", path, "-o", obj]
+    cmd = [HIPCC, "-x", "hip", *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, r.returncode, r.stdout + r.stderr, obj
 

@@ -41,6 +41,11 @@ struct SweepParams {
     int nt1, nt2;     // lines along transverse axes 1, 2 (nt2 = 1 in 2-D)
     int si_n, si_t1, si_t2;  // input strides, elements
     int so_n, so_t1, so_t2;  // output strides, elements
+    // nseg_log2 completes the 16-byte block of the output strides: every
+    // sweep instantiation uses all four, so the kernel's one scalar load of
+    // them has no dead register that the compiler could reuse (and wait for)
+    // before the wave's first global load
+    int nseg_log2;    // log2(P)
     int periodic;
     int dirichlet;    // T = 0 walls: odd ghosts; the wrap-face entries of alpha / beta1
                       // hold the right / left wall coefficients of the line
@@ -50,7 +55,6 @@ struct SweepParams {
     int wpl;          // waves per line
     int lpw;          // lines per workgroup
     int P;            // segments per line: power of two, <= 64*wpl, <= n
-    int nseg_log2;    // log2(P)
     int spl_log2;     // log2(64*wpl)
     int lpw_log2;     // log2(lpw)
     int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)

@@ -5,16 +5,41 @@
 
 namespace asd {
 
+// The parameters every wave needs before its first global load arrive as
+// leading scalar arguments, which the build preloads into scalar registers
+// at wave launch (gfx950 kernel-argument preloading, at most 14 dwords): the
+// wave then issues its loads without first waiting on a scalar load of the
+// argument block.  The remaining fields are read from P as usual; the
+// leading arguments override the copies of those fields in P.
+//   packed: bits 0-3 log2(64 wpl), 4-7 log2(lpw), 8 periodic, 9 solve only,
+//           10-14 LDS pad, 15 aligned tile layout.
 template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
-__global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads)) sweep_kernel(SweepParams<T> P) {
+__global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
+    sweep_kernel(const T* U, const T* alpha, const T* beta1, int n, int nt1, int si_t1, int si_t2, int nb1,
+                 int nblk, int packed, int row1, SweepParams<T> Pk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    SweepParams<T> P = Pk;
+    P.U = U;
+    P.alpha = alpha;
+    P.beta1 = beta1;
+    P.n = n;
+    P.nt1 = nt1;
+    P.si_t1 = si_t1;
+    P.si_t2 = si_t2;
+    P.spl_log2 = packed & 15;
+    P.wpl = 1 << (P.spl_log2 - 6);
+    P.lpw_log2 = (packed >> 4) & 15;
+    P.lpw = 1 << P.lpw_log2;
+    P.periodic = (packed >> 8) & 1;
+    P.rhs_mode = (packed >> 9) & 1;
+    P.lds.pad = (packed >> 10) & 31;
+    P.lds.aligned = (packed >> 15) & 1;
+    P.lds.row1 = row1;
     // XCD-aware block order: consecutive logical blocks on the same XCD so
     // that halo lines and the partial lines of a transposed store are shared
     // through that XCD's L2.
     int blk = blockIdx.x;
-    const int nblk = gridDim.x;
     if ((nblk & 7) == 0) blk = (blk & 7) * (nblk >> 3) + (blk >> 3);
-    const int nb1 = (P.nt1 + P.lpw - 1) / P.lpw;
     const int l2 = blk / nb1;
     const int l1_0 = (blk - l2 * nb1) * P.lpw;
     double lsum;
@@ -31,14 +56,22 @@ template <typename T, int NDIM>
 static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid, dim3 block, size_t lds,
                                    hipStream_t st) {
     const bool ext = P.dirichlet || P.Q;
+    if (P.lpw != (1 << P.lpw_log2) || 64 * P.wpl != (1 << P.spl_log2) || P.spl_log2 > 15 || P.lpw_log2 > 15 ||
+        P.lds.pad < 0 || P.lds.pad > 31)
+        return hipErrorInvalidValue;
+    // the kernel's leading (preloaded) arguments; P.rhs_mode holds 0 or SWEEP_SOLVE_ONLY
+    const int nb1 = (P.nt1 + P.lpw - 1) / P.lpw;
+    const int packed = P.spl_log2 | (P.lpw_log2 << 4) | ((P.periodic != 0) << 8) | ((P.rhs_mode != 0) << 9) |
+                       (P.lds.pad << 10) | ((P.lds.aligned != 0) << 15);
+#define ASD_SWEEP_ARGS P.U, P.alpha, P.beta1, P.n, P.nt1, P.si_t1, P.si_t2, nb1, (int)grid.x, packed, P.lds.row1, P
 #define ASD_SWEEP_CASE(MM)                                                                          \
     case MM:                                                                                        \
         if (ext)                                                                                    \
-            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1, true>), grid, block, lds, st, P);     \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1, true>), grid, block, lds, st, ASD_SWEEP_ARGS);     \
         else if (P.limiter == LIM_VANLEER)                                                          \
-            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, LIM_VANLEER, false>), grid, block, lds, st, P); \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, LIM_VANLEER, false>), grid, block, lds, st, ASD_SWEEP_ARGS); \
         else                                                                                        \
-            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1, false>), grid, block, lds, st, P);    \
+            hipLaunchKernelGGL((sweep_kernel<T, NDIM, MM, -1, false>), grid, block, lds, st, ASD_SWEEP_ARGS);    \
         return hipGetLastError();
     switch (mmax) {
         ASD_SWEEP_CASE(1)
@@ -49,6 +82,7 @@ static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid,
         default: return hipErrorInvalidValue;
     }
 #undef ASD_SWEEP_CASE
+#undef ASD_SWEEP_ARGS
 }
 
 // Raise the dynamic-LDS limit of every sweep instantiation to the gfx950
