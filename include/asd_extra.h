@@ -74,8 +74,9 @@ int asd_get_sweep_config(asd_grid g, int32_t axis, int32_t *wpl, int32_t *lpw, i
 int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw);
 
 /* Time every admissible (wpl, lpw) of each sweep on the grid's stream with
- * HIP events (reps launches each, T -> workspace, T unchanged) and keep the
- * fastest.  Needs T and b set.  Synchronises the stream. */
+ * HIP events (reps whole steps each, best of three timings, T -> workspace,
+ * T unchanged) and keep the fastest; two passes over the axes.  Needs T and
+ * b set.  Synchronises the stream. */
 int asd_tune(asd_grid g, double dt, int32_t reps);
 
 /* Enable (1) or disable (0) hipGraph capture of multi-step calls (on by
