@@ -147,10 +147,10 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
             if (rc) return rc;
             rc = stencil<T>(g, 1, dt, mu, TS[i], S[i + 1], lam, gchi);
             if (rc) return rc;
-            // x sweep: T^n -> T*
-            rc = enqueue_sweep(g, 0, dt, lam, tB, 1, no_reduce(), nullptr, nullptr);
-            if (rc) return rc;
-            rc = enqueue_permute_2d(g, tB, mu, false);
+            // x sweep: T^n -> T*; the solve writes mu in the natural layout
+            // directly (line-contiguous store, no transpose)
+            rc = enqueue_sweep(g, 0, dt, lam, mu, SWEEP_SOLVE_ONLY | SWEEP_KEEP_LAYOUT, no_reduce(), nullptr,
+                               nullptr);
             if (rc) return rc;
             rc = stencil<T>(g, 0, dt, mu, S[i], TS[i], lam, gchi);
             if (rc) return rc;
