@@ -15,9 +15,10 @@ extern "C" {
 /* ------------------------------------------------------------------ batch
  * Many independent 2-D problems of uneven sizes advanced together: the
  * semi-implicit step of asd.h (section 2, Eqs. xup / yup) applied to each
- * problem with its own grid, b field, chi_par and dt.  Problems share bc,
- * dtype and limiter (taken from descs[0]); each desc gives n, h, chi_par,
- * chi_perp of its problem.  FP32 or FP64; ndim must be 2. */
+ * problem with its own grid, b field, chi_par and dt.  Problems share bc
+ * (periodic, insulating or T = 0 walls; no source term), dtype and limiter
+ * (taken from descs[0]); each desc gives n, h, chi_par, chi_perp of its
+ * problem.  FP32 or FP64; ndim must be 2. */
 typedef struct asd_batch_s *asd_batch;
 
 /* Workspace bytes for nprob problems (descs: host array of nprob). */

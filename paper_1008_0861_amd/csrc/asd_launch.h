@@ -132,10 +132,10 @@ struct BatchProblem {
 };
 template <typename T>
 hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
-                                   int mmax, int nthreads, size_t lds, int limiter, hipStream_t st);
+                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
-                                int mmax, int nthreads, size_t lds, int limiter, hipStream_t st);
+                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, hipStream_t st);
 hipError_t batch_set_lds_limits(int bytes);
 
 // ----------------------------------------------------------------- adjoint

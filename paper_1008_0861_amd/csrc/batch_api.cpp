@@ -59,8 +59,6 @@ static int check_descs(const asd_desc* descs, int32_t nprob) {
         int rc = validate_desc(&descs[p]);
         if (rc) return rc;
         if (descs[p].ndim != 2) return asd_fail(ASD_EUNSUPPORTED, "batched problems must be 2-D");
-        if (descs[p].bc == ASD_BC_DIRICHLET)
-            return asd_fail(ASD_EUNSUPPORTED, "batched problems are periodic or insulating");
         if (descs[p].bc != descs[0].bc || descs[p].dtype != descs[0].dtype || descs[p].limiter != descs[0].limiter)
             return asd_fail(ASD_EINVAL, "problem %d: bc, dtype and limiter must match problem 0", p);
         if ((descs[p].flags & ASD_FLAG_PER_CELL_CHI) || descs[p].chi_exp != 0.0)
@@ -284,12 +282,12 @@ static int batch_step_t(asd_batch b, int nsteps, int mode) {
     hipError_t e = hipSuccess;
     if (mode == 0) {
         e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds,
-                                       b->d0.limiter, b->st);
+                                       b->d0.limiter, b->d0.bc == ASD_BC_DIRICHLET, b->st);
     } else {
         for (int s = 0; s < nsteps && e == hipSuccess; ++s)
             for (int d = 0; d < 2 && e == hipSuccess; ++d)
                 e = launch_batch_grouped<T>(probs, b->d_gs[d], b->nprob, b->ngroups[d], d, b->mmax, b->nthreads,
-                                            b->lds, b->d0.limiter, b->st);
+                                            b->lds, b->d0.limiter, b->d0.bc == ASD_BC_DIRICHLET, b->st);
     }
     if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch launch: %s", hipGetErrorString(e));
     return ASD_OK;

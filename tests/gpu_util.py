@@ -87,3 +87,15 @@ class GpuProblem:
 
 def max_rel_err(got, ref):
     return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)))
+
+
+def mixed_rel_err(got, ref):
+    """Relative error per cell with the denominator floored at 0.1 max|T|.
+    T = 0 walls pull cells towards zero; there the solve forms the cell as
+    U + delta with U and delta of the field's size, so its rounding is
+    absolute (a few eps max|T|), not relative to the small result.  The
+    floor turns the bar into an absolute 0.1 TOL max|T| for those cells
+    (1e-6 max|T| in FP32, about 16 eps; 1e-13 in FP64) and leaves it
+    relative elsewhere."""
+    scale = float(np.max(np.abs(ref)))
+    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 0.1 * scale)))

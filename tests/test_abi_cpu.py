@@ -209,10 +209,12 @@ def test_batch_refuses_chi_of_T(asd):
     assert rc == 0
 
 
-def test_batch_refuses_dirichlet(asd):
-    descs = (asd.Desc * 2)(_desc(asd), _desc(asd, bc="dirichlet"))
+def test_batch_boundary_conditions(asd):
+    # T = 0 walls are accepted; every problem of a batch takes problem 0's bc
     n = ctypes.c_size_t()
-    assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == -8
-    assert "periodic or insulating" in asd.last_error()
-    rc, _ = _rc_ws(asd, _desc(asd, bc="dirichlet", shape=(2, 2), h=(1.0, 1.0)))
-    assert rc == 0
+    descs = (asd.Desc * 2)(_desc(asd, bc="dirichlet"), _desc(asd, bc="dirichlet", shape=(7, 5)))
+    assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == 0
+    assert n.value > 0
+    descs = (asd.Desc * 2)(_desc(asd), _desc(asd, bc="dirichlet"))
+    assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == -1
+    assert "must match problem 0" in asd.last_error()

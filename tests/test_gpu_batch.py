@@ -1,19 +1,21 @@
 """Batched uneven problems (asd_batch_*): every schedule against the oracle,
 problem by problem, on identical inputs."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
 
 import synth
 from paper_1008_0861_amd import binding as asd
-from tests.gpu_util import TOL, max_rel_err, oracle_run, tol_steps
+from tests.gpu_util import TOL, max_rel_err, mixed_rel_err, oracle_run, tol_steps
 
 pytestmark = pytest.mark.gpu
 
 DT = {"f32": torch.float32, "f64": torch.float64}
 
 
-def _gpu_batch(probs, prec, stream):
+def _gpu_batch(probs, prec, stream, bc="periodic"):
     dt = DT[prec]
     items = []
     with torch.cuda.stream(stream):
@@ -22,7 +24,7 @@ def _gpu_batch(probs, prec, stream):
                               T=torch.from_numpy(p.T0).to(dt).cuda(),
                               bx=torch.from_numpy(p.b[0]).to(dt).cuda(),
                               by=torch.from_numpy(p.b[1]).to(dt).cuda()))
-        b = asd.Batch(items, dtype=dt)
+        b = asd.Batch(items, bc=bc, dtype=dt)
     return b, items
 
 
@@ -44,6 +46,24 @@ def test_batch_modes_match_oracle(mode, prec):
         ref = oracle_run(p, prec, nsteps=5)
         got = it["T"].double().cpu().numpy()
         assert max_rel_err(got, ref) <= TOL[prec], (p.name, p.shape)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_dirichlet_matches_oracle(mode, prec):
+    # T = 0 walls (odd ghosts) on every problem: the tiles run the wall path
+    # (wall diagonal terms, negated transverse neighbours of the wall lines)
+    probs = [dataclasses.replace(p, bc="dirichlet") for p in _small_batch(10, 19)]
+    st = torch.cuda.Stream()
+    b, items = _gpu_batch(probs, prec, st, bc="dirichlet")
+    with torch.cuda.stream(st):
+        b.step(5, mode)
+    st.synchronize()
+    for p, it in zip(probs, items):
+        ref = oracle_run(p, prec, nsteps=5)
+        got = it["T"].double().cpu().numpy()
+        # the walls pull cells towards zero: absolute rounding there
+        assert mixed_rel_err(got, ref) <= TOL[prec], (p.name, p.shape)
 
 
 @pytest.mark.parametrize("prec,nthreads", [("f64", 256), ("f64", 512), ("f32", 256), ("f32", 512), ("f32", 1024)])

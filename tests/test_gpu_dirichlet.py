@@ -9,7 +9,7 @@ import torch
 import synth
 from oracle import oracle
 from paper_1008_0861_amd import binding as asd
-from tests.gpu_util import TOL, GpuProblem, max_rel_err, oracle_run
+from tests.gpu_util import TOL, GpuProblem, max_rel_err, mixed_rel_err, oracle_run
 from tests.test_gpu_parity import _random_problem
 
 pytestmark = pytest.mark.gpu
@@ -24,16 +24,7 @@ def _dirichlet(shape, seed, source=True, per_cell_chi=False, nsteps=4, ncfl=20.0
     return dataclasses.replace(p, bc="dirichlet", src=src)
 
 
-def _mixed_err(got, ref):
-    """Relative error per cell with the denominator floored at 0.1 max|T|.
-    T = 0 walls pull cells towards zero; there the solve forms the cell as
-    U + delta with U and delta of the field's size, so its rounding is
-    absolute (a few eps max|T|), not relative to the small result.  The
-    floor turns the bar into an absolute 0.1 TOL max|T| for those cells
-    (1e-6 max|T| in FP32, about 16 eps; 1e-13 in FP64) and leaves it
-    relative elsewhere."""
-    scale = float(np.max(np.abs(ref)))
-    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 0.1 * scale)))
+_mixed_err = mixed_rel_err
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
