@@ -53,7 +53,7 @@ extern "C" {
 #define ASD_BC_DIRICHLET 2   /* T = 0 on the walls (section 3.2): odd ghost cells (T_ghost = -T_cell),
                                 the wall face's b and chi those of its cell, its normal flux
                                 implicit in the sweeps, no transverse flux through it.  Not for
-                                the adjoint or batched problems */
+                                the adjoint */
 
 /* element types */
 #define ASD_F32 0
