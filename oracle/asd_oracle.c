@@ -7,7 +7,10 @@
  * baseline leg of the benchmark load this file.  It shares no code, header,
  * table or helper with the GPU library; it is plain C99, serial, FP64, built
  * with -ffp-contract=off, and loops in the natural order so that every line
- * can be checked against the paper by eye.
+ * can be checked against the paper by eye.  A second build of the same
+ * source with OpenMP (liborc_omp.so) shares the independent lines of each
+ * sweep out over the host's cores for the all-core timing baseline; each
+ * line's arithmetic is unchanged, so both builds agree bit for bit.
  *
  * Layout of every cell array: index (k*ny + j)*nx + i, i (x) fastest.
  *
@@ -55,6 +58,9 @@
  */
 #include <math.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <string.h>
 
 #define ORC_BC_PERIODIC 0
@@ -349,11 +355,11 @@ static int line_face(const orc_grid *g, const double *U, int d, const long base[
  * before out is written (out must not alias U).  dt_t = 0 is a pure
  * implicit solve; dt_q = 0 (or no source) adds nothing.
  */
-int orc_sweep3(const orc_grid *g, int d, double dt_n, double dt_t, double dt_q, const double *U, double *out)
+/* One line of a sweep: base gives the line's coordinates on the two other axes. */
+static int sweep_line(const orc_grid *g, int d, double dt_n, double dt_t, double dt_q, const double *U,
+                      double *out, const long base[3])
 {
     const long n = g->n[d];
-    if (g->bc == ORC_BC_PERIODIC && n < 3) return -1;
-    if (n < 2) return -1;
     double *alpha = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     double *flux = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     int *wall = (int *)malloc(sizeof(int) * (size_t)(n + 1));
@@ -364,44 +370,35 @@ int orc_sweep3(const orc_grid *g, int d, double dt_n, double dt_t, double dt_q, 
     double *x = (double *)malloc(sizeof(double) * (size_t)n);
     int rc = 0;
     if (!alpha || !flux || !wall || !lo || !di || !up || !r || !x) rc = -1;
-
-    /* the two axes other than d enumerate the lines */
-    int ax1 = (d + 1) % 3, ax2 = (d + 2) % 3;
-    for (long l2 = 0; rc == 0 && l2 < g->n[ax2]; ++l2) {
-        for (long l1 = 0; rc == 0 && l1 < g->n[ax1]; ++l1) {
-            long base[3];
-            base[d] = 0;
-            base[ax1] = l1;
-            base[ax2] = l2;
-            /* faces k + 1/2 for k = -1 .. n-1; entry k+1 holds face k+1/2 */
-            for (long k = -1; k < n; ++k)
-                wall[k + 1] = line_face(g, U, d, base, k, dt_n, dt_t, &alpha[k + 1], &flux[k + 1]);
-            for (long i = 0; i < n; ++i) {
-                const double am = alpha[i];     /* face i - 1/2 */
-                const double ap = alpha[i + 1]; /* face i + 1/2 */
-                long p[3] = {base[0], base[1], base[2]};
-                p[d] = i;
-                lo[i] = -am;
-                up[i] = -ap;
-                di[i] = 1.0 + am + ap;
-                /* a Dirichlet wall face couples the cell to its odd ghost
-                   (x_ghost = -x_cell): 2 alpha on the diagonal, no
-                   off-diagonal entry (insulating walls have alpha = 0) */
-                if (wall[i]) { lo[i] = 0.0; di[i] += am; }
-                if (wall[i + 1]) { up[i] = 0.0; di[i] += ap; }
-                const long c = cell_index(g, p);
-                r[i] = U[c] + flux[i + 1] - flux[i];
-                if (g->src && dt_q != 0.0) r[i] += dt_q * g->src[c];
-            }
-            if (g->bc == ORC_BC_PERIODIC)
-                rc = orc_cyclic(n, lo, di, up, r, x);
-            else
-                rc = orc_thomas(n, lo, di, up, r, x);
-            for (long i = 0; rc == 0 && i < n; ++i) {
-                long p[3] = {base[0], base[1], base[2]};
-                p[d] = i;
-                out[cell_index(g, p)] = x[i];
-            }
+    if (rc == 0) {
+        /* faces k + 1/2 for k = -1 .. n-1; entry k+1 holds face k+1/2 */
+        for (long k = -1; k < n; ++k)
+            wall[k + 1] = line_face(g, U, d, base, k, dt_n, dt_t, &alpha[k + 1], &flux[k + 1]);
+        for (long i = 0; i < n; ++i) {
+            const double am = alpha[i];     /* face i - 1/2 */
+            const double ap = alpha[i + 1]; /* face i + 1/2 */
+            long p[3] = {base[0], base[1], base[2]};
+            p[d] = i;
+            lo[i] = -am;
+            up[i] = -ap;
+            di[i] = 1.0 + am + ap;
+            /* a Dirichlet wall face couples the cell to its odd ghost
+               (x_ghost = -x_cell): 2 alpha on the diagonal, no
+               off-diagonal entry (insulating walls have alpha = 0) */
+            if (wall[i]) { lo[i] = 0.0; di[i] += am; }
+            if (wall[i + 1]) { up[i] = 0.0; di[i] += ap; }
+            const long c = cell_index(g, p);
+            r[i] = U[c] + flux[i + 1] - flux[i];
+            if (g->src && dt_q != 0.0) r[i] += dt_q * g->src[c];
+        }
+        if (g->bc == ORC_BC_PERIODIC)
+            rc = orc_cyclic(n, lo, di, up, r, x);
+        else
+            rc = orc_thomas(n, lo, di, up, r, x);
+        for (long i = 0; rc == 0 && i < n; ++i) {
+            long p[3] = {base[0], base[1], base[2]};
+            p[d] = i;
+            out[cell_index(g, p)] = x[i];
         }
     }
     free(alpha);
@@ -413,6 +410,47 @@ int orc_sweep3(const orc_grid *g, int d, double dt_n, double dt_t, double dt_q, 
     free(r);
     free(x);
     return rc;
+}
+
+/*
+ * out = (1 + dt_n D_dd)^-1 (U + transverse fluxes of U at dt_t + dt_q Q)
+ * along axis d.  Every coefficient is computed from the complete input U
+ * before out is written (out must not alias U).  dt_t = 0 is a pure
+ * implicit solve; dt_q = 0 (or no source) adds nothing.  The lines are
+ * independent: a build with OpenMP (liborc_omp.so, the all-core timing
+ * baseline) shares them out over threads; each line's arithmetic is the
+ * same either way.
+ */
+int orc_sweep3(const orc_grid *g, int d, double dt_n, double dt_t, double dt_q, const double *U, double *out)
+{
+    const long n = g->n[d];
+    if (g->bc == ORC_BC_PERIODIC && n < 3) return -1;
+    if (n < 2) return -1;
+    /* the two axes other than d enumerate the lines */
+    const int ax1 = (d + 1) % 3, ax2 = (d + 2) % 3;
+    const long n1 = g->n[ax1], nlines = g->n[ax1] * g->n[ax2];
+    int rc = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : rc)
+#endif
+    for (long l = 0; l < nlines; ++l) {
+        long base[3];
+        base[d] = 0;
+        base[ax1] = l % n1;
+        base[ax2] = l / n1;
+        rc |= sweep_line(g, d, dt_n, dt_t, dt_q, U, out, base);
+    }
+    return rc ? -1 : 0;
+}
+
+/* Threads the oracle's sweeps use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 int orc_sweep2(const orc_grid *g, int d, double dt_n, double dt_t, const double *U, double *out)

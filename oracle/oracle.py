@@ -33,16 +33,16 @@ class _OrcGrid(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    """Load liborc.so, building it with gcc only when it is missing."""
-    global _lib
-    if _lib is None:
-        path = _build.LIB
+def lib(omp=False):
+    """Load liborc.so (omp: liborc_omp.so, the OpenMP build), building it
+    with gcc only when it is missing."""
+    if omp not in _libs:
+        path = _build.LIB_OMP if omp else _build.LIB
         if not os.path.exists(path):
-            _build.build()
+            _build.build(omp=omp)
         L = ctypes.CDLL(path)
         L.orc_lim2.restype = ctypes.c_double
         L.orc_lim2.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
@@ -68,10 +68,17 @@ def lib():
         L.orc_energy.argtypes = [ctypes.POINTER(_OrcGrid), _dp]
         L.orc_dt_from_ncfl.restype = ctypes.c_double
         L.orc_dt_from_ncfl.argtypes = [ctypes.POINTER(_OrcGrid), ctypes.c_double]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
         L.orc_grid_sizeof.restype = ctypes.c_long
         assert L.orc_grid_sizeof() == ctypes.sizeof(_OrcGrid), "orc_grid layout mismatch"
-        _lib = L
-    return _lib
+        _libs[omp] = L
+    return _libs[omp]
+
+
+def num_threads(omp=False):
+    """Threads the oracle's sweeps use."""
+    return lib(omp).orc_num_threads()
 
 
 def _ptr(a):
@@ -90,11 +97,13 @@ class OracleGrid:
     """
 
     def __init__(self, b, h, bc="periodic", limiter="vanleer", chi_par=1.0, chi_perp=0.0, chi=None,
-                 chi_exp=0.0, chi_tref=1.0, src=None):
+                 chi_exp=0.0, chi_tref=1.0, src=None, omp=False):
         """chi_exp != 0: temperature-dependent chi_par(T) = chi_par (T / chi_tref)^chi_exp
         from the state each sweep (or explicit step) reads (chi must then be None).
         bc "dirichlet": T = 0 on the boundary faces.  src: per-cell source Q,
-        dt Q added to the first sweep of each step."""
+        dt Q added to the first sweep of each step.  omp: run on the OpenMP
+        build (same results, lines shared out over the host's cores)."""
+        self._L = lib(omp)
         self.b = [_f64(c) for c in b]
         self.ndim = len(self.b)
         if self.ndim not in (2, 3):
@@ -145,7 +154,7 @@ class OracleGrid:
         """One directional sweep along axis (0=x, 1=y, 2=z); returns a new array."""
         U = self._check(U)
         out = np.empty_like(U)
-        rc = lib().orc_sweep(ctypes.byref(self._s), int(axis), float(dt), _ptr(U), _ptr(out))
+        rc = self._L.orc_sweep(ctypes.byref(self._s), int(axis), float(dt), _ptr(U), _ptr(out))
         if rc != 0:
             raise RuntimeError(f"orc_sweep failed ({rc})")
         return out
@@ -155,7 +164,7 @@ class OracleGrid:
         transverse (explicit) part at dt_transverse (0: a pure solve)."""
         U = self._check(U)
         out = np.empty_like(U)
-        rc = lib().orc_sweep2(ctypes.byref(self._s), int(axis), float(dt_normal), float(dt_transverse),
+        rc = self._L.orc_sweep2(ctypes.byref(self._s), int(axis), float(dt_normal), float(dt_transverse),
                               _ptr(U), _ptr(out))
         if rc != 0:
             raise RuntimeError(f"orc_sweep2 failed ({rc})")
@@ -165,7 +174,7 @@ class OracleGrid:
         """sweep2 plus dt_source Q on the right-hand side."""
         U = self._check(U)
         out = np.empty_like(U)
-        rc = lib().orc_sweep3(ctypes.byref(self._s), int(axis), float(dt_normal), float(dt_transverse),
+        rc = self._L.orc_sweep3(ctypes.byref(self._s), int(axis), float(dt_normal), float(dt_transverse),
                               float(dt_source), _ptr(U), _ptr(out))
         if rc != 0:
             raise RuntimeError(f"orc_sweep3 failed ({rc})")
@@ -178,17 +187,35 @@ class OracleGrid:
         T = self._check(T).copy()
         e = np.empty(nsteps + 1) if energy else None
         flags = (1 if four_step else 0) | (2 if reverse else 0)
-        rc = lib().orc_step_si_ex(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
+        rc = self._L.orc_step_si_ex(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
                                   _ptr(e) if e is not None else _dp(), flags)
         if rc != 0:
             raise RuntimeError(f"orc_step_si failed ({rc})")
         return (T, e) if energy else T
 
+    def step_si_stored(self, T, dt, nsteps=1, store=np.float32, rounding_seed=None):
+        """step_si (2-step scheme, sweeps x, y (, z), no source term) with the
+        state rounded to the type `store` after every sweep: the method as
+        an implementation computes it that keeps its state in that type but
+        evaluates each sweep exactly (in FP64).  Its difference from step_si
+        is the part of a reduced-precision run's error that the storage
+        alone causes.  rounding_seed: None rounds to nearest; an integer
+        rounds faithfully in seeded random directions (round_to), another
+        equally valid run of that precision."""
+        if self.src is not None:
+            raise ValueError("step_si_stored takes no source term")
+        rng = None if rounding_seed is None else np.random.default_rng(rounding_seed)
+        T = self._check(T).astype(store).astype(np.float64)
+        for _ in range(nsteps):
+            for axis in range(self.ndim):
+                T = round_to(self.sweep(axis, dt, T), store, rng)
+        return T
+
     def step_explicit(self, T, dt, nsteps=1, energy=False):
         """nsteps explicit limited steps; returns T (and energies if asked)."""
         T = self._check(T).copy()
         e = np.empty(nsteps + 1) if energy else None
-        rc = lib().orc_step_explicit(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
+        rc = self._L.orc_step_explicit(ctypes.byref(self._s), float(dt), int(nsteps), _ptr(T),
                                      _ptr(e) if e is not None else _dp())
         if rc != 0:
             raise RuntimeError(f"orc_step_explicit failed ({rc})")
@@ -196,10 +223,24 @@ class OracleGrid:
 
     def energy(self, T):
         T = self._check(T)
-        return lib().orc_energy(ctypes.byref(self._s), _ptr(T))
+        return self._L.orc_energy(ctypes.byref(self._s), _ptr(T))
 
     def dt_from_ncfl(self, ncfl):
-        return lib().orc_dt_from_ncfl(ctypes.byref(self._s), float(ncfl))
+        return self._L.orc_dt_from_ncfl(ctypes.byref(self._s), float(ncfl))
+
+
+def round_to(x, store, rng=None):
+    """x (FP64) rounded to the floating type `store`, returned as FP64.
+    rng None: to nearest.  Otherwise faithfully, in a random direction per
+    value: to the neighbour of `store` below or above x, each with
+    probability 1/2 (a value of `store` stays as it is)."""
+    f = x.astype(store)
+    if rng is None:
+        return f.astype(np.float64)
+    fd = f.astype(np.float64)
+    lo = np.where(fd > x, np.nextafter(f, store(-np.inf)), f)
+    hi = np.where(fd < x, np.nextafter(f, store(np.inf)), f)
+    return np.where(rng.random(x.shape) < 0.5, lo, hi).astype(np.float64)
 
 
 def lim2(limiter, a, b):

@@ -288,3 +288,50 @@ def test_perpendicular_numerical_diffusion_converges_second_order(orc):
     assert 2.0 < vals[16] / vals[32] < 4.5, vals
     assert 3.3 < vals[32] / vals[64] < 4.5, vals
     assert 5e-4 < vals[64] < 3e-3, vals
+
+
+def test_harmonic_face_chi_is_series_conduction(orc):
+    """Harmonic face diffusivity (section 2: a variable chi is averaged
+    harmonically at faces) is exact series conduction.  b = x_hat, a per-cell
+    chi that jumps by up to 100x from cell to cell, T = 0 walls and a source
+    in one column only: in the steady state every source-free stretch of a
+    row carries one constant heat flux F, and for a conductivity that is
+    constant inside each cell the exact solution drops by F times the two
+    half-cell resistances h/(2 chi_i) + h/(2 chi_i+1) between neighbouring
+    centres, and by F h/(2 chi) between a wall and its cell.  The fluxes
+    leaving the source column on both sides add up to Q h.  An arithmetic
+    face mean, or a wall face at a full cell width, fails these."""
+    nx, ny, k = 24, 3, 7
+    shape = (ny, nx)
+    h = (1.0 / nx, 0.25)
+    rng = np.random.default_rng(29)
+    chi_row = np.exp(rng.uniform(np.log(0.1), np.log(10.0), nx))
+    chi = np.tile(chi_row, (ny, 1))
+    q = 5.0
+    Q = np.zeros(shape)
+    Q[:, k] = q
+    g = orc.OracleGrid(const_field(shape, (1.0, 0.0)), h, bc="dirichlet", chi_par=1.0, chi=chi, src=Q)
+    dt = 1e3
+    T = g.step_si(np.zeros(shape), dt, 40)
+    T2 = g.step_si(T, dt, 1)
+    np.testing.assert_allclose(T2, T, rtol=1e-14, atol=0)  # steady
+    hx = h[0]
+    for row in T:
+        # right of the source: F_R leaves through the right wall
+        F_R = row[-1] / (hx / (2 * chi_row[-1]))
+        for i in range(k + 1, nx - 1):
+            R = hx / (2 * chi_row[i]) + hx / (2 * chi_row[i + 1])
+            assert abs((row[i] - row[i + 1]) / R - F_R) <= 1e-12 * abs(F_R)
+        # left of the source: F_L leaves through the left wall
+        F_L = row[0] / (hx / (2 * chi_row[0]))
+        for i in range(0, k - 1):
+            R = hx / (2 * chi_row[i]) + hx / (2 * chi_row[i + 1])
+            assert abs((row[i + 1] - row[i]) / R - F_L) <= 1e-12 * abs(F_L)
+        assert abs(F_L + F_R - q * hx) <= 1e-12 * q * hx
+        # the two faces of the source cell carry the same fluxes
+        R_k = hx / (2 * chi_row[k]) + hx / (2 * chi_row[k + 1])
+        assert abs((row[k] - row[k + 1]) / R_k - F_R) <= 1e-12 * abs(F_R)
+    # an arithmetic face mean would give different drops across the stretch
+    row = T[0]
+    arith = [(row[i] - row[i + 1]) * 0.5 * (chi_row[i] + chi_row[i + 1]) / hx for i in range(k + 1, nx - 1)]
+    assert np.ptp(arith) > 1e-2 * abs(np.mean(arith))
