@@ -14,17 +14,6 @@ NP = {"f32": np.float32, "f64": np.float64}
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
-def tol_steps(prec, nsteps):
-    """The FP32 bar for runs of more than 10 steps: every sweep rounds the
-    stored state and its own arithmetic, and two builds that only contract
-    differently (an FMA here or there) drift apart step by step; the bar
-    grows like a random walk of that per-step rounding, 1e-5 sqrt(nsteps/10).
-    FP64 keeps 1e-12."""
-    if prec == "f64":
-        return TOL["f64"]
-    return TOL["f32"] * max(1.0, (nsteps / 10.0) ** 0.5)
-
-
 def rounded(p, prec):
     """Inputs as the GPU sees them, back in float64 for the oracle."""
     r = lambda a: None if a is None else a.astype(NP[prec]).astype(np.float64)  # noqa: E731
@@ -46,6 +35,16 @@ def oracle_run(p, prec, nsteps=None, scheme="si", dt=None, energy=False, four_st
     if scheme == "si":
         return g.step_si(T0, dt, nsteps, energy=energy, four_step=four_step, reverse=reverse)
     return g.step_explicit(T0, dt, nsteps, energy=energy)
+
+
+def stored_oracle_run(p, prec, nsteps=None, rounding_seed=None):
+    """The oracle on the inputs the GPU sees, with its state rounded to the
+    GPU's storage type after every sweep (oracle.OracleGrid.step_si_stored;
+    rounding_seed: faithful rounding in seeded random directions)."""
+    b, T0, chi = rounded(p, prec)
+    g = oracle.OracleGrid(b, p.h, bc=p.bc, limiter=p.limiter, chi_par=p.chi_par, chi_perp=p.chi_perp, chi=chi)
+    nsteps = p.nsteps if nsteps is None else nsteps
+    return g.step_si_stored(T0, p.dt, nsteps, store=NP[prec], rounding_seed=rounding_seed)
 
 
 class GpuProblem:

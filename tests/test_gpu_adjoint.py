@@ -146,10 +146,13 @@ def test_autograd_function_matches_reference():
 
 def test_adjoint_1024_fp32_against_central_differences():
     """The full adjoint workload: 1024^2 FP32, 50 steps, checkpoints every 10,
-    L = sum (T_N - T_target)^2.  dL/dchi and dL/dT0 at 32 random cells
-    against central differences of the FP64 GPU forward (itself at oracle
-    parity).  A cell whose quotient changes between eps and eps/2 sits on a
-    limiter kink and is skipped."""
+    L = sum (T_N - T_target)^2.  dL/dchi and dL/dT0 at the same 32 random
+    cells each against central differences of the FP64 GPU forward (itself
+    at oracle parity).  A cell whose quotient changes between eps and eps/2
+    sits on a limiter kink and is skipped; at most a quarter of each
+    gradient's cells may be.  Bar per cell: 1 % of the difference quotient,
+    plus 1e-4 of the gradient's largest magnitude for gradients near zero
+    (the FP32 adjoint's rounding is relative to the field, not to the cell)."""
     p = synth.adjoint_problem(n=1024, nsteps=50)
     chi_t = p.meta["chi_target"]
     f64 = AdjGrid(p.b, p.chi, p.h, "f64")
@@ -163,11 +166,11 @@ def test_adjoint_1024_fp32_against_central_differences():
 
     rng = np.random.default_rng(53)
     cells = [tuple(int(v) for v in rng.integers(0, 1024, 2)) for _ in range(32)]
-    gscale_c = np.max(np.abs(gC))
-    gscale_t = np.max(np.abs(gT))
-    checked = 0
-    for which, grad, base, gscale in (("chi", gC, p.chi, gscale_c), ("T", gT, p.T0, gscale_t)):
-        for cell in cells[:16]:
+    bad = []
+    for which, grad, base in (("chi", gC, p.chi), ("T", gT, p.T0)):
+        gscale = float(np.max(np.abs(grad)))
+        skipped = 0
+        for cell in cells:
             def fd(eps):
                 up, dn = base.copy(), base.copy()
                 up[cell] += eps
@@ -177,8 +180,15 @@ def test_adjoint_1024_fp32_against_central_differences():
                 return (loss(up, p.chi) - loss(dn, p.chi)) / (2 * eps)
             e = 1e-4 * (base[cell] if which == "chi" else 1.0)
             f1, f2 = fd(e), fd(e / 2)
-            if abs(f1 - f2) > 1e-3 * max(abs(f1), 1e-3 * gscale):
+            kink = abs(f1 - f2) > 1e-3 * max(abs(f1), 1e-3 * gscale)
+            tol = 1e-2 * abs(f2) + 1e-4 * gscale
+            print(f"\n{which} {cell} grad {grad[cell]:.6e} fd {f2:.6e} fd(2eps) {f1:.6e} "
+                  f"err/tol {abs(grad[cell] - f2) / tol:.3f}{' kink' if kink else ''}")
+            if kink:
+                skipped += 1
                 continue
-            assert abs(grad[cell] - f2) <= 2e-3 * gscale + 1e-2 * abs(f2), (which, cell, grad[cell], f2)
-            checked += 1
-    assert checked >= 24
+            if abs(grad[cell] - f2) > tol:
+                bad.append((which, cell, float(grad[cell]), f2))
+        print(f"\n{which}: {32 - skipped} of 32 cells checked, {skipped} on a limiter kink")
+        assert skipped <= 8, (which, skipped)
+    assert not bad, bad

@@ -1,6 +1,7 @@
 """Batched uneven problems (asd_batch_*): every schedule against the oracle,
 problem by problem, on identical inputs."""
 import dataclasses
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -8,7 +9,7 @@ import torch
 
 import synth
 from paper_1008_0861_amd import binding as asd
-from tests.gpu_util import TOL, max_rel_err, mixed_rel_err, oracle_run, tol_steps
+from tests.gpu_util import TOL, max_rel_err, mixed_rel_err, oracle_run, stored_oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -114,21 +115,81 @@ def test_batch_tuned_schedule():
         assert max_rel_err(it["T"].double().cpu().numpy(), oracle_run(p, "f32", nsteps=5)) <= TOL["f32"]
 
 
+def _rel(got, ref):
+    return np.abs(got - ref) / np.abs(ref)
+
+
 def test_batch_256_uneven_problems_full_size():
     """The batched workload at full size: 256 problems, sides from
-    {64, 96, ..., 512}, FP32, 100 steps in one persistent launch.  Every
-    problem conserves its energy; the four smallest match the oracle."""
+    {64, 96, ..., 512}, FP32, 100 steps, in one persistent launch (mode 0)
+    and in the schedule the autotuner picks, every problem cell by cell
+    against the FP64 oracle on the FP32-rounded inputs, at 1e-5 relative.
+
+    Next to the nulls of a random field (b turns by up to 180 degrees from
+    one cell to the next) the method amplifies FP32-sized rounding: over 100
+    steps a few dozen cells there move by up to ~1e-3 from the FP64 run, in
+    whichever direction the rounding sends them.  The oracle shows it by
+    itself: runs of the oracle with the state rounded faithfully to FP32
+    after every sweep, in seeded random directions (equally valid FP32 runs,
+    exact arithmetic otherwise), spread over that range in those cells and
+    agree to ~1e-6 elsewhere.  So for a problem with cells beyond 1e-5 of the
+    FP64 oracle, such runs (seeds 1.., in groups of 8, up to 32) give each
+    cell its range of valid FP32 values, the FP64 value included; every cell
+    must lie in that range widened by 1e-5 relative, and every cell where
+    the runs agree to half the bar must be within 1e-5 of the FP64 oracle.
+    The counts are printed per problem."""
     probs = synth.batch_problems(nprob=256, master_seed=40, nsteps=100)
     st = torch.cuda.Stream()
     b, items = _gpu_batch(probs, "f32", st)
-    e0 = [float(np.sum(p.T0.astype(np.float32).astype(np.float64))) for p in probs]
+    with ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(lambda p: oracle_run(p, "f32", nsteps=100), probs))
     with torch.cuda.stream(st):
-        b.step(100, 0)
-    st.synchronize()
-    for p, it, e in zip(probs, items, e0):
-        got = it["T"].double().cpu().numpy()
-        assert abs(np.sum(got) - e) <= 1e-5 * abs(e), p.name
-    small = sorted(range(256), key=lambda i: probs[i].ncells)[:4]
-    for i in small:
-        ref = oracle_run(probs[i], "f32", nsteps=100)
-        assert max_rel_err(items[i]["T"].double().cpu().numpy(), ref) <= tol_steps("f32", 100), probs[i].shape
+        mode, nthreads = b.tune(probe_steps=2)
+    results = {}
+    for label, m in (("persistent", 0), ("tuned", -1)):
+        with torch.cuda.stream(st):
+            for p, it in zip(probs, items):
+                it["T"].copy_(torch.from_numpy(p.T0).float())
+            b.step(100, m)
+        st.synchronize()
+        results[label] = [it["T"].double().cpu().numpy() for it in items]
+    tol = TOL["f32"]
+
+    def check(i):
+        """Rows (mode, max error vs FP64, cells beyond 1e-5, FP32 runs used,
+        largest excess over the widened range, largest error where the runs
+        agree) for problem i."""
+        ref = refs[i]
+        fields = {k: results[k][i] for k in ("persistent", "tuned")}
+        errs = {k: _rel(v, ref) for k, v in fields.items()}
+        if max(e.max() for e in errs.values()) <= tol:
+            return i, [(k, float(e.max()), 0, 0, 0.0, float(e.max())) for k, e in errs.items()]
+        lo, hi = ref.copy(), ref.copy()
+        seeds = 0
+        while True:
+            for _ in range(8):
+                seeds += 1
+                run = stored_oracle_run(probs[i], "f32", nsteps=100, rounding_seed=seeds)
+                lo, hi = np.minimum(lo, run), np.maximum(hi, run)
+            excess = {k: float(np.max(np.maximum(lo - v, v - hi) / np.abs(ref))) for k, v in fields.items()}
+            if max(excess.values()) <= tol or seeds >= 32:
+                break
+        agree = (hi - lo) / np.abs(ref) <= 0.5 * tol
+        return i, [(k, float(e.max()), int((e > tol).sum()), seeds, excess[k], float(e[agree].max()))
+                   for k, e in errs.items()]
+
+    with ThreadPoolExecutor(16) as ex:
+        table = list(ex.map(check, range(len(probs))))
+    print(f"\nbatch 256 x 100 steps FP32: tuned mode {mode}, {nthreads} threads")
+    print("problem shape mode max_err_vs_fp64 cells_over_1e-5 fp32_runs excess_over_range max_err_where_runs_agree")
+    bad = []
+    n_over = 0
+    for i, rows in table:
+        for label, e64, nover, seeds, excess, e_agree in rows:
+            if nover:
+                n_over += label == "tuned"
+                print(f"{i} {probs[i].shape} {label} {e64:.3e} {nover} {seeds} {excess:.3e} {e_agree:.3e}")
+            if excess > tol or e_agree > tol:
+                bad.append((i, probs[i].shape, label, e64, excess, e_agree))
+    print(f"problems with cells beyond 1e-5 of the FP64 oracle (tuned mode): {n_over} of {len(probs)}")
+    assert not bad, bad

@@ -107,12 +107,13 @@ def test_ring_512_semi_implicit_min_temperature():
 def test_ring_512_explicit_min_temperature():
     """Section 3.1: the explicit scheme with the van Leer limiter stays within
     the initial bounds; without limiters (linear averaging, our reading of
-    the paper's unlimited explicit method) it undershoots well below zero
-    (the paper prints -0.41 for its unlimited explicit scheme)."""
+    the paper's unlimited explicit method) it undershoots to the paper's
+    printed minimum of -0.41, within 20 %."""
     m_vl, _ = _ring512_min(1.0, scheme="ex", limiter="vanleer")
     assert m_vl >= 0.1 * (1 - 1e-12), m_vl
     m_lin, _ = _ring512_min(1.0, scheme="ex", limiter="linear")
-    assert m_lin < -0.05, m_lin
+    gold = json.load(open(GOLDEN))["ring_unlimited_explicit_min"]["value"]
+    assert 1.2 * gold < m_lin < 0.8 * gold, (m_lin, gold)
 
 
 def test_matched_l1_reference_against_oracle_128():
