@@ -97,6 +97,11 @@ int asd_bench_sweep(asd_grid g, int32_t axis, double dt, int32_t reps);
  * the calibration kernel for HBM byte counters. */
 int asd_bench_copy(const void *src, void *dst, size_t nbytes, void *stream);
 
+/* Streaming copy of nbytes (multiple of 4; src and dst 16-byte aligned) with
+ * 16-byte accesses and several loads in flight per lane: the practical HBM
+ * bandwidth ceiling the kernels are measured against. */
+int asd_bench_copy_wide(const void *src, void *dst, size_t nbytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

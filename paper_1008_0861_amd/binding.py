@@ -37,7 +37,7 @@ EXPORTED = [
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
     "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune",
     "asd_get_sweep_config", "asd_set_sweep_config", "asd_tune", "asd_set_graphs",
-    "asd_bench_sweep", "asd_bench_copy",
+    "asd_bench_sweep", "asd_bench_copy", "asd_bench_copy_wide",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
             "asd_set_graphs": (ctypes.c_int, [vp, i32]),
             "asd_bench_sweep": (ctypes.c_int, [vp, i32, dbl, i32]),
             "asd_bench_copy": (ctypes.c_int, [vp, vp, sz, vp]),
+            "asd_bench_copy_wide": (ctypes.c_int, [vp, vp, sz, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -357,8 +358,10 @@ class Batch:
             pass
 
 
-def bench_copy(src, dst, stream=None):
-    """Plain device copy kernel of src.numel()*itemsize bytes (counter calibration)."""
+def bench_copy(src, dst, stream=None, wide=False):
+    """Device copy kernel of src.numel()*itemsize bytes: the plain one
+    (counter calibration) or, wide=True, the 16-byte streaming copy (the
+    practical bandwidth ceiling)."""
     sp, _ = _stream_handle(stream)
-    check(lib().asd_bench_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
-                               src.numel() * src.element_size(), sp))
+    f = lib().asd_bench_copy_wide if wide else lib().asd_bench_copy
+    check(f(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel() * src.element_size(), sp))

@@ -94,6 +94,18 @@ inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int
     return true;
 }
 
+// One captured step loop, keyed on what the capture baked in.
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int kind = 0;  // 1 = semi-implicit, 2 = explicit
+    double dt = 0.0;
+    int nsteps = 0;
+    double* energy = nullptr;
+    double* series = nullptr;
+    uint64_t last_use = 0;
+};
+static constexpr int kGraphCacheEntries = 4;
+
 struct asd_grid_s {
     asd_desc d{};
     hipStream_t st = nullptr;
@@ -116,15 +128,13 @@ struct asd_grid_s {
     unsigned* flags = nullptr;
     double* stats = nullptr;
     SweepCfg cfg[3];
-    // graph cache of the step loop
+    // graph cache of step loops: a few captured loops, least recently used
+    // replaced first; graph_valid = false marks every entry stale (fields,
+    // coefficients or launch shapes changed)
     bool use_graphs = true;
     bool graph_valid = false;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_kind = 0;  // 1 = semi-implicit, 2 = explicit
-    double graph_dt = 0.0;
-    int graph_nsteps = 0;
-    double* graph_energy = nullptr;
-    double* graph_series = nullptr;
+    GraphEntry graphs[kGraphCacheEntries];
+    uint64_t graph_clock = 0;
 };
 
 // capi.cpp

@@ -174,6 +174,9 @@ template <typename T>
 hipError_t launch_copy(const T* in, T* out, int64_t N, hipStream_t st);
 template <typename T>
 hipError_t launch_axpy(T* y, const T* x, T a, int64_t N, hipStream_t st);
+// Streaming copy of nbytes (a multiple of 4) with 16-byte accesses where
+// both pointers are 16-byte aligned.
+hipError_t launch_copy_wide(const void* in, void* out, size_t nbytes, hipStream_t st);
 
 // ------------------------------------------------- block reduction epilogue
 // Block-wide (sum, min, max); every thread must call it.  Writes the

@@ -99,6 +99,15 @@ extern "C" int asd_bench_copy(const void* src, void* dst, size_t nbytes, void* s
     return ASD_OK;
 }
 
+extern "C" int asd_bench_copy_wide(const void* src, void* dst, size_t nbytes, void* stream) {
+    if (!src || !dst) return asd_fail(ASD_EINVAL, "NULL pointer");
+    if (nbytes % 4) return asd_fail(ASD_EINVAL, "nbytes must be a multiple of 4");
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return asd_fail(ASD_EINVAL, "src and dst must be 16-byte aligned");
+    hipError_t e = launch_copy_wide(src, dst, nbytes, (hipStream_t)stream);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "copy launch: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
 // ------------------------------------------------------------- autotuner
 
 // Time reps whole steps (every sweep in order, each reading what the

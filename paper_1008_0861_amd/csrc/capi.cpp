@@ -196,7 +196,8 @@ extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes
 
 extern "C" int asd_destroy(asd_grid g) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
-    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    for (GraphEntry& e : g->graphs)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
     delete g;
     return ASD_OK;
 }

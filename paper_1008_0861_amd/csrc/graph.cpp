@@ -1,6 +1,8 @@
 // hipGraph capture of step loops.  A loop of nsteps steps is captured once
 // per (scheme, dt, nsteps, output pointers) and replayed, so a
 // long run costs one graph launch instead of 2-3 kernel launches per step.
+// The grid keeps the last few distinct loops (kGraphCacheEntries), so
+// callers that alternate step counts or outputs do not re-capture.
 // Only kernels are captured (no memset or memcpy nodes).  One graph holds
 // at most kGraphMaxSteps steps: a longer call without per-step outputs
 // replays a graph of that many steps and launches the remainder directly;
@@ -14,15 +16,25 @@ using namespace asd;
 
 static int run_graph(asd_grid g, int kind, double dt, int nsteps, const StepOut& out) {
     // callers only come here with a capturable (non-default) stream
-    const bool hit = g->graph_valid && g->graph_kind == kind && g->graph_dt == dt &&
-                     g->graph_nsteps == nsteps && g->graph_energy == out.energy &&
-                     g->graph_series == out.series && g->graph_exec;
-    if (!hit) {
-        if (g->graph_exec) {
-            (void)hipGraphExecDestroy(g->graph_exec);
-            g->graph_exec = nullptr;
+    if (!g->graph_valid) {
+        for (GraphEntry& e : g->graphs) {
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+            e = GraphEntry{};
         }
-        g->graph_valid = false;
+        g->graph_valid = true;
+    }
+    GraphEntry* hit = nullptr;
+    GraphEntry* victim = nullptr;  // an empty entry if there is one, else the least recently used
+    for (GraphEntry& e : g->graphs) {
+        if (e.exec && e.kind == kind && e.dt == dt && e.nsteps == nsteps && e.energy == out.energy &&
+            e.series == out.series)
+            hit = &e;
+        const uint64_t age = e.exec ? e.last_use : 0;
+        if (!victim || age < (victim->exec ? victim->last_use : 0)) victim = &e;
+    }
+    if (!hit) {
+        if (victim->exec) (void)hipGraphExecDestroy(victim->exec);
+        *victim = GraphEntry{};
         hipError_t e = hipStreamBeginCapture(g->st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return asd_fail(ASD_EHIP, "begin capture: %s", hipGetErrorString(e));
         const int rc = kind == 1 ? enqueue_si_loop(g, dt, nsteps, out) : enqueue_explicit_loop(g, dt, nsteps, out);
@@ -37,15 +49,16 @@ static int run_graph(asd_grid g, int kind, double dt, int nsteps, const StepOut&
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return asd_fail(ASD_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-        g->graph_exec = exec;
-        g->graph_kind = kind;
-        g->graph_dt = dt;
-        g->graph_nsteps = nsteps;
-        g->graph_energy = out.energy;
-        g->graph_series = out.series;
-        g->graph_valid = true;
+        victim->exec = exec;
+        victim->kind = kind;
+        victim->dt = dt;
+        victim->nsteps = nsteps;
+        victim->energy = out.energy;
+        victim->series = out.series;
+        hit = victim;
     }
-    hipError_t e = hipGraphLaunch(g->graph_exec, g->st);
+    hit->last_use = ++g->graph_clock;
+    hipError_t e = hipGraphLaunch(hit->exec, g->st);
     if (e != hipSuccess) return asd_fail(ASD_EHIP, "graph launch: %s", hipGetErrorString(e));
     return ASD_OK;
 }

@@ -121,6 +121,41 @@ hipError_t launch_copy(const T* in, T* out, int64_t N, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Streaming copy for the practical bandwidth ceiling: 16-byte accesses,
+// each thread keeps kWideUnroll loads in flight before its stores, and the
+// block's accesses of one round are contiguous (coalesced).  nvec 16-byte
+// vectors; the caller copies any remainder.
+static constexpr int kWideUnroll = 4;
+__global__ void __launch_bounds__(256) copy_wide_kernel(const float4* __restrict__ in, float4* __restrict__ out,
+                                                        int64_t nvec) {
+    const int64_t base = (int64_t)blockIdx.x * (256 * kWideUnroll) + threadIdx.x;
+    float4 v[kWideUnroll];
+#pragma unroll
+    for (int j = 0; j < kWideUnroll; ++j) {
+        const int64_t i = base + j * 256;
+        if (i < nvec) v[j] = in[i];
+    }
+#pragma unroll
+    for (int j = 0; j < kWideUnroll; ++j) {
+        const int64_t i = base + j * 256;
+        if (i < nvec) out[i] = v[j];
+    }
+}
+hipError_t launch_copy_wide(const void* in, void* out, size_t nbytes, hipStream_t st) {
+    const int64_t nvec = (int64_t)(nbytes / 16);
+    if (nvec > 0) {
+        const int64_t nb = (nvec + 256 * kWideUnroll - 1) / (256 * kWideUnroll);
+        if (nb > INT32_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(copy_wide_kernel, dim3((unsigned)nb), dim3(256), 0, st, (const float4*)in, (float4*)out,
+                           nvec);
+    }
+    const int64_t tail = (int64_t)(nbytes - 16 * (size_t)nvec) / 4;  // nbytes is a multiple of 4
+    if (tail > 0)
+        hipLaunchKernelGGL(copy_kernel<float>, dim3(1), dim3(256), 0, st, (const float*)in + 4 * nvec,
+                           (float*)out + 4 * nvec, tail);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) axpy_kernel(T* __restrict__ y, const T* __restrict__ x, T a, int64_t N) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
