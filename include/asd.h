@@ -98,9 +98,9 @@ typedef struct {
     int32_t limiter;  /* ASD_LIM_* */
     int64_t n[3];     /* cells along x, y, z; n[2] must be 1 when ndim == 2.
                          n >= 2 (insulating) or n >= 3 (periodic) on every axis.  Every
-                         grid line is solved in one workgroup's LDS: n <= 8192 on every
-                         axis in 2-D FP32, 6381 in 3-D FP32, 4096 in 2-D FP64 and 3181 in
-                         3-D FP64, else ASD_EUNSUPPORTED; fewer than 2^31 cells in all */
+                         grid line is solved in one workgroup's LDS: n <= 16109 on every
+                         axis in FP32 (and n = 16384) and n <= 4096 in FP64, else
+                         ASD_EUNSUPPORTED; fewer than 2^31 cells in all */
     double h[3];      /* cell widths (> 0); h[2] ignored in 2-D */
     double chi_par;   /* parallel diffusivity (> 0) when chi is not per cell */
     double chi_perp;  /* isotropic part (>= 0, <= chi) */

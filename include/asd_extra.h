@@ -71,10 +71,19 @@ int asd_step_series(asd_grid g, int32_t scheme, double dt, int32_t nsteps, doubl
 int asd_get_sweep_config(asd_grid g, int32_t axis, int32_t *wpl, int32_t *lpw, int32_t *P, int32_t *mmax);
 
 /* Request a launch shape (wpl, lpw powers of two); EUNSUPPORTED if it does
- * not fit the register or LDS budget. */
+ * not fit the register or LDS budget.  Same as asd_set_sweep_shape with
+ * io = 1. */
 int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw);
 
-/* Time every admissible (wpl, lpw) of each sweep on the grid's stream with
+/* Launch shape with io (1 or 2): the loads, face evaluation and stores of a
+ * line run on io * wpl waves, the line solve on wpl of them (a workgroup has
+ * 64 * wpl * io * lpw threads).  EUNSUPPORTED if it does not fit. */
+int asd_set_sweep_shape(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io);
+
+/* The io factor of the sweep along `axis` (see asd_set_sweep_shape). */
+int asd_get_sweep_io(asd_grid g, int32_t axis, int32_t *io);
+
+/* Time every admissible (wpl, lpw, io) of each sweep on the grid's stream with
  * HIP events (reps whole steps each, best of three timings, T -> workspace,
  * T unchanged) and keep the fastest; two passes over the axes.  Needs T and
  * b set.  Synchronises the stream. */

@@ -211,6 +211,25 @@ class OracleGrid:
                 T = round_to(self.sweep(axis, dt, T), store, rng)
         return T
 
+    def step_si_noisy(self, T, dt, nsteps=1, seed=0, ulps=1):
+        """step_si (2-step scheme, sweeps x, y (, z), no source term) with
+        every value moved by a random whole number of units in the last place
+        (uniform in -ulps .. ulps, seeded) after every sweep: an FP64 run
+        whose arithmetic rounds differently.  Its difference from step_si
+        measures how far the method itself carries FP64 rounding noise."""
+        if self.src is not None:
+            raise ValueError("step_si_noisy takes no source term")
+        rng = np.random.default_rng(seed)
+        T = self._check(T).copy()
+        for _ in range(nsteps):
+            for axis in range(self.ndim):
+                T = self.sweep(axis, dt, T)
+                k = rng.integers(-ulps, ulps + 1, T.shape)
+                for j in range(ulps):
+                    T = np.where(k > j, np.nextafter(T, np.inf), T)
+                    T = np.where(k < -j, np.nextafter(T, -np.inf), T)
+        return T
+
     def step_explicit(self, T, dt, nsteps=1, energy=False):
         """nsteps explicit limited steps; returns T (and energies if asked)."""
         T = self._check(T).copy()

@@ -36,7 +36,8 @@ EXPORTED = [
     "asd_adjoint_step", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
     "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune",
-    "asd_get_sweep_config", "asd_set_sweep_config", "asd_tune", "asd_set_graphs",
+    "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io", "asd_tune",
+    "asd_set_graphs",
     "asd_bench_sweep", "asd_bench_copy", "asd_bench_copy_wide",
 ]
 
@@ -98,6 +99,8 @@ def lib():
             "asd_batch_tune": (ctypes.c_int, [vp, i32, P(i32), P(i32)]),
             "asd_get_sweep_config": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
             "asd_set_sweep_config": (ctypes.c_int, [vp, i32, i32, i32]),
+            "asd_set_sweep_shape": (ctypes.c_int, [vp, i32, i32, i32, i32]),
+            "asd_get_sweep_io": (ctypes.c_int, [vp, i32, P(i32)]),
             "asd_tune": (ctypes.c_int, [vp, dbl, i32]),
             "asd_set_graphs": (ctypes.c_int, [vp, i32]),
             "asd_bench_sweep": (ctypes.c_int, [vp, i32, dbl, i32]),
@@ -274,13 +277,14 @@ class Grid:
         return gT, gC
 
     def sweep_config(self, axis):
-        w, l, p, m = (ctypes.c_int32() for _ in range(4))
+        w, l, p, m, io = (ctypes.c_int32() for _ in range(5))
         check(lib().asd_get_sweep_config(self.handle, int(axis), ctypes.byref(w), ctypes.byref(l),
                                          ctypes.byref(p), ctypes.byref(m)))
-        return dict(wpl=w.value, lpw=l.value, P=p.value, mmax=m.value)
+        check(lib().asd_get_sweep_io(self.handle, int(axis), ctypes.byref(io)))
+        return dict(wpl=w.value, lpw=l.value, P=p.value, mmax=m.value, io=io.value)
 
-    def set_sweep_config(self, axis, wpl, lpw):
-        check(lib().asd_set_sweep_config(self.handle, int(axis), int(wpl), int(lpw)))
+    def set_sweep_config(self, axis, wpl, lpw, io=1):
+        check(lib().asd_set_sweep_shape(self.handle, int(axis), int(wpl), int(lpw), int(io)))
 
     def tune(self, dt, reps=20):
         check(lib().asd_tune(self.handle, float(dt), int(reps)))

@@ -87,40 +87,36 @@ __device__ __forceinline__ int64_t nb_coord(int64_t c, int64_t n, bool periodic)
 }
 
 // LDS layout of one sweep tile (byte offsets; computed by the host, stored
-// in the sweep parameters).  Each line of the tile owns a row of cell
-// slots of four elements [S1, A, B1, U]: the limited transverse slope, the
-// normal and transverse coefficients of the face after the cell, and the
-// state (replaced by the solution once the line is solved).  In 3-D a
-// second row holds the pairs [S2, B2].  Slot n repeats cell 0 (the right
-// neighbour of the last cell of a periodic line; a wall face has zero
-// coefficients, so the copy is harmless there), and a few spare slots
-// follow it.  When every segment of the line has the same power-of-two
-// length, a 16-byte pad (a pair-sized pad in the second row) follows every
-// 2^pad cells, 2^pad being the distance between the segments of
-// neighbouring lanes, so that those lanes hit distinct banks; no segment
-// then contains a pad, and a segment's slots are always consecutive.
-// When several waves share a line, the interface reduction has two
-// exchange buffers with one slot per thread; the second lives in the dead
-// [S1, A, B1] part of the line's first slots when the line has at least as
-// many cells as lanes.
-__host__ __device__ inline int cell_off1(int p, int es, int pad) { return p * 4 * es + ((p >> pad) << 4); }
-__host__ __device__ inline int cell_off2(int p, int es, int pad) { return (p + (p >> pad)) * 2 * es; }
+// in the sweep parameters).  Each line of the tile owns a row of face
+// slots of two elements [A, PHI]: the normal coefficient alpha and the
+// face flux Phi of the face after the cell (computed once, while the tile
+// is staged).  The back substitution writes the solved increment over PHI
+// for the store phase.  A few spare slots follow the n slots of a line, so
+// that a lane may read a whole MMAX-cell window past the line's end (the
+// values there are ignored).  When every segment of the line has the same
+// power-of-two length, a 16-byte pad follows every 2^pad slots, 2^pad being
+// the distance between the segments of neighbouring lanes, so that those
+// lanes hit distinct banks; no segment then contains a pad, and a segment's
+// slots are always consecutive.  When several waves share a line, the
+// interface reduction exchanges through two buffers with one 4-element
+// entry per thread; on aligned tiles with segments of at least 8 cells the
+// buffers live in the segments' own face slots instead (no extra bytes).
+__host__ __device__ inline int slot_off(int p, int es, int pad) { return p * 2 * es + ((p >> pad) << 4); }
 
-static constexpr int kRowSpare = 17;  // spare slots after the copy of cell 0 (reads up to MMAX + 1 past a segment start)
+static constexpr int kRowSpare = 17;  // spare slots after the n face slots of a line
 
 struct TileLayout {
     int aligned;   // every segment has the kernel's maximal length (pads in use)
-    int pad;       // log2 of the cells per pad (30: no pad)
+    int pad;       // log2 of the slots per pad (30: no pad)
     int row1;      // bytes per line, slot rows
-    int row2;      // bytes per line, pair rows (3-D)
-    int rows2_at;  // offset of the pair rows
-    int pcr0_at;   // offset of exchange buffer 0
-    int pcr1_at;   // offset of exchange buffer 1, or -1: inside the slot rows
+    int pcr0_at;   // offset of exchange buffer 0 (several waves per line)
+    int pcr1_at;   // offset of exchange buffer 1
     int total;     // bytes
 };
 
 __host__ __device__ inline TileLayout tile_layout(int es, int ndim, int n, int lpw, int nthreads, int wpl,
                                                   int nseg_log2, int mmax) {
+    (void)ndim;
     TileLayout L;
     const int m = n >> nseg_log2;
     L.aligned = (m << nseg_log2) == n && m == mmax;  // mmax is a power of two
@@ -130,25 +126,17 @@ __host__ __device__ inline TileLayout tile_layout(int es, int ndim, int n, int l
         while ((2 << l) <= m * wpl) ++l;
         L.pad = l;  // 2^pad = m * wpl: segments of neighbouring lanes
     }
-    int r1 = cell_off1(n + 1 + kRowSpare, es, L.pad);
+    int r1 = (slot_off(n + kRowSpare, es, L.pad) + 15) & ~15;
     if (((r1 >> 4) & 1) == 0) r1 += 16;  // odd number of 16-byte units: rows start in different banks
     L.row1 = r1;
-    int r2 = 0;
-    if (ndim == 3) {
-        r2 = (cell_off2(n + 1 + kRowSpare, es, L.pad) + 15) & ~15;
-        if (((r2 >> 4) & 1) == 0) r2 += 16;
-    }
-    L.row2 = r2;
-    L.rows2_at = lpw * r1;
-    int at = L.rows2_at + lpw * r2;
+    int at = lpw * r1;
     L.pcr0_at = at;
-    L.pcr1_at = -1;
-    if (wpl > 1) {
-        at += nthreads * 4 * es;
-        if (64 * wpl > n) {
-            L.pcr1_at = at;
-            at += nthreads * 4 * es;
-        }
+    L.pcr1_at = at;
+    // several waves per line exchange through two buffers, except on aligned
+    // tiles of at least 8 cells per segment, which keep them in face slots
+    if (wpl > 1 && !(L.aligned && m >= 8)) {
+        L.pcr1_at = at + nthreads * 4 * es;
+        at += 2 * nthreads * 4 * es;
     }
     L.total = at;
     return L;

@@ -10,11 +10,13 @@
 #include "asd_device.h"
 #include "asd_launch.h"
 
-// Launch shape of one sweep: waves per line, lines per workgroup, segments
-// per line (power of two), and the compiled per-lane capacity MMAX.
+// Launch shape of one sweep: waves per line (wpl, the solve's), lines per
+// workgroup, segments per line (power of two), the compiled per-lane
+// capacity MMAX, and io (1 or 2): staging and stores run on io times the
+// solve's waves.
 struct SweepCfg {
-    int wpl = 1, lpw = 1, P = 2, mmax = 1;
-    int nthreads() const { return 64 * wpl * lpw; }
+    int wpl = 1, lpw = 1, P = 2, mmax = 1, io = 1;
+    int nthreads() const { return 64 * wpl * io * lpw; }
 };
 
 // gfx950: 160 KiB of LDS per workgroup; keep 2 KiB for static shared data.
@@ -34,23 +36,20 @@ inline int ilog2(int v) {
 
 // LDS bytes of a sweep launch (tile_layout: slot rows of the lpw lines and
 // the interface-exchange buffers).
-inline size_t sweep_lds(int es, int ndim, int n, int lpw, int nthreads, int mmax) {
-    const int wpl = nthreads / (64 * lpw);
+inline size_t sweep_lds(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax) {
     const int P = std::min(64 * wpl, pow2_floor(n));
     return (size_t)asd::tile_layout(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax).total;
 }
 
-inline int sweep_threads_cap(int es, int mmax) {
-    const int bytes = es * mmax;
-    return bytes >= 128 ? 256 : (bytes >= 32 ? 512 : 1024);
-}
+inline int sweep_threads_cap(int es, int mmax) { return asd::sweep_max_threads(es, mmax); }
 
 // Fill *out for a line of n cells.  want_wpl / want_lpw: 0 = heuristic.
 // Returns false if no configuration fits.
-inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out);
+inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out, int io = 1);
 
-inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, int want_lpw, SweepCfg* out) {
-    if (want_wpl > 0) return choose_sweep_cfg_wpl(es, ndim, n, chi, want_wpl, want_lpw, out);
+inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, int want_lpw, SweepCfg* out,
+                             int io = 1) {
+    if (want_wpl > 0) return choose_sweep_cfg_wpl(es, ndim, n, chi, want_wpl, want_lpw, out, io);
     // heuristic: the fewest waves per line that keep <= pref cells per lane;
     // otherwise the feasible shape with the fewest cells per lane
     const int pref = es == 8 ? 8 : 16;
@@ -72,25 +71,28 @@ inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, in
     return found;
 }
 
-inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out) {
+inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out, int io) {
     if (wpl < 1 || wpl > 16 || (wpl & (wpl - 1))) return false;
+    if (io != 1 && io != 2) return false;
     const int P = std::min(64 * wpl, pow2_floor(n));
     const int m = (n + P - 1) / P;
     int mmax = 1;
     while (mmax < m) mmax *= 2;
     if (mmax > 16) return false;
     const int cap = sweep_threads_cap(es, mmax);
-    if (64 * wpl > cap) return false;
+    const int tpl = 64 * wpl * io;  // threads per line
+    if (tpl > cap) return false;
     int lpw = want_lpw;
     if (lpw <= 0) lpw = std::max(1, 256 / (64 * wpl));
-    while (lpw > 1 && (64 * wpl * lpw > cap || sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw, mmax) > kLdsLimit))
+    while (lpw > 1 && (tpl * lpw > cap || sweep_lds(es, ndim, n, lpw, wpl, tpl * lpw, mmax) > kLdsLimit))
         lpw /= 2;
-    if (64 * wpl * lpw > cap) return false;
-    if (sweep_lds(es, ndim, n, lpw, 64 * wpl * lpw, mmax) > kLdsLimit) return false;
+    if (tpl * lpw > cap) return false;
+    if (sweep_lds(es, ndim, n, lpw, wpl, tpl * lpw, mmax) > kLdsLimit) return false;
     out->wpl = wpl;
     out->lpw = lpw;
     out->P = P;
     out->mmax = mmax;
+    out->io = io;
     return true;
 }
 

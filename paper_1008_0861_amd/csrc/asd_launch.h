@@ -56,6 +56,7 @@ struct SweepParams {
     int lpw;          // lines per workgroup
     int P;            // segments per line: power of two, <= 64*wpl, <= n
     int spl_log2;     // log2(64*wpl)
+    int io_log2;      // log2(io): staging and stores use 64*wpl*io threads per line (io = 1 or 2)
     int lpw_log2;     // log2(lpw)
     int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)
     TileLayout lds;   // LDS layout of a tile (tile_layout)
@@ -87,12 +88,18 @@ struct CoefParams {
 template <typename T>
 hipError_t launch_coef(const CoefParams<T>& C, hipStream_t st);
 
-// Largest workgroup a sweep instantiation is compiled for (register budget
-// of the per-lane segment arrays: seven arrays of MMAX values).
+// Largest workgroup of a sweep instantiation (register budget of the
+// per-lane segment arrays, about eleven arrays of MMAX values): FP32 keeps
+// segments of up to 16 cells within 128 registers, i.e. four waves per
+// SIMD; FP64 needs twice the registers per value.
+__host__ __device__ constexpr int sweep_max_threads(int es, int mmax) {
+    return es == 4 ? 1024 : (es * mmax >= 128 ? 256 : (es * mmax >= 64 ? 512 : 1024));
+}
+
 template <typename T, int MMAX>
 struct SweepBounds {
     static constexpr int bytes = (int)sizeof(T) * MMAX;
-    static constexpr int max_threads = bytes >= 128 ? 256 : (bytes >= 32 ? 512 : 1024);
+    static constexpr int max_threads = sweep_max_threads((int)sizeof(T), MMAX);
 };
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block,

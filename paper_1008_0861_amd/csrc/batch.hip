@@ -32,7 +32,8 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
             for (int d = 0; d < 2; ++d) {
                 const SweepParams<T> P = bp->sweep[d];
                 const int ng = bp->ngroups[d];
-                for (int g = 0; g < ng; ++g) sweep_tile<T, 2, MMAX, LIMC, EXT>(P, g * P.lpw, 0, smem_raw, lsum, lmin, lmax);
+                for (int g = 0; g < ng; ++g)
+                    sweep_tile<T, 2, MMAX, LIMC, EXT, true>(P, g * P.lpw, 0, smem_raw, lsum, lmin, lmax);
                 // sweep_tile ends with a block barrier: this sweep's stores are
                 // visible to every thread of the workgroup before the next sweep
             }

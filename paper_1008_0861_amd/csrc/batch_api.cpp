@@ -90,7 +90,7 @@ static bool batch_line_cfg(int es, int n, int nthreads, int mmax, SweepCfg* out)
         const int P = std::min(64 * wpl, pow2_floor(n));
         if ((n + P - 1) / P > mmax) continue;
         const int lpw = nthreads / (64 * wpl);
-        if (sweep_lds(es, 2, n, lpw, nthreads, mmax) > kLdsLimit) continue;
+        if (sweep_lds(es, 2, n, lpw, wpl, nthreads, mmax) > kLdsLimit) continue;
         out->wpl = wpl;
         out->lpw = lpw;
         out->P = P;
@@ -112,7 +112,7 @@ static int batch_shape(asd_batch b, int nthreads) {
             for (int d = 0; d < 2 && ok; ++d) {
                 const int n = (int)b->sub[p]->d.n[d];
                 ok = batch_line_cfg(es, n, nthreads, mmax, &cfg[2 * p + d]);
-                if (ok) lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, nthreads, mmax));
+                if (ok) lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, cfg[2 * p + d].wpl, nthreads, mmax));
             }
         }
         if (!ok) continue;

@@ -24,17 +24,30 @@ extern "C" int asd_get_sweep_config(asd_grid g, int32_t axis, int32_t* wpl, int3
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-extern "C" int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw) {
+extern "C" int asd_set_sweep_shape(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
     if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
     if (!is_pow2(wpl) || !is_pow2(lpw)) return asd_fail(ASD_EINVAL, "wpl and lpw must be powers of two");
+    if (io != 1 && io != 2) return asd_fail(ASD_EINVAL, "io must be 1 or 2");
     SweepCfg c;
     const bool chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) != 0;
-    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c) || c.wpl != wpl ||
-        c.lpw != lpw)
-        return asd_fail(ASD_EUNSUPPORTED, "launch shape wpl=%d lpw=%d does not fit", wpl, lpw);
+    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c, io) || c.wpl != wpl ||
+        c.lpw != lpw || c.io != io)
+        return asd_fail(ASD_EUNSUPPORTED, "launch shape wpl=%d lpw=%d io=%d does not fit", wpl, lpw, io);
     g->cfg[axis] = c;
     g->graph_valid = false;
+    return ASD_OK;
+}
+
+extern "C" int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw) {
+    return asd_set_sweep_shape(g, axis, wpl, lpw, 1);
+}
+
+extern "C" int asd_get_sweep_io(asd_grid g, int32_t axis, int32_t* io) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
+    if (!io) return asd_fail(ASD_EINVAL, "NULL output");
+    *io = g->cfg[axis].io;
     return ASD_OK;
 }
 
@@ -163,11 +176,12 @@ extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
         for (int axis = 0; axis < g->d.ndim; ++axis) {
             SweepCfg best = cur[axis];
             float best_ms = 1e30f;
+            for (int io = 1; io <= 2; ++io)
             for (int wpl = 1; wpl <= 16; wpl *= 2) {
-                for (int lpw = 1; wpl * lpw <= 16; lpw *= 2) {
+                for (int lpw = 1; wpl * lpw * io <= 16; lpw *= 2) {
                     SweepCfg c;
-                    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c)) continue;
-                    if (c.wpl != wpl || c.lpw != lpw) continue;
+                    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c, io)) continue;
+                    if (c.wpl != wpl || c.lpw != lpw || c.io != io) continue;
                     SweepCfg trial[3] = {cur[0], cur[1], cur[2]};
                     trial[axis] = c;
                     float ms = 1e30f;

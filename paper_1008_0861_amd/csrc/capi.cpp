@@ -392,6 +392,7 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.P = c.P;
     P.nseg_log2 = ilog2(c.P);
     P.spl_log2 = ilog2(64 * c.wpl);
+    P.io_log2 = ilog2(c.io);
     P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode & SWEEP_SOLVE_ONLY;
     P.lds = tile_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), c.wpl, P.nseg_log2, c.mmax);
@@ -422,7 +423,7 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
     if (nblocks_out) *nblocks_out = (int)nblocks;
     if (red.partials && nblocks > g->max_blocks)
         return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
-    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), c.mmax);
+    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax);
     return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st),
                      "sweep launch");
 }

@@ -12,7 +12,7 @@ namespace asd {
 // argument block.  The remaining fields are read from P as usual; the
 // leading arguments override the copies of those fields in P.
 //   packed: bits 0-3 log2(64 wpl), 4-7 log2(lpw), 8 periodic, 9 solve only,
-//           10-14 LDS pad, 15 aligned tile layout.
+//           10-14 LDS pad, 15 aligned tile layout, 16 log2(io).
 template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
 __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     sweep_kernel(const T* U, const T* alpha, const T* beta1, int n, int nt1, int si_t1, int si_t2, int nb1,
@@ -34,6 +34,7 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     P.rhs_mode = (packed >> 9) & 1;
     P.lds.pad = (packed >> 10) & 31;
     P.lds.aligned = (packed >> 15) & 1;
+    P.io_log2 = (packed >> 16) & 1;
     P.lds.row1 = row1;
     // XCD-aware block order: consecutive logical blocks on the same XCD so
     // that halo lines and the partial lines of a transposed store are shared
@@ -57,12 +58,13 @@ static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid,
                                    hipStream_t st) {
     const bool ext = P.dirichlet || P.Q;
     if (P.lpw != (1 << P.lpw_log2) || 64 * P.wpl != (1 << P.spl_log2) || P.spl_log2 > 15 || P.lpw_log2 > 15 ||
-        P.lds.pad < 0 || P.lds.pad > 31)
+        P.lds.pad < 0 || P.lds.pad > 31 || P.io_log2 < 0 || P.io_log2 > 1 ||
+        (int)block.x != (P.lpw << (P.spl_log2 + P.io_log2)))
         return hipErrorInvalidValue;
     // the kernel's leading (preloaded) arguments; P.rhs_mode holds 0 or SWEEP_SOLVE_ONLY
     const int nb1 = (P.nt1 + P.lpw - 1) / P.lpw;
     const int packed = P.spl_log2 | (P.lpw_log2 << 4) | ((P.periodic != 0) << 8) | ((P.rhs_mode != 0) << 9) |
-                       (P.lds.pad << 10) | ((P.lds.aligned != 0) << 15);
+                       (P.lds.pad << 10) | ((P.lds.aligned != 0) << 15) | ((P.io_log2 & 1) << 16);
 #define ASD_SWEEP_ARGS P.U, P.alpha, P.beta1, P.n, P.nt1, P.si_t1, P.si_t2, nb1, (int)grid.x, packed, P.lds.row1, P
 #define ASD_SWEEP_CASE(MM)                                                                          \
     case MM:                                                                                        \

@@ -3,39 +3,50 @@
 //
 //     out = (1 + dt D_nn)^-1 ( U + F_{p+1/2} - F_{p-1/2} )      along each line
 //
-// (computed as U + A^-1 (Phi_{p+1/2} - Phi_{p-1/2}), Phi_f = F_f + alpha_f (U_{p+1} - U_p),
-// the same solution in increment form) with, at the face between line
-// cells p and p+1,
+// computed in increment form, out = U + delta with
+//     A delta = Phi_{p+1/2} - Phi_{p-1/2},   Phi_f = F_f + alpha_f (U_{p+1} - U_p)
+// (the same solution; the solve's rounding then scales with |delta|, not
+// |out|), where at the face f between line cells p and p+1
 //     alpha_f = dt D_nn,f / h_n^2                  (precomputed, coef.hip)
 //     F_f     = sum_t beta_t,f L(s_t(p+1), s_t(p))  beta_t,f = dt D_nt,f/(h_n h_t)
 //     s_t(c)  = L(U[c+e_t] - U[c], U[c] - U[c-e_t])  (limited cell slope)
-// Wall faces (insulating walls) have alpha = beta = 0 in the coefficient
-// arrays, so every line is handled as a cyclic system.  T = 0 walls use odd
-// ghosts (U[-1] = -U[0]): the transverse neighbours of a wall line are
-// negated copies, and a wall face of cell c adds 2 alpha_w to its diagonal
-// and -2 alpha_w U_c to its right-hand side (no coupling across the wrap);
-// the two alpha_w of a line arrive in its wrap-face coefficient entry.  A
-// source adds dt Q to U in the right-hand side (not in the slopes).
+// and A has -alpha_{p-1/2}, 1 + alpha_{p-1/2} + alpha_{p+1/2}, -alpha_{p+1/2}
+// on row p.  Wall faces (insulating walls) have alpha = beta = 0 in the
+// coefficient arrays, so every line is handled as a cyclic system.  T = 0
+// walls use odd ghosts (U[-1] = -U[0]): the transverse neighbours of a wall
+// line are negated copies, the wrap face carries nothing, and a wall face
+// of cell c adds 2 alpha_w to its diagonal and -2 alpha_w U_c to its
+// right-hand side (the two alpha_w of a line arrive in its wrap-face
+// coefficient entry).  A source adds dt Q to the right-hand side.
 //
 // gfx950 mapping.  A workgroup owns `lpw` neighbouring lines; each line is
 // owned by `wpl` waves (a wave never spans two lines, so every per-line
-// quantity is wave-uniform and lives in scalar registers).  Phase 1 streams
-// the lines (and the neighbouring lines needed for the transverse slopes)
-// from HBM with coalesced loads, all issued before use, and packs each
-// cell's slope, coefficients and state into one LDS slot (tile_layout).
-// Phase 2 splits each line into P contiguous segments, one per lane, dealt
-// to the line's waves in turn; a lane reads its segment's slots (one vector
-// LDS read per cell), builds the rows and eliminates the segment interior
-// in registers, leaving one interface unknown per segment (its last cell).
-// The P interface unknowns form a cyclic tridiagonal system (the Schur
-// complement), solved by parallel cyclic reduction in log2(P) steps: every
-// step whose stride is at least wpl pairs two lanes of one wave (a
-// shuffle); only the log2(wpl) shorter strides go through LDS.  Each
-// equation is kept normalised (unit diagonal), so a reduction step costs
-// one reciprocal.  Phase 3 writes the tile back, transposed when the output
-// layout has the transverse axis fastest (the next sweep then reads
-// contiguous lines again).  The systems are symmetric, strictly diagonally
-// dominant M-matrices: no pivoting anywhere.
+// quantity is wave-uniform).
+//   Phase 1 streams the lines (and the neighbouring lines the transverse
+//   slopes need) from HBM with coalesced loads, all issued before use.  Each
+//   wave takes a contiguous range of 64-cell chunks, lane k cell k of each:
+//   a lane evaluates the face after its cell, taking the next cell's state
+//   and slope from lane k+1 by a DPP rotation of the wave (lane 63 from lane
+//   0 of the next chunk).  Every face is evaluated once, with no exchange
+//   between waves, and the pair (alpha_f, Phi_f) goes to the face's LDS slot.
+//   Phase 2 splits each line into P contiguous segments, one per lane, dealt
+//   to the line's waves in turn; a lane reads its segment's face slots,
+//   builds its rows and eliminates the segment interior in registers,
+//   leaving one interface unknown per segment (its last cell).  The P
+//   interface unknowns form a cyclic tridiagonal system (the Schur
+//   complement), solved by parallel cyclic reduction in log2(P) steps:
+//   every step whose stride is at least wpl pairs two lanes of one wave (a
+//   shuffle); only the log2(wpl) shorter strides go through LDS.  Each
+//   equation is kept normalised (unit diagonal), so a reduction step costs
+//   one reciprocal.  The back substitution writes each cell's increment into
+//   its face slot.
+//   Phase 3 adds the increments to U (read again from cache, issued before
+//   the solve so that the solve hides the latency) and writes the
+//   tile, transposed when the output layout has the transverse axis fastest
+//   (the next sweep then reads contiguous lines again).  The FP64 sum and
+//   the min / max of the written values are reduced here when asked for.
+// The systems are symmetric, strictly diagonally dominant M-matrices: no
+// pivoting anywhere.
 //
 // LIMC: the limiter as a compile-time constant (straight-line code), or -1
 // to read it from the parameters.  EXT: compile in T = 0 walls and the
@@ -48,46 +59,70 @@
 
 namespace asd {
 
+// Two-element slot accesses (one 8- or 16-byte LDS access).
+template <typename T>
+__device__ __forceinline__ void lds_put_pair(unsigned char* p, T a, T b);
+template <>
+__device__ __forceinline__ void lds_put_pair<float>(unsigned char* p, float a, float b) {
+    *reinterpret_cast<float2*>(p) = make_float2(a, b);
+}
+template <>
+__device__ __forceinline__ void lds_put_pair<double>(unsigned char* p, double a, double b) {
+    *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
+template <typename T>
+__device__ __forceinline__ void lds_get_pair(const unsigned char* p, T& a, T& b);
+template <>
+__device__ __forceinline__ void lds_get_pair<float>(const unsigned char* p, float& a, float& b) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    a = v.x;
+    b = v.y;
+}
+template <>
+__device__ __forceinline__ void lds_get_pair<double>(const unsigned char* p, double& a, double& b) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    a = v.x;
+    b = v.y;
+}
+
 // Per-thread view of one tile: lines l1_0 .. l1_0+lpw-1 (transverse
 // coordinate t2 = l2) of the sweep described by P, staged in the LDS buffer
-// starting at buf.  Threads [q*spl, (q+1)*spl) own line q of the tile
-// (spl = 64*wpl lanes: a power of two, so line membership is a shift,
-// uniform over a wave).
+// starting at buf.  Threads [q*sio, (q+1)*sio) own line q of the tile for
+// staging and stores (sio = 64*wpl*io lanes: a power of two, so line
+// membership is a shift, uniform over a wave); the first spl = 64*wpl of
+// them also solve it.
 template <typename T>
 struct TileCtx {
-    int l1_0, l2, q, k, l1;
+    int l1_0, l2, q, k, w, lane, l1;
     int line_ok;
+    unsigned base;  // element offset of the line in the input layout
     unsigned char* buf;
     unsigned char* row1;
-    unsigned char* row2;
-    const T *gU, *gU1m, *gU1p, *gU2m, *gU2p, *gA, *gB1, *gB2, *gQ;
+    const T *gU, *gU1m, *gU1p, *gU2m, *gU2p, *gA, *gB1, *gB2;
     int neg1m, neg1p, neg2m, neg2p;  // T = 0 walls: that transverse neighbour is the odd ghost
-    int ok1, ok2;        // LDS offsets of the thread's first cell (k) in its line's rows
-    int ostep1, ostep2;  // LDS bytes between cells spl apart
 };
 
 template <typename T, int NDIM, bool EXT>
 __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0, int l2, unsigned char* buf) {
-    constexpr int ES = (int)sizeof(T);
-    const TileLayout& Lo = P.lds;
-    const int spl = 64 * P.wpl;
-    const int pad = Lo.pad;
+    const int sio_log2 = P.spl_log2 + P.io_log2;
     const bool periodic = P.periodic != 0;
     const bool solve_only = P.rhs_mode != 0;
     TileCtx<T> c;
     c.l1_0 = l1_0;
     c.l2 = l2;
-    c.q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> P.spl_log2);
-    c.k = threadIdx.x & (spl - 1);
+    c.q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> sio_log2);
+    c.k = threadIdx.x & ((1 << sio_log2) - 1);
+    c.w = __builtin_amdgcn_readfirstlane(c.k >> 6);
+    c.lane = c.k & 63;
     c.l1 = l1_0 + c.q;
     c.line_ok = c.l1 < P.nt1;
     c.buf = buf;
-    c.row1 = buf + c.q * Lo.row1;
-    c.row2 = buf + Lo.rows2_at + c.q * Lo.row2;
+    c.row1 = buf + c.q * P.lds.row1;
     // element offsets of this line and of its transverse neighbours (the
     // boundary rule applies once per line, not per cell)
     const int l1 = c.l1;
     const unsigned base = c.line_ok ? (unsigned)(l1 * P.si_t1 + l2 * P.si_t2) : 0u;
+    c.base = base;
     unsigned base1m = base, base1p = base, base2m = base, base2p = base;
     if (c.line_ok && !solve_only) {
         base1m = base + (int)(nb_coord(l1 - 1, P.nt1, periodic) - l1) * P.si_t1;
@@ -110,221 +145,259 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0
     c.gA = P.alpha + base;
     c.gB1 = P.beta1 + base;
     c.gB2 = NDIM == 3 ? P.beta2 + base : nullptr;
-    c.gQ = EXT && P.Q ? P.Q + base : nullptr;
-    // spl is a multiple of the pad period, so cells spl apart are a fixed
-    // number of bytes apart in LDS
-    c.ok1 = cell_off1(c.k, ES, pad);
-    c.ok2 = cell_off2(c.k, ES, pad);
-    c.ostep1 = spl * 4 * ES + ((spl >> pad) << 4);
-    c.ostep2 = (spl + (spl >> pad)) * 2 * ES;
     return c;
 }
 
-// Global data of CH of the thread's cells (k + (it0 + j) spl, j < CH).
-template <typename T, int NDIM, int CH>
-struct CellLoads {
-    T u[CH], u1m[CH], u1p[CH], u2m[CH], u2p[CH], va[CH], vb1[CH], vb2[CH], q[CH];
+// Phase 1, staging.  Wave w of a line owns the chunks c0 .. c0+jn-1 of 64
+// cells (chunk c: cells 64c .. 64c+63; c0 = w * cpw, cpw = ceil(nch / wpl),
+// nch = ceil(n / 64)), and lane k takes cell 64c+k of each.  The right
+// neighbour of a lane's cell is in lane k+1 (a rotation of the wave by one
+// lane), except for lane 63, whose neighbour is lane 0 of the next chunk:
+// the next chunk of the wave, or for the wave's last chunk one extra chunk
+// loaded only for that (the first chunk of the next wave's range, or chunk 0
+// past the line's end: the periodic wrap).
+template <typename T>
+struct ChunkData {
+    T u, u1m, u1p, u2m, u2p, a, b1, b2;
 };
 
-// ---------------- phase 1a: coalesced loads of a chunk of cells.  Lane k of
-// the line takes cells k, k+spl, ... (at most MMAX of them: the host
-// guarantees n <= MMAX*spl).  All loads are issued before any is used; cells
-// past the line end are clamped to the line's last cell.
-template <typename T, int NDIM, int CH, bool EXT>
-__device__ __forceinline__ void load_cells(const SweepParams<T>& P, const TileCtx<T>& c, int it0,
-                                           CellLoads<T, NDIM, CH>& r) {
+// Loads of chunk `chunk` (face data too when `face`), all issued before use.
+// Cell n is cell 0 on a periodic line (the wrap neighbour); cells past the
+// line's end are otherwise clamped to its last cell (their values are not
+// used).
+template <typename T, int NDIM>
+__device__ __forceinline__ void load_chunk(const SweepParams<T>& P, const TileCtx<T>& c, int chunk, bool face,
+                                           ChunkData<T>& r) {
     constexpr int ES = (int)sizeof(T);
     const bool solve_only = P.rhs_mode != 0;
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-        const unsigned p = (unsigned)(c.k + ((it0 + j) << P.spl_log2));
-        const unsigned bo = min(p, (unsigned)(P.n - 1)) * (unsigned)ES;
-        r.u[j] = ldg_off(c.gU, bo);
-        r.va[j] = ldg_off(c.gA, bo);
-        // T = 0 walls need beta1 of the last cell (the left wall) in every sweep
-        if (EXT && solve_only && P.dirichlet) r.vb1[j] = ldg_off(c.gB1, bo);
-        if (EXT && P.Q) r.q[j] = ldg_off(c.gQ, bo);
+    const int n = P.n;
+    int p = (chunk << 6) + c.lane;
+    if ((chunk << 6) + 63 >= n) p = p < n ? p : (p == n && P.periodic ? 0 : n - 1);  // wave-uniform test
+    const unsigned bo = (unsigned)p * (unsigned)ES;
+    r.u = ldg_off(c.gU, bo);
+    if (!solve_only) {
+        r.u1m = ldg_off(c.gU1m, bo);
+        r.u1p = ldg_off(c.gU1p, bo);
+        if (NDIM == 3) {
+            r.u2m = ldg_off(c.gU2m, bo);
+            r.u2p = ldg_off(c.gU2p, bo);
+        }
+    }
+    if (face) {
+        r.a = ldg_off(c.gA, bo);
         if (!solve_only) {
-            r.u1m[j] = ldg_off(c.gU1m, bo);
-            r.u1p[j] = ldg_off(c.gU1p, bo);
-            r.vb1[j] = ldg_off(c.gB1, bo);
-            if (NDIM == 3) {
-                r.u2m[j] = ldg_off(c.gU2m, bo);
-                r.u2p[j] = ldg_off(c.gU2p, bo);
-                r.vb2[j] = ldg_off(c.gB2, bo);
-            }
+            r.b1 = ldg_off(c.gB1, bo);
+            if (NDIM == 3) r.b2 = ldg_off(c.gB2, bo);
         }
     }
 }
 
-// ---------------- phase 1b: limited transverse slopes, packed into the
-// cells' LDS slots (and the copy of cell 0 after the last cell).
-template <typename T, int NDIM, int CH, int LIMC, bool EXT>
-__device__ __forceinline__ void stage_cells(const SweepParams<T>& P, const TileCtx<T>& c, int it0,
-                                            const CellLoads<T, NDIM, CH>& r) {
+// Lane i takes v of lane i+1 mod 64 (a DPP rotation of the whole wave).
+template <typename T>
+__device__ __forceinline__ T rotate_down(T v) {
+    return dpp_mov<0x134, 0xf>(v, v);
+}
+
+// Stages the tile's faces: for every cell p of the line,
+//   Phi_f = alpha_f (U_{p+1} - U_p) + sum_t beta_t,f L(s_t(p+1), s_t(p))
+// and (alpha_f, Phi_f) into the face's slot.  Loads go in batches of up to
+// nine chunks; the last chunk of a batch waits for the next batch's first
+// (its lane 63 needs it).
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
+__device__ __forceinline__ void stage_tile(const SweepParams<T>& P, const TileCtx<T>& c) {
     constexpr int ES = (int)sizeof(T);
+    constexpr int CH = MMAX < 8 ? MMAX + 1 : 9;
     const bool solve_only = P.rhs_mode != 0;
     const int lim = LIMC >= 0 ? LIMC : P.limiter;
     const int n = P.n;
-    if (!c.line_ok) return;
+    const int wio_log2 = P.spl_log2 + P.io_log2 - 6;  // staging waves per line: wpl * io
+    const int nch = (n + 63) >> 6;
+    const int cpw = (nch + (1 << wio_log2) - 1) >> wio_log2;
+    const int c0 = c.w * cpw;
+    const int jn = min(cpw, nch - c0);  // this wave's chunks (wave-uniform, may be <= 0)
+    if (jn <= 0 || !c.line_ok) return;
+    const int cnext = c0 + jn < nch ? c0 + jn : 0;
+    // the chunk whose faces wait for its successor: own data and its rotation
+    T pu = T(0), ps1 = T(0), ps2 = T(0), pa = T(0), pb1 = T(0), pb2 = T(0);
+    T ru = T(0), rs1 = T(0), rs2 = T(0);
+    // (guards rather than early exits keep the unrolled batch arrays in registers)
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-        const int p = c.k + ((it0 + j) << P.spl_log2);
-        if (p >= n) continue;
-        // solve-only sweeps store zero slopes and transverse coefficients:
-        // their transverse flux is then exactly zero
-        T s1 = T(0), b1 = T(0), s2 = T(0), b2 = T(0);
-        const T u = r.u[j];
-        if (!solve_only) {
-            s1 = EXT ? cell_slope<T>(lim, c.neg1m ? -u : r.u1m[j], u, c.neg1p ? -u : r.u1p[j])
-                     : cell_slope<T>(lim, r.u1m[j], u, r.u1p[j]);
-            b1 = r.vb1[j];
-            if (NDIM == 3) {
-                s2 = EXT ? cell_slope<T>(lim, c.neg2m ? -u : r.u2m[j], u, c.neg2p ? -u : r.u2p[j])
-                         : cell_slope<T>(lim, r.u2m[j], u, r.u2p[j]);
-                b2 = r.vb2[j];
+    for (int j0 = 0; j0 <= MMAX; j0 += CH) {
+        if (j0 > jn) continue;
+        ChunkData<T> r[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int jj = j0 + j;  // chunk jj of the wave; jj == jn: the extra chunk
+            if (jj <= jn) load_chunk<T, NDIM>(P, c, jj < jn ? c0 + jj : cnext, jj < jn, r[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int jj = j0 + j;
+            if (jj > jn) continue;
+            const T u = r[j].u;
+            T s1 = T(0), s2 = T(0);
+            if (!solve_only) {
+                s1 = EXT ? cell_slope<T>(lim, c.neg1m ? -u : r[j].u1m, u, c.neg1p ? -u : r[j].u1p)
+                         : cell_slope<T>(lim, r[j].u1m, u, r[j].u1p);
+                if (NDIM == 3)
+                    s2 = EXT ? cell_slope<T>(lim, c.neg2m ? -u : r[j].u2m, u, c.neg2p ? -u : r[j].u2p)
+                             : cell_slope<T>(lim, r[j].u2m, u, r[j].u2p);
             }
-        }
-        // the right-hand side's U (the slopes above use the state itself)
-        const T us = EXT && P.Q ? u + P.dtq * r.q[j] : u;
-        T a = r.va[j];
-        if (EXT && P.dirichlet && p == n - 1) {
-            // wrap face: no coupling and no transverse flux; its two wall
-            // coefficients and this cell's U go to the spare slot after the
-            // copy of cell 0
-            lds_put4<T>(c.row1 + cell_off1(n + 1, ES, P.lds.pad), r.vb1[j], a, us, T(0));
-            a = T(0);
-            b1 = T(0);
-        }
-        lds_put4<T>(c.row1 + c.ok1 + (it0 + j) * c.ostep1, s1, a, b1, us);
-        if (NDIM == 3) lds_put2<T>(c.row2 + c.ok2 + (it0 + j) * c.ostep2, s2, b2);
-        if (p == 0) {  // the copy of cell 0 after the last cell
-            lds_put4<T>(c.row1 + cell_off1(n, ES, P.lds.pad), s1, a, b1, us);
-            if (NDIM == 3) lds_put2<T>(c.row2 + cell_off2(n, ES, P.lds.pad), s2, b2);
+            const T nru = rotate_down<T>(u);
+            T nrs1 = T(0), nrs2 = T(0);
+            if (!solve_only) {
+                nrs1 = rotate_down<T>(s1);
+                if (NDIM == 3) nrs2 = rotate_down<T>(s2);
+            }
+            if (jj > 0) {
+                // faces of chunk jj-1: the right neighbours from its own
+                // rotation, lane 63's from this chunk's lane 0
+                const bool last_lane = c.lane == 63;
+                const T un = last_lane ? nru : ru;
+                const int p = ((c0 + jj - 1) << 6) + c.lane;
+                if (p < n) {
+                    T a = pa;
+                    T phi = a * (un - pu);
+                    if (!solve_only) {
+                        phi += pb1 * limit2<T>(lim, last_lane ? nrs1 : rs1, ps1);
+                        if (NDIM == 3) phi += pb2 * limit2<T>(lim, last_lane ? nrs2 : rs2, ps2);
+                    }
+                    if (EXT && P.dirichlet && p == n - 1) {
+                        // the wrap face couples nothing; its coefficient entry holds the
+                        // line's two wall coefficients, read by the solve
+                        a = T(0);
+                        phi = T(0);
+                    }
+                    lds_put_pair<T>(c.row1 + slot_off(p, ES, P.lds.pad), a, phi);
+                }
+            }
+            pu = u;
+            ps1 = s1;
+            ps2 = s2;
+            pa = r[j].a;
+            pb1 = r[j].b1;
+            pb2 = r[j].b2;
+            ru = nru;
+            rs1 = nrs1;
+            rs2 = nrs2;
         }
     }
 }
 
-// Phases 2-3 of a staged tile: every thread of the block must call it; it
-// ends with a barrier so that the tile's LDS buffer may be refilled.
+// Phases 2-3 of a staged tile: every thread of the block must call it.
 // smem: the block's LDS base (exchange buffers).  Returns the thread's FP64
-// sum and min / max of the values it wrote.  FULL: every segment holds
-// exactly MMAX cells (an aligned tile layout), so the segment length is a
-// compile-time constant and the per-cell bounds tests vanish.
-template <typename T, int NDIM, int MMAX, int LIMC, bool EXT, bool FULL>
+// sum and min / max of the values it wrote when the launch reduces (else
+// 0, +inf, -inf).  FULL: every segment holds exactly MMAX cells (an aligned
+// tile layout), so the segment length is a compile-time constant and the
+// per-cell bounds tests vanish.  REUSE: the block stages another tile in
+// the same LDS afterwards (a closing barrier).
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT, bool FULL, bool REUSE>
 __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileCtx<T>& ctx, unsigned char* smem,
-                                            double& lsum, T& lmin, T& lmax) {
+                                            const T (&uu)[MMAX], double& lsum, T& lmin, T& lmax) {
     constexpr int ES = (int)sizeof(T);
-    constexpr int SLOT = 4 * ES;  // bytes of a cell slot / exchange slot
-    constexpr int UPOS = 3 * ES;  // byte offset of U inside a cell slot
+    constexpr int SLOT = 2 * ES;   // bytes of a face slot
+    constexpr int XSLOT = 4 * ES;  // bytes of an exchange entry
     const int n = P.n;
     const int lpw = P.lpw;
     const int spl = 64 * P.wpl;
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
-    const int lim = LIMC >= 0 ? LIMC : P.limiter;
     const TileLayout& Lo = P.lds;
     const int pad = Lo.pad;
     const int spl_log2 = P.spl_log2;
     const int q = ctx.q, k = ctx.k, l1 = ctx.l1, l1_0 = ctx.l1_0, l2 = ctx.l2;
     const bool line_ok = ctx.line_ok;
     unsigned char* row1 = ctx.row1;
-    unsigned char* row2 = ctx.row2;
-    const int ok1 = ctx.ok1, ostep1 = ctx.ostep1;
 
     // ---------------- phase 2: per-lane segment elimination
     // Segments are interleaved over the line's waves: lane l of wave w owns
     // segment kseg = l * wpl + w.
     const int wpl_log2 = spl_log2 - 6;
+    const int sio_log2 = spl_log2 + P.io_log2;
     const int nseg = 1 << P.nseg_log2;
+    const bool part = k < spl;  // this thread takes part in the solve
     const int kseg = ((k & 63) << wpl_log2) | (k >> 6);
-    const bool active = line_ok && kseg < nseg;
-    const int s0 = active ? (kseg * n) >> P.nseg_log2 : 0;
+    const bool active = part && line_ok && kseg < nseg;
+    const int s0 = active ? (FULL ? kseg * MMAX : (kseg * n) >> P.nseg_log2) : 0;
     const int m = FULL ? MMAX : (active ? (((kseg + 1) * n) >> P.nseg_log2) - s0 : 1);
-    const int os0 = cell_off1(s0, ES, pad);  // the segment's first slot
+    const int os0 = slot_off(s0, ES, pad);  // the segment's first slot
 
-    // The segment's slots: index 0 is the left neighbour cell s0-1 (mod n),
-    // index c+1 is cell s0+c, c = 0..MMAX (slots past the segment's right
-    // neighbour hold values that are ignored).  The segment's own slots are
-    // consecutive; the neighbours are found separately where a pad or the
-    // wrap may lie between (the copy of cell 0 covers the wrap on the
-    // right).  All reads are issued before any arithmetic.
-    T cs1[MMAX + 2], ca[MMAX + 2], cb1[MMAX + 2], cu[MMAX + 2], cs2[MMAX + 2], cb2[MMAX + 2];
+    // The faces of the segment: index 0 is the face before cell s0 (the last
+    // face of the previous segment, or the wrap face), index i+1 the face
+    // after cell s0+i, i = 0..MMAX-1 (faces past the segment's end are read
+    // from the row's spare slots and ignored).  The segment's own slots are
+    // consecutive.  All reads are issued before any arithmetic.
+    T fa[MMAX + 1], fp[MMAX + 1];
     {
         int jl = s0 - 1;
         if (jl < 0) jl += n;
-        const int jr = s0 + MMAX;  // right neighbour of an aligned segment (m == MMAX)
-        const int os2 = cell_off2(s0, ES, pad);
-        const int ol1 = cell_off1(jl, ES, pad), ol2 = cell_off2(jl, ES, pad);
-        const int or1 = Lo.aligned ? cell_off1(jr, ES, pad) : os0 + MMAX * SLOT;
-        const int or2 = Lo.aligned ? cell_off2(jr, ES, pad) : os2 + MMAX * 2 * ES;
-        lds_get4<T>(row1 + ol1, cs1[0], ca[0], cb1[0], cu[0]);
-        if (NDIM == 3) lds_get2<T>(row2 + ol2, cs2[0], cb2[0]);
+        lds_get_pair<T>(row1 + slot_off(jl, ES, pad), fa[0], fp[0]);
+        if constexpr (FULL && (MMAX % 2) == 0) {
 #pragma unroll
-        for (int c = 0; c < MMAX; ++c) {
-            lds_get4<T>(row1 + os0 + c * SLOT, cs1[c + 1], ca[c + 1], cb1[c + 1], cu[c + 1]);
-            if (NDIM == 3) lds_get2<T>(row2 + os2 + c * 2 * ES, cs2[c + 1], cb2[c + 1]);
+            for (int c = 0; c < MMAX; c += 2)
+                lds_get4<T>(row1 + os0 + c * SLOT, fa[c + 1], fp[c + 1], fa[c + 2], fp[c + 2]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < MMAX; ++c) lds_get_pair<T>(row1 + os0 + c * SLOT, fa[c + 1], fp[c + 1]);
         }
-        lds_get4<T>(row1 + or1, cs1[MMAX + 1], ca[MMAX + 1], cb1[MMAX + 1], cu[MMAX + 1]);
-        if (NDIM == 3) lds_get2<T>(row2 + or2, cs2[MMAX + 1], cb2[MMAX + 1]);
     }
 
     T av[MMAX], bv[MMAX], cv[MMAX], rv[MMAX];
-    T gv[MMAX], hv[MMAX], wv[MMAX];
-    T ae = T(0), be = T(1), ce = T(0), re = T(0);  // row of the segment's last cell
-    {
-        // Face f = 0..MMAX lies between slots f and f+1.  The line system
-        // A x = U + F_{+} - F_{-} is solved in increment form,
-        // x = U + delta with A delta = Phi_{+} - Phi_{-} and the face flux
-        // Phi_f = F_f + alpha_f (U_right - U_left): algebraically the same
-        // solution, but the solve's rounding now scales with |delta| rather
-        // than |x|, and the right-hand side telescopes exactly.
-        T phi_prev = T(0), alpha_prev = T(0);
 #pragma unroll
-        for (int f = 0; f <= MMAX; ++f) {
-            T phi = ca[f] * (cu[f + 1] - cu[f]) + cb1[f] * limit2<T>(lim, cs1[f + 1], cs1[f]);
-            if (NDIM == 3) phi += cb2[f] * limit2<T>(lim, cs2[f + 1], cs2[f]);
-            if (f > 0) {
-                const int i = f - 1;  // cell s0 + i, faces (f-1, f)
-                av[i] = -alpha_prev;
-                cv[i] = -ca[f];
-                bv[i] = T(1) + alpha_prev + ca[f];
-                rv[i] = phi - phi_prev;
-                const bool last = f == m;
-                ae = last ? av[i] : ae;
-                be = last ? bv[i] : be;
-                ce = last ? cv[i] : ce;
-                re = last ? rv[i] : re;
+    for (int i = 0; i < MMAX; ++i) {
+        av[i] = -fa[i];
+        cv[i] = -fa[i + 1];
+        bv[i] = T(1) + fa[i] + fa[i + 1];
+        rv[i] = fp[i + 1] - fp[i];
+    }
+    if (EXT && active) {
+        const T* lineU = P.U + ctx.base;
+        if (P.Q) {
+            // the source joins the right-hand side (input in the natural layout)
+            const T* lineQ = P.Q + ctx.base;
+#pragma unroll
+            for (int i = 0; i < MMAX; ++i)
+                if (i < m) rv[i] += P.dtq * lineQ[s0 + i];
+        }
+        if (P.dirichlet) {
+            // T = 0 walls: the wall faces of the line's first and last cells
+            // (alpha of the right wall and beta1 of the left wall sit in the
+            // wrap-face entry of the coefficient arrays)
+            if (s0 == 0) {
+                const T e = T(2) * P.beta1[ctx.base + n - 1];
+                bv[0] += e;
+                rv[0] -= e * lineU[0];
             }
-            alpha_prev = ca[f];
-            phi_prev = phi;
+            if (s0 + m == n) {
+                const T e = T(2) * P.alpha[ctx.base + n - 1];
+                const T ul = lineU[n - 1];
+#pragma unroll
+                for (int i = 0; i < MMAX; ++i) {
+                    if (i == m - 1) {
+                        bv[i] += e;
+                        rv[i] -= e * ul;
+                    }
+                }
+            }
         }
     }
-    // T = 0 walls: the wall faces of the line's first and last cells (the
-    // rows above saw zero coupling and flux across the wrap face)
-    if (EXT && P.dirichlet && active && (s0 == 0 || s0 + m == n)) {
-        T aL, aR, uR, unused;
-        lds_get4<T>(row1 + cell_off1(n + 1, ES, pad), aL, aR, uR, unused);
-        if (s0 == 0) {
-            const T e = T(2) * aL;
-            bv[0] += e;
-            rv[0] -= e * cu[1];
-            if (m == 1) {
-                be += e;
-                re -= e * cu[1];
-            }
-        }
-        if (s0 + m == n) {
-            const T e = T(2) * aR;
-            be += e;
-            re -= e * uR;
+    T ae = av[MMAX - 1], be = bv[MMAX - 1], ce = cv[MMAX - 1], re = rv[MMAX - 1];  // row of the last cell
+    if (!FULL) {
+#pragma unroll
+        for (int i = 0; i < MMAX; ++i) {
+            const bool last = i == m - 1;
+            ae = last ? av[i] : ae;
+            be = last ? bv[i] : be;
+            ce = last ? cv[i] : ce;
+            re = last ? rv[i] : re;
         }
     }
     // interior elimination: x_i = g_i - h_i x_{i+1} + w_i X_left, i = 0..m-2
+    T gv[MMAX], hv[MMAX], wv[MMAX];
     T gp = T(0), hp = T(0), wp = T(1);
 #pragma unroll
     for (int i = 0; i < MMAX - 1; ++i) {
-        if (i < m - 1) {
+        if (FULL || i < m - 1) {
             const T inv = fast_rcp<T>(bv[i] - av[i] * hp);
             gv[i] = (rv[i] - av[i] * gp) * inv;
             hv[i] = cv[i] * inv;
@@ -336,13 +409,13 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
     }
     // first cell as a function of both interface unknowns: x_0 = Y + Uc XL + V XR
     T Y = T(0), Uc = T(0), V = T(1);
-    if (m >= 2) {
+    if (FULL ? MMAX >= 2 : m >= 2) {
         Y = gp;
         Uc = wp;
         V = -hp;
 #pragma unroll
         for (int i = MMAX - 3; i >= 0; --i) {
-            if (i <= m - 3) {
+            if (FULL || i <= m - 3) {
                 Y = gv[i] - hv[i] * Y;
                 Uc = wv[i] - hv[i] * Uc;
                 V = -hv[i] * V;
@@ -387,34 +460,39 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
         // one barrier.  Segment j's entry sits at the index of the thread
         // that owns it, (j mod wpl)*64 + j/wpl: a wave's stores are
         // contiguous.
-        const int lb = q * spl;
+        // Segments of MMAX >= 8 cells on an aligned tile keep both buffers
+        // in their own face slots 4..7, which only the owner reads before
+        // the first exchange (the last face slot, which the next segment
+        // also reads, is rewritten only after that exchange's barrier).
+        constexpr bool INSLOT = FULL && MMAX >= 8;
+        const int lb = q << sio_log2;
         const int wmask = P.wpl - 1;
-        auto slot = [&](int b, int j) -> unsigned char* {
+        unsigned char* const xbuf0 = smem + Lo.pcr0_at + lb * XSLOT;
+        unsigned char* const xbuf1 = smem + Lo.pcr1_at + lb * XSLOT;
+        auto xslot = [&](int b, int j) -> unsigned char* {
+            if constexpr (INSLOT) return row1 + slot_off(j * MMAX, ES, pad) + (4 + 2 * b) * SLOT;
             const int t = ((j & wmask) << 6) + (j >> wpl_log2);
-            if (b == 0) return smem + Lo.pcr0_at + (lb + t) * SLOT;
-            return Lo.pcr1_at < 0 ? row1 + cell_off1(t, ES, pad) : smem + Lo.pcr1_at + (lb + t) * SLOT;
+            return (b == 0 ? xbuf0 : xbuf1) + t * XSLOT;
         };
         int cur = 0;
-        // Segments of at least 4 cells (MMAX >= 8, or a full tile with
-        // MMAX >= 4): one exchange gives every segment its reduced row and
-        // the stride-1 reduction step.  Segment k publishes the four numbers
-        // that define its row given the first-cell expression (Y', U', V') of
-        // segment k+1,
+        // Segments of MMAX >= 8 cells on an aligned tile: one exchange gives
+        // every segment its reduced row and the stride-1 reduction step.
+        // Segment k publishes the four numbers that define its row given the
+        // first-cell expression (Y', U', V') of segment k+1,
         //   ib = 1 / (A1 + A2 U'),  Ra = A3 ib,  Rc = A2 V' ib,  Rd = (A4 - A2 Y') ib,
-        // and its own first-cell expression, in its second and third slots
-        // (read by no other lane, and dead once the lane has read its
-        // segment; the back substitution rewrites their U words only after
-        // further barriers); a lane then forms rows k-1, k and k+1 itself.
-        // Shorter segments exchange the first-cell expressions through
-        // buffer 0 (its own area: other waves may still be reading the slot
-        // rows) and take the stride-1 step in the loop below.
-        constexpr bool MERGED = MMAX >= 8 || (FULL && MMAX >= 4);
+        // and its own first-cell expression, in its first four face slots
+        // (read by no other lane: only the segment's last face slot is also
+        // read by the next segment, and the back substitution rewrites them
+        // only after further barriers); a lane then forms rows k-1, k and
+        // k+1 itself.  Otherwise the first-cell expressions go through
+        // buffer 0 and the stride-1 step runs in the loop below.
+        constexpr bool MERGED = FULL && MMAX >= 8;
         int s_first = 1;
         if constexpr (MERGED) {
             const T A1 = be - ae * hp, A2 = ce, A3 = ae * wp, A4 = re - ae * gp;
             if (active) {
-                lds_put4<T>(row1 + cell_off1(s0 + 1, ES, pad), A1, A2, A3, A4);
-                lds_put3<T>(row1 + cell_off1(s0 + 2, ES, pad), Y, Uc, V);
+                lds_put4<T>(row1 + os0, A1, A2, A3, A4);
+                lds_put4<T>(row1 + os0 + 2 * SLOT, Y, Uc, V, T(0));
             }
             __syncthreads();
             if (active) {
@@ -424,15 +502,14 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
                     rc = a2 * vp * ib;
                     rd = (a4 - a2 * yp) * ib;
                 };
-                auto seg_start = [&](int j) { return FULL ? j * MMAX : (j * n) >> P.nseg_log2; };
-                const int sm = seg_start((kseg - 1) & (nseg - 1));
-                const int sp1 = seg_start((kseg + 1) & (nseg - 1));
-                const int sp2 = seg_start((kseg + 2) & (nseg - 1));
+                const int om = slot_off(((kseg - 1) & (nseg - 1)) * MMAX, ES, pad);
+                const int op1 = slot_off(((kseg + 1) & (nseg - 1)) * MMAX, ES, pad);
+                const int op2 = slot_off(((kseg + 2) & (nseg - 1)) * MMAX, ES, pad);
                 T m1, m2, m3, m4, q1, q2, q3, q4, y1, u1, v1, y2, u2, v2, unused;
-                lds_get4<T>(row1 + cell_off1(sm + 1, ES, pad), m1, m2, m3, m4);
-                lds_get4<T>(row1 + cell_off1(sp1 + 1, ES, pad), q1, q2, q3, q4);
-                lds_get4<T>(row1 + cell_off1(sp1 + 2, ES, pad), y1, u1, v1, unused);
-                lds_get4<T>(row1 + cell_off1(sp2 + 2, ES, pad), y2, u2, v2, unused);
+                lds_get4<T>(row1 + om, m1, m2, m3, m4);
+                lds_get4<T>(row1 + op1, q1, q2, q3, q4);
+                lds_get4<T>(row1 + op1 + 2 * SLOT, y1, u1, v1, unused);
+                lds_get4<T>(row1 + op2 + 2 * SLOT, y2, u2, v2, unused);
                 T am, cm, dm, a0, c0, d0, ap, cp, dp;
                 row(m1, m2, m3, m4, Y, Uc, V, am, cm, dm);   // row k-1 (its right neighbour is k)
                 row(A1, A2, A3, A4, y1, u1, v1, a0, c0, d0);  // row k
@@ -445,16 +522,12 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
                 Ra = T(0); Rc = T(0); Rd = T(0);
             }
             s_first = 2;
-            // the next exchange takes buffer 0: buffer 1 may lie in the slot
-            // rows, whose private slots other lanes may not have read yet
-            // (no barrier separates those reads from the next exchange's
-            // writes); buffer 1 is used only after that exchange's barrier
-            cur = 1;
+            cur = 1;  // the next exchange takes buffer 0
         } else {
-            lds_put3<T>(slot(0, kseg), Y, Uc, V);
+            if (part) lds_put4<T>(xslot(0, kseg), Y, Uc, V, T(0));
             __syncthreads();
             T Yp, Up, Vp, unused;
-            lds_get4<T>(slot(0, (kseg + 1) & (nseg - 1)), Yp, Up, Vp, unused);
+            lds_get4<T>(xslot(0, (kseg + 1) & (nseg - 1)), Yp, Up, Vp, unused);
             if (active) {
                 const T ib = fast_rcp<T>(be - ae * hp + ce * Up);
                 Ra = ae * wp * ib;
@@ -467,12 +540,12 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
         // (further) strides below wpl: partners in other waves
         for (int s = s_first; s < nseg && s < P.wpl; s <<= 1) {
             cur ^= 1;
-            lds_put3<T>(slot(cur, kseg), Ra, Rc, Rd);
+            if (part) lds_put4<T>(xslot(cur, kseg), Ra, Rc, Rd, T(0));
             __syncthreads();
             if (active) {
                 T am, cm, dm, ap, cp, dp, unused;
-                lds_get4<T>(slot(cur, (kseg - s) & (nseg - 1)), am, cm, dm, unused);
-                lds_get4<T>(slot(cur, (kseg + s) & (nseg - 1)), ap, cp, dp, unused);
+                lds_get4<T>(xslot(cur, (kseg - s) & (nseg - 1)), am, cm, dm, unused);
+                lds_get4<T>(xslot(cur, (kseg + s) & (nseg - 1)), ap, cp, dp, unused);
                 const T ib = fast_rcp<T>(T(1) - Ra * cm - Rc * ap);
                 const T na = -Ra * am, nc = -Rc * cp, nd = Rd - Ra * dm - Rc * dp;
                 Ra = na * ib;
@@ -498,87 +571,126 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
         }
         XR = Rd * fast_rcp<T>(T(1) + Ra + Rc);
         cur ^= 1;
-        *reinterpret_cast<T*>(slot(cur, kseg)) = XR;
+        if (part) *reinterpret_cast<T*>(xslot(cur, kseg)) = XR;
         __syncthreads();
-        XL = *reinterpret_cast<const T*>(slot(cur, (kseg - 1) & (nseg - 1)));
+        XL = *reinterpret_cast<const T*>(xslot(cur, (kseg - 1) & (nseg - 1)));
     }
 
-    // ---------------- back substitution: x = U + delta, written over U in
-    // the lane's own slots (the U positions are never part of an exchange)
-    lsum = 0.0;
-    lmin = T(__builtin_huge_val());
-    lmax = T(-__builtin_huge_val());
+    // ---------------- back substitution: each cell's increment goes into the
+    // second element of its face slot (no exchange reads those after this)
     if (active) {
         T dn = XR;
 #pragma unroll
         for (int i = MMAX - 1; i >= 0; --i) {
-            if (i < m) {
+            if (FULL || i < m) {
                 T d = XR;
-                if (i < MMAX - 1 && i != m - 1) d = gv[i] - hv[i] * dn + wv[i] * XL;
+                if (i < MMAX - 1 && (FULL || i != m - 1)) d = gv[i] - hv[i] * dn + wv[i] * XL;
                 dn = d;
-                const T x = cu[i + 1] + d;
-                *reinterpret_cast<T*>(row1 + os0 + i * SLOT + UPOS) = x;
-                lsum += (double)x;
-                lmin = x < lmin ? x : lmin;
-                lmax = x > lmax ? x : lmax;
+                *reinterpret_cast<T*>(row1 + os0 + i * SLOT + ES) = d;
             }
         }
     }
     __syncthreads();
 
-    // ---------------- phase 3: store the tile
+    // ---------------- phase 3: out = U + delta, stored
+    const bool reduce = P.red.partials != nullptr;
+    lsum = 0.0;
+    lmin = T(__builtin_huge_val());
+    lmax = T(-__builtin_huge_val());
     if (P.so_t1 == 1) {
         // transposed output (t1 fastest): consecutive threads take the lpw
         // lines of one position p, so each store covers lpw adjacent elements
         const int lpw_log2 = P.lpw_log2;
-        const int ncell = lpw * n;
         const int qq = tid & (lpw - 1);
         const int p0 = tid >> lpw_log2;
         const int pstep = nthreads >> lpw_log2;
+        const int lq = l1_0 + qq;
+        const bool qq_ok = lq < P.nt1;
         T* ob = P.out + (l1_0 + l2 * P.so_t2);
-        const bool qq_ok = l1_0 + qq < P.nt1;
-        // pstep == spl: consecutive positions of a thread are ostep1 apart in LDS
-        const unsigned char* rq = ctx.buf + qq * Lo.row1 + UPOS + cell_off1(p0, ES, pad);
-        const unsigned o0 = (unsigned)(p0 * P.so_n + qq);
-        const unsigned ostep = (unsigned)(pstep * P.so_n);
+        const unsigned char* rq = ctx.buf + qq * Lo.row1;
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
-            if (tid + it * nthreads >= ncell) break;
-            if (qq_ok) ob[o0 + it * ostep] = *reinterpret_cast<const T*>(rq + it * ostep1);
+            const int p = p0 + it * pstep;
+            if (p >= n) break;
+            if (qq_ok) {
+                T unused, d;
+                lds_get_pair<T>(rq + slot_off(p, ES, pad), unused, d);
+                const T x = uu[it] + d;
+                ob[(unsigned)(p * P.so_n + qq)] = x;
+                if (reduce) {
+                    lsum += (double)x;
+                    lmin = x < lmin ? x : lmin;
+                    lmax = x > lmax ? x : lmax;
+                }
+            }
         }
     } else if (line_ok) {
         // line-contiguous output
         T* ob = P.out + (l1 * P.so_t1 + l2 * P.so_t2);
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
-            const int p = k + (it << spl_log2);
+            const int p = k + (it << sio_log2);
             if (p >= n) break;
-            ob[(unsigned)(p * P.so_n)] = *reinterpret_cast<const T*>(row1 + ok1 + it * ostep1 + UPOS);
+            T unused, d;
+            lds_get_pair<T>(row1 + slot_off(p, ES, pad), unused, d);
+            const T x = uu[it] + d;
+            ob[(unsigned)(p * P.so_n)] = x;
+            if (reduce) {
+                lsum += (double)x;
+                lmin = x < lmin ? x : lmin;
+                lmax = x > lmax ? x : lmax;
+            }
         }
     }
-
-    __syncthreads();  // the LDS may be refilled by the next tile
+    if (REUSE) __syncthreads();  // the LDS may be refilled by the next tile
 }
 
-// One whole tile (phases 1-3) in LDS buffer 0, loading in chunks of up to 8
-// cells per thread.
-template <typename T, int NDIM, int MMAX, int LIMC, bool EXT = false>
+// U at the cells the thread stores in phase 3, in the store's mapping:
+// transposed output (t1 fastest): thread tid takes line tid mod lpw at
+// positions tid / lpw + it * (nthreads / lpw); line-contiguous output: the
+// thread's line at positions k + it * sio.  Cells past the line end get 0.
+template <typename T, int MMAX>
+__device__ __forceinline__ void load_store_u(const SweepParams<T>& P, const TileCtx<T>& c, T (&uu)[MMAX]) {
+    const int n = P.n;
+    if (P.so_t1 == 1) {
+        const int tid = threadIdx.x;
+        const int qq = tid & (P.lpw - 1);
+        const int p0 = tid >> P.lpw_log2;
+        const int pstep = (int)blockDim.x >> P.lpw_log2;
+        const int lq = c.l1_0 + qq;
+        const bool qq_ok = lq < P.nt1;
+        const T* uq = P.U + (qq_ok ? (unsigned)(lq * P.si_t1 + c.l2 * P.si_t2) : 0u);
+#pragma unroll
+        for (int it = 0; it < MMAX; ++it) {
+            const int p = p0 + it * pstep;
+            uu[it] = (qq_ok && p < n) ? uq[p] : T(0);
+        }
+    } else {
+        const T* lineU = P.U + c.base;
+#pragma unroll
+        for (int it = 0; it < MMAX; ++it) {
+            const int p = c.k + (it << (P.spl_log2 + P.io_log2));
+            uu[it] = (c.line_ok && p < n) ? lineU[p] : T(0);
+        }
+    }
+}
+
+// One whole tile (phases 1-3) in the LDS buffer at smem.  REUSE: the caller
+// stages further tiles in the same LDS afterwards.
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT = false, bool REUSE = false>
 __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem,
                                            double& lsum, T& lmin, T& lmax) {
     const TileCtx<T> c = tile_ctx<T, NDIM, EXT>(P, l1_0, l2, smem);
-    constexpr int CH = MMAX < 8 ? MMAX : 8;
-#pragma unroll
-    for (int it0 = 0; it0 < MMAX; it0 += CH) {
-        if ((it0 << P.spl_log2) >= P.n) break;
-        CellLoads<T, NDIM, CH> r;
-        load_cells<T, NDIM, CH, EXT>(P, c, it0, r);
-        stage_cells<T, NDIM, CH, LIMC, EXT>(P, c, it0, r);
-    }
+    stage_tile<T, NDIM, MMAX, LIMC, EXT>(P, c);
+    // U of the cells this thread stores in phase 3 (same lines, still in
+    // cache): loaded now, so that the solve hides their latency
+    T uu[MMAX];
+    load_store_u<T, MMAX>(P, c, uu);
     __syncthreads();
     if (P.lds.aligned)
-        solve_store<T, NDIM, MMAX, LIMC, EXT, true>(P, c, smem, lsum, lmin, lmax);
+        solve_store<T, NDIM, MMAX, LIMC, EXT, true, REUSE>(P, c, smem, uu, lsum, lmin, lmax);
     else
-        solve_store<T, NDIM, MMAX, LIMC, EXT, false>(P, c, smem, lsum, lmin, lmax);
+        solve_store<T, NDIM, MMAX, LIMC, EXT, false, REUSE>(P, c, smem, uu, lsum, lmin, lmax);
 }
 
 }  // namespace asd

@@ -96,8 +96,8 @@ def test_bad_descriptions(asd, mutate, code):
     assert asd.last_error()
 
 
-@pytest.mark.parametrize("ndim,dtype,nmax", [(2, "float32", 8192), (3, "float32", 6381),
-                                             (2, "float64", 4096), (3, "float64", 3181)])
+@pytest.mark.parametrize("ndim,dtype,nmax", [(2, "float32", 16109), (3, "float32", 16109),
+                                             (2, "float64", 4096), (3, "float64", 4096)])
 def test_longest_line(asd, ndim, dtype, nmax):
     """The documented maximum line length is accepted on every axis and one
     more cell is refused with EUNSUPPORTED (the line no longer fits in LDS)."""
@@ -109,6 +109,14 @@ def test_longest_line(asd, ndim, dtype, nmax):
             shape[ndim - 1 - axis] = n
             rc, _ = _rc_ws(asd, _desc(asd, shape=tuple(shape), h=(1.0,) * ndim, dtype=dt))
             assert rc == code, (axis, n, asd.last_error())
+
+
+def test_longest_aligned_fp32_line(asd):
+    """16384 cells (16 per lane of 1024 segments) fit in FP32 as well."""
+    import torch
+    for shape in ((4, 16384), (16384, 4)):
+        rc, _ = _rc_ws(asd, _desc(asd, shape=shape, h=(1.0, 1.0), dtype=torch.float32))
+        assert rc == 0, asd.last_error()
 
 
 def test_insulating_allows_two_cells(asd):

@@ -85,12 +85,12 @@ def test_si_line_lengths(n):
         assert max_rel_err(got, ref) <= TOL["f64"], (shape, max_rel_err(got, ref))
 
 
-@pytest.mark.parametrize("prec,shape", [("f32", (5, 8192)), ("f32", (8192, 5)), ("f64", (5, 4096)),
-                                        ("f64", (3, 4, 3181)), ("f64", (3181, 3, 4)), ("f32", (3, 6381, 4)),
-                                        ("f32", (3, 4, 6381))])
+@pytest.mark.parametrize("prec,shape", [("f32", (5, 16109)), ("f32", (16109, 5)), ("f32", (4, 16384)),
+                                        ("f64", (5, 4096)), ("f64", (3, 4, 4096)), ("f64", (4096, 3, 4)),
+                                        ("f32", (3, 16109, 4)), ("f32", (3, 4, 16109))])
 def test_si_longest_lines(prec, shape):
-    """The longest lines the LDS holds (8192 cells in 2-D FP32, 6381 in 3-D
-    FP32, 4096 in 2-D FP64, 3181 in 3-D FP64), on each axis in turn."""
+    """The longest lines the LDS holds (16109 cells in FP32, and 16384;
+    4096 in FP64), on each axis in turn."""
     p = _random_problem(shape, "periodic", ncfl=10.0, seed=sum(shape), nsteps=2)
     ref = oracle_run(p, prec)
     got = GpuProblem(p, prec).run()

@@ -767,3 +767,20 @@ def test_openmp_build_equals_serial(orc, shape):
     dt = ser.dt_from_ncfl(8.0)
     np.testing.assert_array_equal(par.step_si(T0, dt, 3), ser.step_si(T0, dt, 3))
     np.testing.assert_array_equal(par.step_si(T0, dt, 2, four_step=True), ser.step_si(T0, dt, 2, four_step=True))
+
+
+def test_noisy_oracle(orc):
+    """step_si_noisy: ulps = 0 is step_si bit for bit; with one unit of noise
+    per sweep a smooth problem moves by a few units in the last place only,
+    and the seed fixes the run."""
+    rng = np.random.default_rng(12)
+    shape = (16, 20)
+    b = _random_unit_field(shape, rng)
+    T0 = 1.0 + 0.3 * rng.random(shape)
+    g = orc.OracleGrid(b, (1 / 20, 1 / 16), bc="periodic", chi_par=1.0)
+    dt = g.dt_from_ncfl(5.0)
+    ref = g.step_si(T0, dt, 4)
+    np.testing.assert_array_equal(g.step_si_noisy(T0, dt, 4, seed=1, ulps=0), ref)
+    a = g.step_si_noisy(T0, dt, 4, seed=1)
+    np.testing.assert_array_equal(a, g.step_si_noisy(T0, dt, 4, seed=1))
+    assert 0 < np.max(np.abs(a - ref) / ref) < 1e-14
