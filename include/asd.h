@@ -180,6 +180,25 @@ int asd_status(asd_grid g, uint32_t *flags, double *stats);
 /* Release the handle (does not free borrowed or workspace memory). */
 int asd_destroy(asd_grid g);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): nsteps
+ * steps of asd_step_semi_implicit on the grid `desc` in one call, with no
+ * handle, no workspace argument and no allocation.  The scratch (T*, face
+ * coefficients, reduction slots, status word) is a static device array of
+ * asd_noalloc_scratch_bytes() bytes (64 MiB) that each GPU holds until the
+ * process ends; the call uses the array of the current device.  Grids whose
+ * asd_workspace_bytes exceeds it are refused with ASD_EUNSUPPORTED (2-D
+ * grids up to about 2.6 million cells in FP32, 1.3 million in FP64).
+ * dev_T is advanced in place; dev_bx, dev_by (dev_bz in 3-D, dev_chi with
+ * ASD_FLAG_PER_CELL_CHI) are read; dev_energy as for asd_step_semi_implicit.
+ * No source term; the steps are launched directly on `stream` (no graph).
+ * Every call on a GPU shares that GPU's array and rewrites all of it that it
+ * uses: calls that overlap on one GPU (two streams, two threads) race. */
+size_t asd_noalloc_scratch_bytes(void);
+int asd_step_semi_implicit_noalloc(const asd_desc *desc, void *dev_T, const void *dev_bx, const void *dev_by,
+                                   const void *dev_bz, const void *dev_chi, double dt, int32_t nsteps,
+                                   double *dev_energy, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

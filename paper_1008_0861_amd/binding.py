@@ -39,6 +39,7 @@ EXPORTED = [
     "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io", "asd_tune",
     "asd_set_graphs",
     "asd_bench_sweep", "asd_bench_copy", "asd_bench_copy_wide",
+    "asd_noalloc_scratch_bytes", "asd_step_semi_implicit_noalloc",
 ]
 
 
@@ -106,6 +107,8 @@ def lib():
             "asd_bench_sweep": (ctypes.c_int, [vp, i32, dbl, i32]),
             "asd_bench_copy": (ctypes.c_int, [vp, vp, sz, vp]),
             "asd_bench_copy_wide": (ctypes.c_int, [vp, vp, sz, vp]),
+            "asd_noalloc_scratch_bytes": (sz, []),
+            "asd_step_semi_implicit_noalloc": (ctypes.c_int, [P(Desc), vp, vp, vp, vp, vp, dbl, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -369,3 +372,24 @@ def bench_copy(src, dst, stream=None, wide=False):
     sp, _ = _stream_handle(stream)
     f = lib().asd_bench_copy_wide if wide else lib().asd_bench_copy
     check(f(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel() * src.element_size(), sp))
+
+
+def noalloc_scratch_bytes():
+    """Bytes of the static device scratch behind step_semi_implicit_noalloc."""
+    return int(lib().asd_noalloc_scratch_bytes())
+
+
+def step_semi_implicit_noalloc(T, b, h, dt, nsteps, bc="periodic", limiter="vanleer", chi_par=1.0, chi_perp=0.0,
+                               chi=None, energy=None, stream=None):
+    """nsteps semi-implicit steps of T in place through the no-allocation
+    entry point (static scratch, no handle, no workspace).  b: (bx, by[, bz])
+    device tensors of T's shape and dtype; chi: per-cell chi or None;
+    energy: None or a device FP64 tensor of nsteps + 1 entries."""
+    shape = tuple(T.shape)
+    desc = make_desc(shape, h, bc=bc, dtype=T.dtype, limiter=limiter, chi_par=chi_par, chi_perp=chi_perp,
+                     per_cell_chi=chi is not None)
+    sp, _ = _stream_handle(stream)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)  # noqa: E731
+    bz = b[2] if len(b) == 3 else None
+    check(lib().asd_step_semi_implicit_noalloc(ctypes.byref(desc), ptr(T), ptr(b[0]), ptr(b[1]), ptr(bz), ptr(chi),
+                                               float(dt), int(nsteps), ptr(energy), sp))

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libasd.so")
 SOURCES = ["sweep.hip", "coef.hip", "explicit.hip", "util.hip", "adjoint.hip", "batch.hip", "capi.cpp",
-           "graph.cpp", "adjoint_api.cpp", "batch_api.cpp", "bench_api.cpp"]
+           "graph.cpp", "adjoint_api.cpp", "batch_api.cpp", "bench_api.cpp", "noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

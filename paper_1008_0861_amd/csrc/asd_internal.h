@@ -142,6 +142,10 @@ struct asd_grid_s {
 // capi.cpp
 int asd_fail(int code, const char* fmt, ...);
 int validate_desc(const asd_desc* d);
+size_t grid_workspace_bytes(const asd_desc* desc);  // desc validated
+// Fill a grid handle over a workspace (desc validated; no device work).
+int init_grid_in_place(asd_grid_s* g, const asd_desc* desc, void* dev_ws, size_t ws_bytes, void* stream);
+int check_dt(asd_grid g, double dt, bool explicit_scheme);
 // Sweep mode bits (the rhs_mode argument of fill_sweep_params / enqueue_sweep).
 enum : int {
     SWEEP_SOLVE_ONLY = 1,   // right-hand side = U (no transverse term)

@@ -156,18 +156,14 @@ extern "C" int asd_workspace_bytes(const asd_desc* desc, size_t* bytes) {
 
 // ------------------------------------------------------------------ grid
 
-extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes, void* stream,
-                             asd_grid* out) {
-    int rc = validate_desc(desc);
-    if (rc) return rc;
-    if (!out) return asd_fail(ASD_EINVAL, "out is NULL");
+size_t grid_workspace_bytes(const asd_desc* desc) { return plan_ws(desc).total; }
+
+int init_grid_in_place(asd_grid_s* g, const asd_desc* desc, void* dev_ws, size_t ws_bytes, void* stream) {
     WsPlan p = plan_ws(desc);
     if (!dev_ws) return asd_fail(ASD_EWORKSPACE, "workspace is NULL");
     if ((uintptr_t)dev_ws & 255) return asd_fail(ASD_EWORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < p.total)
         return asd_fail(ASD_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, p.total);
-    asd_grid_s* g = new (std::nothrow) asd_grid_s();
-    if (!g) return asd_fail(ASD_EINVAL, "out of host memory");
     g->d = *desc;
     g->st = (hipStream_t)stream;
     g->ws = (char*)dev_ws;
@@ -185,10 +181,23 @@ extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes
     g->stats = (double*)(sm + 8);   // 3 doubles
     for (int q = 0; q < desc->ndim; ++q) {
         if (!choose_sweep_cfg((int)g->es, desc->ndim, (int)desc->n[q],
-                              (desc->flags & ASD_FLAG_PER_CELL_CHI) != 0, 0, 0, &g->cfg[q])) {
-            delete g;
+                              (desc->flags & ASD_FLAG_PER_CELL_CHI) != 0, 0, 0, &g->cfg[q]))
             return asd_fail(ASD_EUNSUPPORTED, "no sweep configuration for axis %d", q);
-        }
+    }
+    return ASD_OK;
+}
+
+extern "C" int asd_init_grid(const asd_desc* desc, void* dev_ws, size_t ws_bytes, void* stream,
+                             asd_grid* out) {
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+    if (!out) return asd_fail(ASD_EINVAL, "out is NULL");
+    asd_grid_s* g = new (std::nothrow) asd_grid_s();
+    if (!g) return asd_fail(ASD_EINVAL, "out of host memory");
+    rc = init_grid_in_place(g, desc, dev_ws, ws_bytes, stream);
+    if (rc) {
+        delete g;
+        return rc;
     }
     *out = g;
     return ASD_OK;
@@ -461,7 +470,7 @@ int enqueue_fold(asd_grid g, const FoldParams& f) {
     return hip_check(launch_fold(f, g->st), "fold launch");
 }
 
-static int check_dt(asd_grid g, double dt, bool explicit_scheme) {
+int check_dt(asd_grid g, double dt, bool explicit_scheme) {
     if (!finite_pos(dt)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
     // the source enters the first sweep, which must read the natural layout
     if (!explicit_scheme && g->src && (g->d.flags & ASD_FLAG_REVERSE_ORDER))

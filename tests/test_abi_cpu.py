@@ -226,3 +226,23 @@ def test_batch_boundary_conditions(asd):
     descs = (asd.Desc * 2)(_desc(asd), _desc(asd, bc="dirichlet"))
     assert asd.lib().asd_batch_workspace_bytes(descs, 2, ctypes.byref(n)) == -1
     assert "must match problem 0" in asd.last_error()
+
+
+def test_noalloc_validation_before_any_gpu_call(asd):
+    """The no-allocation entry point checks its arguments and the static
+    scratch's capacity before any HIP call (no device is needed here)."""
+    import ctypes
+    import torch
+    fake = ctypes.c_void_p(256)
+    big = _desc(asd, shape=(1800, 1800), h=(1 / 1800, 1 / 1800), dtype=torch.float32)
+    rc = asd.lib().asd_step_semi_implicit_noalloc(ctypes.byref(big), fake, fake, fake, None, None, 1e-6, 1, None,
+                                                  None)
+    assert rc == -8 and "scratch" in asd.last_error()
+    small = _desc(asd, shape=(64, 64), h=(1 / 64, 1 / 64), dtype=torch.float32)
+    rc = asd.lib().asd_step_semi_implicit_noalloc(ctypes.byref(small), fake, fake, fake, None, None, 1e-6, -1,
+                                                  None, None)
+    assert rc == -1
+    rc = asd.lib().asd_step_semi_implicit_noalloc(ctypes.byref(small), fake, None, fake, None, None, 1e-6, 1, None,
+                                                  None)
+    assert rc == -1
+    assert asd.noalloc_scratch_bytes() == 64 << 20
