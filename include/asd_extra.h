@@ -38,8 +38,32 @@ int asd_batch_set_problem(asd_batch b, int32_t p, void *dev_T, void *dev_bx, voi
  *           (work-groups own whole problems, assigned largest first);
  *   mode 1: one launch per problem per sweep (the sequential reference);
  *   mode 2: one launch per sweep for all problems (grouped line tiles);
- *   mode -1: the schedule chosen by asd_batch_tune (0 before tuning). */
+ *   mode -1: the schedule chosen by asd_batch_tune (0 before tuning).
+ * Modes 0 and 2 with nsteps >= 2 on a non-default stream are captured into
+ * one graph and replayed: the whole call is one graph launch. */
 int asd_batch_step(asd_batch b, int32_t nsteps, int32_t mode);
+
+/* asd_batch_step with per-problem FP64 outputs: dev_energy (device, FP64,
+ * nprob * (nsteps + 1) entries, problem-major) receives sum T dV of every
+ * problem's initial state and after every step, and the per-problem status
+ * (see asd_batch_status) is updated: NONFINITE, NEG_T and ENERGY_DRIFT
+ * (|E - E0| > 1e-6 |E0| against the call's initial energy; not with T = 0
+ * walls).  Mode 0 reduces inside the persistent launch (each workgroup holds
+ * all of a problem's tiles); mode 2 has every y-sweep tile write a partial
+ * and folds them per problem; mode 1 uses each problem's own step loop.
+ * dev_energy NULL: as asd_batch_step.  Modes 0 and 2 on a non-default
+ * stream run as one captured graph per call (up to 2048 steps; see
+ * asd_batch_set_graphs). */
+int asd_batch_step_energy(asd_batch b, int32_t nsteps, int32_t mode, double *dev_energy);
+
+/* Synchronise the batch's stream and copy the per-problem status bits
+ * (ASD_STATUS_*, host array of nprob) and, when stats is not NULL, the last
+ * energy-producing call's final {sum T dV, min T, max T} per problem (host
+ * array of 3 nprob).  The bits are sticky until read and cleared here. */
+int asd_batch_status(asd_batch b, uint32_t *flags, double *stats);
+
+/* Enable (1, the default) or disable (0) graph capture of batch calls. */
+int asd_batch_set_graphs(asd_batch b, int32_t on);
 
 /* Work-group size of the batch kernels: 256, 512 or 1024 threads
  * (EUNSUPPORTED if some problem's lines do not fit). */

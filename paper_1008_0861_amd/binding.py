@@ -35,7 +35,8 @@ EXPORTED = [
     "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_step_series", "asd_adjoint_workspace_bytes",
     "asd_adjoint_step", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
-    "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune",
+    "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune", "asd_batch_step_energy", "asd_batch_status",
+    "asd_batch_set_graphs",
     "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io", "asd_tune",
     "asd_set_graphs",
     "asd_bench_sweep", "asd_bench_copy", "asd_bench_copy_wide",
@@ -98,6 +99,9 @@ def lib():
             "asd_batch_destroy": (ctypes.c_int, [vp]),
             "asd_batch_set_block": (ctypes.c_int, [vp, i32]),
             "asd_batch_tune": (ctypes.c_int, [vp, i32, P(i32), P(i32)]),
+            "asd_batch_step_energy": (ctypes.c_int, [vp, i32, i32, vp]),
+            "asd_batch_status": (ctypes.c_int, [vp, P(ctypes.c_uint32), P(dbl)]),
+            "asd_batch_set_graphs": (ctypes.c_int, [vp, i32]),
             "asd_get_sweep_config": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(i32), P(i32)]),
             "asd_set_sweep_config": (ctypes.c_int, [vp, i32, i32, i32]),
             "asd_set_sweep_shape": (ctypes.c_int, [vp, i32, i32, i32, i32]),
@@ -342,8 +346,25 @@ class Batch:
                                               ctypes.c_void_p(pr["bx"].data_ptr()),
                                               ctypes.c_void_p(pr["by"].data_ptr()), float(pr["dt"])))
 
-    def step(self, nsteps, mode=-1):
-        check(lib().asd_batch_step(self.handle, int(nsteps), int(mode)))
+    def step(self, nsteps, mode=-1, energy=False):
+        """nsteps steps of every problem; energy=True returns a device FP64
+        tensor (nprob, nsteps + 1) of every problem's sum T dV."""
+        e = torch.empty((len(self.problems), nsteps + 1), dtype=torch.float64, device="cuda") if energy else None
+        check(lib().asd_batch_step_energy(self.handle, int(nsteps), int(mode),
+                                          ctypes.c_void_p(e.data_ptr()) if e is not None else None))
+        return e
+
+    def status(self):
+        """(flags per problem, stats (nprob, 3) of the last energy-producing call)."""
+        import numpy as np
+        n = len(self.problems)
+        fl = (ctypes.c_uint32 * n)()
+        st = (ctypes.c_double * (3 * n))()
+        check(lib().asd_batch_status(self.handle, fl, st))
+        return np.array(fl[:], dtype=np.uint32), np.array(st[:]).reshape(n, 3)
+
+    def set_graphs(self, on):
+        check(lib().asd_batch_set_graphs(self.handle, int(on)))
 
     def set_block(self, nthreads):
         check(lib().asd_batch_set_block(self.handle, int(nthreads)))

@@ -131,18 +131,44 @@ int explicit_num_blocks(int ndim, const int n[3]);
 
 // ------------------------------------------------------------------- batch
 // One problem of a batch: its x sweep (T -> T*, transposed) and y sweep
-// (T* -> T), and the number of line groups of each (batch.hip).
+// (T* -> T), the number of line groups (tiles) of each, where its y-sweep
+// tiles start in the batch-wide tile numbering, and its cell volume.
 template <typename T>
 struct BatchProblem {
     SweepParams<T> sweep[2];
     int ngroups[2];
+    int tile0;        // first y-sweep tile of this problem among all problems' y-sweep tiles
+    int dirichlet;    // T = 0 walls (the energy is not conserved: no drift flag)
+    double dV;
+};
+// Per-problem FP64 outputs of a batch call (all nullable together: energy
+// == nullptr switches them off).
+struct BatchOut {
+    double* energy;       // [nprob][stride]: sum T dV of the initial state and after every step
+    int stride;           // nsteps + 1 of the call
+    int first;            // entry written by the next reduction (grouped-mode folds)
+    unsigned* flags;      // [nprob]: ORed status bits (NONFINITE 1, NEG_T 2, ENERGY_DRIFT 4)
+    double* stats;        // [3 nprob]: E, min T, max T after the call's last step
+    double* partials;     // grouped schedule: per-tile (sum, min, max) of the y sweeps, a ring of slots
+    int slot_stride;      // doubles between the ring's slots
+    int count;            // grouped-mode fold: slots to fold
+    int last;             // grouped-mode fold: the fold that reaches the call's last step
 };
 template <typename T>
 hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
-                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet, hipStream_t st);
+                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet,
+                                   const BatchOut& out, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
-                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, hipStream_t st);
+                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, double* partials,
+                                hipStream_t st);
+// Energy of every problem's current state into out.energy[p * stride + 0].
+template <typename T>
+hipError_t launch_batch_reduce0(const BatchProblem<T>* probs, int nprob, const BatchOut& out, hipStream_t st);
+// Fold out.count ring slots of grouped-mode y-sweep partials into the
+// entries out.first .. out.first + count - 1 of every problem.
+template <typename T>
+hipError_t launch_batch_fold(const BatchProblem<T>* probs, int nprob, const BatchOut& out, hipStream_t st);
 hipError_t batch_set_lds_limits(int bytes);
 
 // ----------------------------------------------------------------- adjoint
@@ -245,7 +271,9 @@ __device__ __forceinline__ void fold_partials(const FoldParams& f) {
         if (f.stats_out && b == f.count - 1) { f.stats_out[0] = E; f.stats_out[1] = MN; f.stats_out[2] = MX; }
         if (f.flags) {
             unsigned fl = 0;
-            if (!(E == E) || E - E != 0.0 || !(MN == MN) || !(MX == MX) || MX - MX != 0.0) fl |= 1u;
+            // isfinite, not x - x != 0: with contraction E - E becomes
+            // fma(S, dV, -E), the product's rounding error
+            if (!__builtin_isfinite(E) || !__builtin_isfinite(MN) || !__builtin_isfinite(MX)) fl |= 1u;
             if (MN < 0.0) fl |= 2u;
             if (f.e0) {
                 const double e0 = *f.e0;

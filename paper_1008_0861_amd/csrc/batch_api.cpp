@@ -19,6 +19,7 @@ using namespace asd;
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+static const int kBatchRingSlots = 4;
 struct asd_batch_s {
     asd_desc d0{};
     int nprob = 0;
@@ -39,6 +40,20 @@ struct asd_batch_s {
     std::vector<char> h_probs;
     std::vector<int> h_off, h_list, h_gs[2];
     bool dirty = true;
+    // per-problem outputs (workspace): status bits, last (E, min, max), and
+    // the ring of grouped-mode y-sweep partials
+    unsigned* d_flags = nullptr;
+    double* d_stats = nullptr;
+    double* d_ring = nullptr;
+    int ring_slots = kBatchRingSlots;
+    int64_t ring_tiles = 0;  // tiles per ring slot (at most one per y-sweep line)
+    // captured step loops: (mode, nsteps, energy) of the current tables
+    bool use_graphs = true;
+    uint64_t version = 1;   // bumped whenever the tables or the launch shape change
+    struct Entry { hipGraphExec_t exec = nullptr; int mode = 0, nsteps = 0; double* energy = nullptr;
+                   uint64_t version = 0, last_use = 0; };
+    Entry graphs[4];
+    uint64_t clock = 0;
 };
 
 static const int kMaxWorkgroups = 1024;
@@ -50,6 +65,16 @@ static size_t probs_bytes(const asd_desc* d0, int nprob) {
 static size_t table_bytes(int nprob) {
     return align256(sizeof(int) * (size_t)(kMaxWorkgroups + 1)) + align256(sizeof(int) * (size_t)nprob) +
            2 * align256(sizeof(int) * (size_t)(nprob + 1));
+}
+// y-sweep lines of all problems (an upper bound of their y-sweep tiles)
+static int64_t ring_tiles_for(const asd_desc* descs, int nprob) {
+    int64_t t = 0;
+    for (int p = 0; p < nprob; ++p) t += descs[p].n[0];
+    return t;
+}
+static size_t outputs_bytes(const asd_desc* descs, int nprob) {
+    return align256(sizeof(unsigned) * (size_t)nprob) + align256(3 * sizeof(double) * (size_t)nprob) +
+           align256((size_t)kBatchRingSlots * ring_tiles_for(descs, nprob) * 3 * sizeof(double));
 }
 
 static int check_descs(const asd_desc* descs, int32_t nprob) {
@@ -73,7 +98,7 @@ extern "C" int asd_batch_workspace_bytes(const asd_desc* descs, int32_t nprob, s
     int rc = check_descs(descs, nprob);
     if (rc) return rc;
     if (!bytes) return asd_fail(ASD_EINVAL, "bytes is NULL");
-    size_t tot = probs_bytes(descs, nprob) + table_bytes(nprob);
+    size_t tot = probs_bytes(descs, nprob) + table_bytes(nprob) + outputs_bytes(descs, nprob);
     for (int p = 0; p < nprob; ++p) {
         size_t b = 0;
         rc = asd_workspace_bytes(&descs[p], &b);
@@ -121,6 +146,7 @@ static int batch_shape(asd_batch b, int nthreads) {
         b->cfg = cfg;
         b->lds = lds;
         b->dirty = true;
+        ++b->version;
         return ASD_OK;
     }
     return asd_fail(ASD_EUNSUPPORTED, "no batch launch shape with %d threads fits every problem", nthreads);
@@ -150,6 +176,13 @@ extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws
         b->d_gs[d] = (int*)cur;
         cur += align256(sizeof(int) * (size_t)(nprob + 1));
     }
+    b->d_flags = (unsigned*)cur;
+    cur += align256(sizeof(unsigned) * (size_t)nprob);
+    b->d_stats = (double*)cur;
+    cur += align256(3 * sizeof(double) * (size_t)nprob);
+    b->ring_tiles = ring_tiles_for(descs, nprob);
+    b->d_ring = (double*)cur;
+    cur += align256((size_t)b->ring_slots * b->ring_tiles * 3 * sizeof(double));
     b->sub.assign(nprob, nullptr);
     b->dt.assign(nprob, 0.0);
     for (int p = 0; p < nprob; ++p) {
@@ -161,6 +194,9 @@ extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws
             return rc;
         }
         b->sub[p]->use_graphs = false;
+        // the sequential schedule's folds report into the batch's per-problem status
+        b->sub[p]->flags = b->d_flags + p;
+        b->sub[p]->stats = b->d_stats + 3 * p;
         cur += align256(wb);
     }
     rc = batch_shape(b, 512);
@@ -173,8 +209,16 @@ extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws
     return ASD_OK;
 }
 
+static void drop_graphs(asd_batch b) {
+    for (auto& e : b->graphs) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        e = asd_batch_s::Entry{};
+    }
+}
+
 extern "C" int asd_batch_destroy(asd_batch b) {
     if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    drop_graphs(b);
     for (asd_grid g : b->sub)
         if (g) asd_destroy(g);
     delete b;
@@ -192,6 +236,7 @@ extern "C" int asd_batch_set_problem(asd_batch b, int32_t p, void* dev_T, void* 
     if (rc) return rc;
     b->dt[p] = dt;
     b->dirty = true;
+    ++b->version;
     return ASD_OK;
 }
 
@@ -220,6 +265,8 @@ static int batch_tables(asd_batch b) {
             const int nt1 = probs[p].sweep[d].nt1, lpw = b->cfg[2 * p + d].lpw;
             probs[p].ngroups[d] = (nt1 + lpw - 1) / lpw;
         }
+        probs[p].dirichlet = g->d.bc == ASD_BC_DIRICHLET;
+        probs[p].dV = g->d.h[0] * g->d.h[1];
         load[p] = (double)g->N;
     }
     // largest first, each to the least-loaded workgroup
@@ -246,6 +293,8 @@ static int batch_tables(asd_batch b) {
         for (int p = 0; p < np; ++p) b->h_gs[d][p + 1] = b->h_gs[d][p] + probs[p].ngroups[d];
         b->ngroups[d] = b->h_gs[d][np];
     }
+    for (int p = 0; p < np; ++p) probs[p].tile0 = b->h_gs[1][p];
+    if (b->ngroups[1] > b->ring_tiles) return asd_fail(ASD_EUNSUPPORTED, "more y-sweep tiles than ring entries");
     // synchronous uploads: the tables change only with the problem set
     hipError_t e = hipMemcpy(b->d_probs, b->h_probs.data(), b->h_probs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_off, b->h_off.data(), sizeof(int) * b->h_off.size(), hipMemcpyHostToDevice);
@@ -254,11 +303,101 @@ static int batch_tables(asd_batch b) {
         e = hipMemcpy(b->d_gs[d], b->h_gs[d].data(), sizeof(int) * (np + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch tables: %s", hipGetErrorString(e));
     b->dirty = false;
+    ++b->version;
     return ASD_OK;
 }
 
+// The kernels of one batch call (eager, or under stream capture).
 template <typename T>
-static int batch_step_t(asd_batch b, int nsteps, int mode) {
+static int enqueue_batch(asd_batch b, int nsteps, int mode, double* energy) {
+    const BatchProblem<T>* probs = (const BatchProblem<T>*)b->d_probs;
+    const bool dir = b->d0.bc == ASD_BC_DIRICHLET;
+    BatchOut out{};
+    if (energy) {
+        out.energy = energy;
+        out.stride = nsteps + 1;
+        out.flags = b->d_flags;
+        out.stats = b->d_stats;
+        out.partials = b->d_ring;
+        out.slot_stride = (int)(b->ring_tiles * 3);
+    }
+    hipError_t e = hipSuccess;
+    if (energy) e = launch_batch_reduce0<T>(probs, b->nprob, out, b->st);
+    if (mode == 0) {
+        if (e == hipSuccess)
+            e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds,
+                                           b->d0.limiter, dir, out, b->st);
+    } else {
+        int used = 0;
+        for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+            for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+                double* part = energy && d == 1 ? b->d_ring + (size_t)used * out.slot_stride : nullptr;
+                e = launch_batch_grouped<T>(probs, b->d_gs[d], b->nprob, b->ngroups[d], d, b->mmax, b->nthreads,
+                                            b->lds, b->d0.limiter, dir, part, b->st);
+            }
+            if (e == hipSuccess && energy && (++used == b->ring_slots || s == nsteps - 1)) {
+                BatchOut f = out;
+                f.first = s + 2 - used;
+                f.count = used;
+                f.last = s == nsteps - 1;
+                e = launch_batch_fold<T>(probs, b->nprob, f, b->st);
+                used = 0;
+            }
+        }
+    }
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch launch: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
+// Replay (capturing on first use) the graph of a call: one graph launch per
+// call, the four most recently used (mode, nsteps, energy) kept.
+template <typename T>
+static int run_batch_graph(asd_batch b, int nsteps, int mode, double* energy) {
+    asd_batch_s::Entry* hit = nullptr;
+    asd_batch_s::Entry* victim = nullptr;
+    for (auto& en : b->graphs) {
+        if (en.exec && en.version != b->version) {
+            (void)hipGraphExecDestroy(en.exec);
+            en = asd_batch_s::Entry{};
+        }
+        if (en.exec && en.mode == mode && en.nsteps == nsteps && en.energy == energy) hit = &en;
+        const uint64_t age = en.exec ? en.last_use : 0;
+        if (!victim || age < (victim->exec ? victim->last_use : 0)) victim = &en;
+    }
+    if (!hit) {
+        if (victim->exec) (void)hipGraphExecDestroy(victim->exec);
+        *victim = asd_batch_s::Entry{};
+        hipError_t e = hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return asd_fail(ASD_EHIP, "begin capture: %s", hipGetErrorString(e));
+        const int rc = enqueue_batch<T>(b, nsteps, mode, energy);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->st, &graph);
+        if (rc != ASD_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e2 != hipSuccess) return asd_fail(ASD_EHIP, "end capture: %s", hipGetErrorString(e2));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return asd_fail(ASD_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        victim->exec = exec;
+        victim->mode = mode;
+        victim->nsteps = nsteps;
+        victim->energy = energy;
+        victim->version = b->version;
+        hit = victim;
+    }
+    hit->last_use = ++b->clock;
+    hipError_t e = hipGraphLaunch(hit->exec, b->st);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "graph launch: %s", hipGetErrorString(e));
+    return ASD_OK;
+}
+
+static constexpr int kBatchGraphMaxSteps = 2048;
+
+template <typename T>
+static int batch_step_t(asd_batch b, int nsteps, int mode, double* energy) {
     for (int p = 0; p < b->nprob; ++p) {
         asd_grid g = b->sub[p];
         if (!(b->dt[p] > 0.0)) return asd_fail(ASD_ENOTSET, "problem %d has not been set", p);
@@ -271,35 +410,54 @@ static int batch_step_t(asd_batch b, int nsteps, int mode) {
     }
     if (mode == 1) {
         for (int p = 0; p < b->nprob; ++p) {
-            int rc = enqueue_si_loop(b->sub[p], b->dt[p], nsteps, StepOut{});
+            StepOut o;
+            o.energy = energy ? energy + (size_t)p * (nsteps + 1) : nullptr;
+            int rc = enqueue_si_loop(b->sub[p], b->dt[p], nsteps, o);
             if (rc) return rc;
         }
         return ASD_OK;
     }
     int rc = batch_tables<T>(b);
     if (rc) return rc;
-    const BatchProblem<T>* probs = (const BatchProblem<T>*)b->d_probs;
-    hipError_t e = hipSuccess;
-    if (mode == 0) {
-        e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds,
-                                       b->d0.limiter, b->d0.bc == ASD_BC_DIRICHLET, b->st);
-    } else {
-        for (int s = 0; s < nsteps && e == hipSuccess; ++s)
-            for (int d = 0; d < 2 && e == hipSuccess; ++d)
-                e = launch_batch_grouped<T>(probs, b->d_gs[d], b->nprob, b->ngroups[d], d, b->mmax, b->nthreads,
-                                            b->lds, b->d0.limiter, b->d0.bc == ASD_BC_DIRICHLET, b->st);
-    }
-    if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch launch: %s", hipGetErrorString(e));
-    return ASD_OK;
+    // a captured call holds (2 + 1/ring) nsteps launches: calls longer than
+    // the cap launch directly, as the single grids do
+    if (b->use_graphs && b->st && nsteps >= 2 && nsteps <= kBatchGraphMaxSteps)
+        return run_batch_graph<T>(b, nsteps, mode, energy);
+    return enqueue_batch<T>(b, nsteps, mode, energy);
 }
 
-extern "C" int asd_batch_step(asd_batch b, int32_t nsteps, int32_t mode) {
+extern "C" int asd_batch_step_energy(asd_batch b, int32_t nsteps, int32_t mode, double* dev_energy) {
     if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
     if (nsteps < 0) return asd_fail(ASD_EINVAL, "nsteps must be >= 0");
     if (mode < -1 || mode > 2) return asd_fail(ASD_EINVAL, "mode must be -1 (tuned), 0, 1 or 2");
     if (mode == -1) mode = b->mode;
-    if (nsteps == 0) return ASD_OK;
-    return b->d0.dtype == ASD_F64 ? batch_step_t<double>(b, nsteps, mode) : batch_step_t<float>(b, nsteps, mode);
+    if (nsteps == 0 && !dev_energy) return ASD_OK;
+    return b->d0.dtype == ASD_F64 ? batch_step_t<double>(b, nsteps, mode, dev_energy)
+                                  : batch_step_t<float>(b, nsteps, mode, dev_energy);
+}
+
+extern "C" int asd_batch_step(asd_batch b, int32_t nsteps, int32_t mode) {
+    return asd_batch_step_energy(b, nsteps, mode, nullptr);
+}
+
+extern "C" int asd_batch_set_graphs(asd_batch b, int32_t on) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    b->use_graphs = on != 0;
+    return ASD_OK;
+}
+
+extern "C" int asd_batch_status(asd_batch b, uint32_t* flags, double* stats) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (!flags) return asd_fail(ASD_EINVAL, "flags is NULL");
+    hipError_t e = hipStreamSynchronize(b->st);
+    if (e == hipSuccess) e = hipMemcpy(flags, b->d_flags, sizeof(unsigned) * (size_t)b->nprob, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && stats)
+        e = hipMemcpy(stats, b->d_stats, 3 * sizeof(double) * (size_t)b->nprob, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "batch status: %s", hipGetErrorString(e));
+    // sticky until read: clear them now they are reported
+    e = launch_fill_u32(b->d_flags, 0u, b->nprob, b->st);
+    if (e != hipSuccess) return asd_fail(ASD_EHIP, "flags reset: %s", hipGetErrorString(e));
+    return ASD_OK;
 }
 
 // Time the persistent and grouped schedules at every admissible workgroup
@@ -317,7 +475,7 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
     for (int nt : {256, 512, 1024}) {
         if (batch_shape(b, nt) != ASD_OK) continue;
         for (int mode : {0, 2}) {
-            rc = asd_batch_step(b, 1, mode);  // warm-up (tables, coefficients)
+            rc = asd_batch_step(b, probe_steps, mode);  // warm-up (tables, coefficients, graph capture)
             if (rc) break;
             if (hipEventRecord(e0, b->st) != hipSuccess) { rc = asd_fail(ASD_EHIP, "event record"); break; }
             rc = asd_batch_step(b, probe_steps, mode);

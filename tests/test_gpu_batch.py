@@ -98,6 +98,56 @@ def test_batch_fp64_1024_threads():
         assert max_rel_err(it["T"].cpu().numpy(), oracle_run(p, "f64", nsteps=4)) <= TOL["f64"]
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_energy_and_status(mode):
+    """Per-problem FP64 energy after every step (fused in the persistent
+    launch, folded per problem from the grouped launches' tile partials,
+    from each problem's own loop in mode 1) equals the oracle's energies;
+    the per-problem status holds the last step's (E, min, max) and no flags;
+    a negative field in one problem flags that problem only."""
+    probs = _small_batch(9, 23)
+    nsteps = 11  # more than the fold ring holds: several folds in mode 2
+    st = torch.cuda.Stream()
+    b, items = _gpu_batch(probs, "f64", st)
+    with torch.cuda.stream(st):
+        e = b.step(nsteps, mode, energy=True)
+    st.synchronize()
+    e = e.cpu().numpy()
+    flags, stats = b.status()
+    for i, (p, it) in enumerate(zip(probs, items)):
+        ref, eref = oracle_run(p, "f64", nsteps=nsteps, energy=True)
+        np.testing.assert_allclose(e[i], eref, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(stats[i], [eref[-1], ref.min(), ref.max()], rtol=1e-12, atol=0)
+        assert flags[i] == 0, (i, flags[i])
+    with torch.cuda.stream(st):
+        items[4]["T"].neg_()  # stays negative: diffusion keeps the extrema inside
+        b.step(2, mode, energy=True)
+    flags, _ = b.status()
+    assert flags[4] == 2 and all(flags[j] == 0 for j in range(len(probs)) if j != 4), flags
+    flags, _ = b.status()  # cleared once read
+    assert not flags.any()
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_batch_graph_replays_equal_eager(mode):
+    """Captured batch calls (one graph launch per call, replayed, alternating
+    step counts and outputs) give the same bits as eager launches."""
+    probs = _small_batch(8, 31)
+    st = torch.cuda.Stream()
+    ga, ia = _gpu_batch(probs, "f32", st)
+    gb, ib = _gpu_batch(probs, "f32", st)
+    gb.set_graphs(False)
+    for nsteps, energy in ((3, False), (5, True), (3, False), (5, True), (3, True)):
+        with torch.cuda.stream(st):
+            ea = ga.step(nsteps, mode, energy=energy)
+            eb = gb.step(nsteps, mode, energy=energy)
+        st.synchronize()
+        for x, y in zip(ia, ib):
+            assert torch.equal(x["T"], y["T"])
+        if energy:
+            assert torch.equal(ea, eb)
+
+
 def test_batch_tuned_schedule():
     probs = _small_batch(10, 3)
     st = torch.cuda.Stream()
