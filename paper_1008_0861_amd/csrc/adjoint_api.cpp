@@ -33,8 +33,8 @@ static AdjPlan adj_plan(asd_grid g, int nsteps, int k) {
     p.nck = nsteps > 0 ? (nsteps + k - 1) / k : 1;
     p.field = align256((size_t)g->N * g->es);
     // checkpoints + (k+1) recomputed states + k T* + transposed scratch +
-    // lambda + mu
-    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k + 1) + 1 + 2);
+    // lambda (both layouts) + mu
+    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k + 1) + 1 + 3);
     return p;
 }
 
@@ -57,7 +57,7 @@ extern "C" int asd_adjoint_workspace_bytes(asd_grid g, int32_t nsteps, int32_t c
 
 template <typename T>
 static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, const void* X, void* lam_out,
-                   void* gchi) {
+                   bool lam_b, void* gchi) {
     AdjParams<T> P{};
     P.mu = (const T*)mu;
     P.U = (const T*)U;
@@ -75,8 +75,11 @@ static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, 
     P.ht = g->d.h[1 - d];
     P.chi_par = g->d.chi_par;
     P.chi_perp = g->d.chi_perp;
+    P.ka = dt / (P.hn * P.hn);
+    P.kb = dt / (P.hn * P.ht);
     P.periodic = g->d.bc == ASD_BC_PERIODIC;
     P.limiter = g->d.limiter;
+    P.lam_b = lam_b ? 1 : 0;
     hipError_t e = launch_adjoint_stencil<T>(P, g->st);
     if (e != hipSuccess) return asd_fail(ASD_EHIP, "adjoint stencil: %s", hipGetErrorString(e));
     return ASD_OK;
@@ -102,7 +105,8 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
     for (int i = 1; i <= k; ++i) S[i] = take();
     for (int i = 0; i < k; ++i) TS[i] = take();
     void* tB = take();
-    void* lam = take();
+    void* lam = take();   // lambda* (after a y sweep's reverse), layout A
+    void* lamB = take();  // lambda^n (after an x sweep's reverse), layout B: the y solve's input
     void* mu = take();
     int rc;
     // forward pass: checkpoints at steps 0, k, 2k, ...
@@ -120,7 +124,7 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
         }
     }
     // reverse pass
-    rc = enqueue_copy(g, lamN, lam);
+    rc = enqueue_permute_2d(g, lamN, lamB, true);
     if (rc) return rc;
     if (gchi) {
         // a fill kernel, not a memset: callers may capture this into a graph
@@ -128,35 +132,41 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
                                   : launch_fill_u32((unsigned*)gchi, 0u, g->N, g->st);
         if (e != hipSuccess) return asd_fail(ASD_EHIP, "clear grad_chi: %s", hipGetErrorString(e));
     }
+    void* St[1025];  // this segment's states T^{ck k + i}
     for (int c = pl.nck - 1; c >= 0; --c) {
         const int len = std::min(k, nsteps - c * k);
-        S[0] = ck[c];
+        St[0] = ck[c];
+        for (int i = 1; i <= len; ++i) St[i] = S[i];
+        // the segment's last state is the next checkpoint, except in the
+        // last segment: that y sweep is not run again
+        const bool last_stored = c + 1 < pl.nck;
+        if (last_stored) St[len] = ck[c + 1];
         for (int i = 0; i < len; ++i) {
-            rc = enqueue_sweep(g, 0, dt, S[i], tB, 0, no_reduce(), nullptr, nullptr);
+            rc = enqueue_sweep(g, 0, dt, St[i], tB, 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             rc = enqueue_permute_2d(g, tB, TS[i], false);
             if (rc) return rc;
-            rc = enqueue_sweep(g, 1, dt, tB, S[i + 1], 0, no_reduce(), nullptr, nullptr);
+            if (i + 1 == len && last_stored) break;
+            rc = enqueue_sweep(g, 1, dt, tB, St[i + 1], 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
         }
         for (int i = len - 1; i >= 0; --i) {
-            // y sweep: T* -> T^{n+1}
-            rc = enqueue_permute_2d(g, lam, tB, true);
+            // y sweep: T* -> T^{n+1}; lambda arrives in the y solve's layout
+            rc = enqueue_sweep(g, 1, dt, lamB, mu, 1, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
-            rc = enqueue_sweep(g, 1, dt, tB, mu, 1, no_reduce(), nullptr, nullptr);
-            if (rc) return rc;
-            rc = stencil<T>(g, 1, dt, mu, TS[i], S[i + 1], lam, gchi);
+            rc = stencil<T>(g, 1, dt, mu, TS[i], St[i + 1], lam, false, gchi);
             if (rc) return rc;
             // x sweep: T^n -> T*; the solve writes mu in the natural layout
-            // directly (line-contiguous store, no transpose)
+            // directly (line-contiguous store, no transpose), the stencil
+            // writes lambda^n in the layout of the next y solve
             rc = enqueue_sweep(g, 0, dt, lam, mu, SWEEP_SOLVE_ONLY | SWEEP_KEEP_LAYOUT, no_reduce(), nullptr,
                                nullptr);
             if (rc) return rc;
-            rc = stencil<T>(g, 0, dt, mu, S[i], TS[i], lam, gchi);
+            rc = stencil<T>(g, 0, dt, mu, St[i], TS[i], lamB, true, gchi);
             if (rc) return rc;
         }
     }
-    return enqueue_copy(g, lam, gT0);
+    return enqueue_permute_2d(g, lamB, gT0, false);
 }
 
 extern "C" int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, const void* dev_T0,

@@ -184,7 +184,9 @@ struct AdjParams {
     T* gchi;          // nullable: += dL/dchi per cell
     int nx, ny, d;
     double dt, hn, ht, chi_par, chi_perp;
+    double ka, kb;    // dt / hn^2 and dt / (hn ht): alpha_f = ka chi_f b_n^2, beta_f = kb (chi_f - chi_perp) b_n b_t
     int periodic, limiter;
+    int lam_b;        // 1: lam_out is written y-fastest ("layout B"), else x-fastest
 };
 template <typename T>
 hipError_t launch_adjoint_stencil(const AdjParams<T>& P, hipStream_t st);
