@@ -16,6 +16,7 @@ namespace asd {
 // steps' partials, slot_stride doubles apart): block b folds reduction b.
 struct ReduceParams {
     double* partials;    // 3 doubles per block; nullptr disables the reduction
+    int of_input;        // reduce the sweep's input state (each cell once) instead of its output
 };
 struct FoldParams {
     const double* partials;  // nullptr: nothing to fold

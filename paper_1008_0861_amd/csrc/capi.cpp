@@ -504,8 +504,13 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     const bool four = (g->d.flags & ASD_FLAG_FOUR_STEP) != 0;
     const bool reverse = (g->d.flags & ASD_FLAG_REVERSE_ORDER) != 0;  // 2-D only
     int rc = ASD_OK;
-    if (outs.any()) {
-        FoldParams f0;
+    // The initial state's energy: reduced by the first sweep, which reads
+    // every cell of it once (2-step scheme in the order x, y), and folded
+    // before the first steps' fold; else by a standalone reduction.
+    const bool fuse_e0 = outs.any() && nsteps > 0 && !four && !reverse;
+    FoldParams f0{};
+    bool f0_pending = false;
+    if (outs.any() && !fuse_e0) {
         rc = enqueue_reduce(g, g->T, outs, &f0);
         if (rc == ASD_OK) rc = enqueue_fold(g, f0);
     }
@@ -528,6 +533,10 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
             const int src = i == 0 ? SWEEP_SOURCE : 0;  // dt Q joins the first sweep
             ReduceParams red = no_reduce();
             if (produce) red.partials = ring_slot(g, used);
+            if (fuse_e0 && s == 0 && i == 0) {
+                red.partials = ring_slot(g, g->ring_slots);
+                red.of_input = 1;
+            }
             int nb = 0;
             void* out;
             if (reverse) {
@@ -543,6 +552,10 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
             } else if (!four) {
                 out = (d == nd - 1) ? g->T : g->tmp[d];
                 rc = sweep(d, in, out, src, red, &nb);
+                if (red.of_input) {
+                    f0 = make_fold(g, red.partials, nb, 1, outs, 0);
+                    f0_pending = true;
+                }
             } else {
                 // 4-step: transverse term at dt with the first half-step
                 // solve, written in the input layout, then the second
@@ -553,7 +566,12 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
                 if (rc == ASD_OK) rc = sweep(d, g->tmp[1], out, SWEEP_SOLVE_ONLY, red, &nb);
             }
             if (rc == ASD_OK && produce && (++used == g->ring_slots || s == nsteps - 1)) {
-                rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, outs, s + 2 - used));
+                // entry 0 first: the later folds check the drift against it
+                if (f0_pending) {
+                    rc = enqueue_fold(g, f0);
+                    f0_pending = false;
+                }
+                if (rc == ASD_OK) rc = enqueue_fold(g, make_fold(g, ring_slot(g, 0), nb, used, outs, s + 2 - used));
                 used = 0;
             }
             in = out;

@@ -594,6 +594,7 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
 
     // ---------------- phase 3: out = U + delta, stored
     const bool reduce = P.red.partials != nullptr;
+    const bool red_in = P.red.of_input != 0;  // the input's cells instead (each stored cell once)
     lsum = 0.0;
     lmin = T(__builtin_huge_val());
     lmax = T(-__builtin_huge_val());
@@ -618,9 +619,10 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
                 const T x = uu[it] + d;
                 ob[(unsigned)(p * P.so_n + qq)] = x;
                 if (reduce) {
-                    lsum += (double)x;
-                    lmin = x < lmin ? x : lmin;
-                    lmax = x > lmax ? x : lmax;
+                    const T rv = red_in ? uu[it] : x;
+                    lsum += (double)rv;
+                    lmin = rv < lmin ? rv : lmin;
+                    lmax = rv > lmax ? rv : lmax;
                 }
             }
         }
@@ -636,9 +638,10 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
             const T x = uu[it] + d;
             ob[(unsigned)(p * P.so_n)] = x;
             if (reduce) {
-                lsum += (double)x;
-                lmin = x < lmin ? x : lmin;
-                lmax = x > lmax ? x : lmax;
+                const T rv = red_in ? uu[it] : x;
+                lsum += (double)rv;
+                lmin = rv < lmin ? rv : lmin;
+                lmax = rv > lmax ? rv : lmax;
             }
         }
     }
