@@ -563,7 +563,7 @@ def main():
     g = make_grid(p, "f32", stream, torch, asd)
     if args.tune_cache and os.path.exists(args.tune_cache):
         for a, c in enumerate(json.load(open(args.tune_cache))):
-            g.set_sweep_config(a, c["wpl"], c["lpw"], c.get("io", 1))
+            g.set_sweep_config(a, c["wpl"], c["lpw"], c.get("io", 1), c.get("variant", 0))
     elif args.tune:
         with torch.cuda.stream(stream):
             g.tune(p.dt, reps=20)

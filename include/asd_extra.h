@@ -101,13 +101,30 @@ int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw);
 
 /* Launch shape with io (1 or 2): the loads, face evaluation and stores of a
  * line run on io * wpl waves, the line solve on wpl of them (a workgroup has
- * 64 * wpl * io * lpw threads).  EUNSUPPORTED if it does not fit. */
+ * 64 * wpl * io * lpw threads).  Face-slot tile body.  EUNSUPPORTED if it
+ * does not fit. */
 int asd_set_sweep_shape(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io);
+
+/* Launch shape and tile body of the sweep along `axis`.  Both bodies compute
+ * the same sweep of section 2 (Eqs. xup / yup) and differ in their LDS use:
+ *   ASD_SWEEP_FACE_SLOTS (0): faces evaluated while a tile is staged,
+ *       8 bytes of LDS per cell in FP32 (longer lines fit; io 1 or 2);
+ *   ASD_SWEEP_CELL_SLOTS (1): cells staged as 16-byte slots, faces evaluated
+ *       in the solve (a shorter staging chain; io must be 1).
+ * EINVAL for a bad argument, EUNSUPPORTED if the shape does not fit the
+ * register or LDS budget of that body.  The autotuner (asd_tune) tries both. */
+#define ASD_SWEEP_FACE_SLOTS 0
+#define ASD_SWEEP_CELL_SLOTS 1
+int asd_set_sweep_kernel(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io, int32_t variant);
 
 /* The io factor of the sweep along `axis` (see asd_set_sweep_shape). */
 int asd_get_sweep_io(asd_grid g, int32_t axis, int32_t *io);
 
-/* Time every admissible (wpl, lpw, io) of each sweep on the grid's stream with
+/* The tile body (ASD_SWEEP_FACE_SLOTS / ASD_SWEEP_CELL_SLOTS) of the sweep
+ * along `axis`. */
+int asd_get_sweep_variant(asd_grid g, int32_t axis, int32_t *variant);
+
+/* Time every admissible (tile body, wpl, lpw, io) of each sweep on the grid's stream with
  * HIP events (reps whole steps each, best of three timings, T -> workspace,
  * T unchanged) and keep the fastest; two passes over the axes.  Needs T and
  * b set.  Synchronises the stream. */

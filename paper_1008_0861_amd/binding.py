@@ -37,7 +37,8 @@ EXPORTED = [
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
     "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune", "asd_batch_step_energy", "asd_batch_status",
     "asd_batch_set_graphs",
-    "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io", "asd_tune",
+    "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io",
+    "asd_set_sweep_kernel", "asd_get_sweep_variant", "asd_tune",
     "asd_set_graphs",
     "asd_bench_sweep", "asd_bench_copy", "asd_bench_copy_wide",
     "asd_noalloc_scratch_bytes", "asd_step_semi_implicit_noalloc",
@@ -106,6 +107,8 @@ def lib():
             "asd_set_sweep_config": (ctypes.c_int, [vp, i32, i32, i32]),
             "asd_set_sweep_shape": (ctypes.c_int, [vp, i32, i32, i32, i32]),
             "asd_get_sweep_io": (ctypes.c_int, [vp, i32, P(i32)]),
+            "asd_set_sweep_kernel": (ctypes.c_int, [vp, i32, i32, i32, i32, i32]),
+            "asd_get_sweep_variant": (ctypes.c_int, [vp, i32, P(i32)]),
             "asd_tune": (ctypes.c_int, [vp, dbl, i32]),
             "asd_set_graphs": (ctypes.c_int, [vp, i32]),
             "asd_bench_sweep": (ctypes.c_int, [vp, i32, dbl, i32]),
@@ -284,14 +287,16 @@ class Grid:
         return gT, gC
 
     def sweep_config(self, axis):
-        w, l, p, m, io = (ctypes.c_int32() for _ in range(5))
+        w, l, p, m, io, v = (ctypes.c_int32() for _ in range(6))
         check(lib().asd_get_sweep_config(self.handle, int(axis), ctypes.byref(w), ctypes.byref(l),
                                          ctypes.byref(p), ctypes.byref(m)))
         check(lib().asd_get_sweep_io(self.handle, int(axis), ctypes.byref(io)))
-        return dict(wpl=w.value, lpw=l.value, P=p.value, mmax=m.value, io=io.value)
+        check(lib().asd_get_sweep_variant(self.handle, int(axis), ctypes.byref(v)))
+        return dict(wpl=w.value, lpw=l.value, P=p.value, mmax=m.value, io=io.value, variant=v.value)
 
-    def set_sweep_config(self, axis, wpl, lpw, io=1):
-        check(lib().asd_set_sweep_shape(self.handle, int(axis), int(wpl), int(lpw), int(io)))
+    def set_sweep_config(self, axis, wpl, lpw, io=1, variant=0):
+        """variant 0: face-slot tile body, 1: cell-slot tile body."""
+        check(lib().asd_set_sweep_kernel(self.handle, int(axis), int(wpl), int(lpw), int(io), int(variant)))
 
     def tune(self, dt, reps=20):
         check(lib().asd_tune(self.handle, float(dt), int(reps)))

@@ -110,14 +110,18 @@ struct TileLayout {
     int pad;       // log2 of the slots per pad (30: no pad)
     int row1;      // bytes per line, slot rows
     int pcr0_at;   // offset of exchange buffer 0 (several waves per line)
-    int pcr1_at;   // offset of exchange buffer 1
+    int pcr1_at;   // offset of exchange buffer 1 (cell-slot layout: -1 = inside the slot rows)
     int total;     // bytes
+    int row2;      // cell-slot layout, 3-D: bytes per line of the pair rows
+    int rows2_at;  // cell-slot layout, 3-D: offset of the pair rows
 };
 
 __host__ __device__ inline TileLayout tile_layout(int es, int ndim, int n, int lpw, int nthreads, int wpl,
                                                   int nseg_log2, int mmax) {
     (void)ndim;
     TileLayout L;
+    L.row2 = 0;
+    L.rows2_at = 0;
     const int m = n >> nseg_log2;
     L.aligned = (m << nseg_log2) == n && m == mmax;  // mmax is a power of two
     L.pad = 30;
@@ -137,6 +141,54 @@ __host__ __device__ inline TileLayout tile_layout(int es, int ndim, int n, int l
     if (wpl > 1 && !(L.aligned && m >= 8)) {
         L.pcr1_at = at + nthreads * 4 * es;
         at += 2 * nthreads * 4 * es;
+    }
+    L.total = at;
+    return L;
+}
+
+// The cell-slot layout of the second sweep variant (sweep_cell.h): each
+// line owns a row of cell slots of four elements [S1, A, B1, U] (the
+// limited transverse slope, the normal and transverse coefficients of the
+// face after the cell, and the state, replaced by the solution once the
+// line is solved); in 3-D a second row holds the pairs [S2, B2].  Slot n
+// repeats cell 0 and a few spare slots follow.  Pads as in tile_layout.
+// With several waves per line the interface reduction has two exchange
+// buffers of one slot per thread; the second lives in the dead [S1, A, B1]
+// part of the line's first slots when the line has at least as many cells
+// as lanes (pcr1_at = -1).
+__host__ __device__ inline int cell_off1(int p, int es, int pad) { return p * 4 * es + ((p >> pad) << 4); }
+__host__ __device__ inline int cell_off2(int p, int es, int pad) { return (p + (p >> pad)) * 2 * es; }
+
+__host__ __device__ inline TileLayout tile_layout_cell(int es, int ndim, int n, int lpw, int nthreads, int wpl,
+                                                       int nseg_log2, int mmax) {
+    TileLayout L;
+    const int m = n >> nseg_log2;
+    L.aligned = (m << nseg_log2) == n && m == mmax;
+    L.pad = 30;
+    if (L.aligned && m * wpl >= 2) {
+        int l = 0;
+        while ((2 << l) <= m * wpl) ++l;
+        L.pad = l;
+    }
+    int r1 = cell_off1(n + 1 + kRowSpare, es, L.pad);
+    if (((r1 >> 4) & 1) == 0) r1 += 16;
+    L.row1 = r1;
+    int r2 = 0;
+    if (ndim == 3) {
+        r2 = (cell_off2(n + 1 + kRowSpare, es, L.pad) + 15) & ~15;
+        if (((r2 >> 4) & 1) == 0) r2 += 16;
+    }
+    L.row2 = r2;
+    L.rows2_at = lpw * r1;
+    int at = L.rows2_at + lpw * r2;
+    L.pcr0_at = at;
+    L.pcr1_at = -1;
+    if (wpl > 1) {
+        at += nthreads * 4 * es;
+        if (64 * wpl > n) {
+            L.pcr1_at = at;
+            at += nthreads * 4 * es;
+        }
     }
     L.total = at;
     return L;

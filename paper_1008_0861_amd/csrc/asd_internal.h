@@ -12,10 +12,11 @@
 
 // Launch shape of one sweep: waves per line (wpl, the solve's), lines per
 // workgroup, segments per line (power of two), the compiled per-lane
-// capacity MMAX, and io (1 or 2): staging and stores run on io times the
-// solve's waves.
+// capacity MMAX, io (1 or 2): staging and stores run on io times the
+// solve's waves, and the tile body (face slots, or cell slots with io = 1).
 struct SweepCfg {
     int wpl = 1, lpw = 1, P = 2, mmax = 1, io = 1;
+    int variant = asd::SWEEP_FACE_SLOTS;
     int nthreads() const { return 64 * wpl * io * lpw; }
 };
 
@@ -34,22 +35,30 @@ inline int ilog2(int v) {
     return l;
 }
 
-// LDS bytes of a sweep launch (tile_layout: slot rows of the lpw lines and
-// the interface-exchange buffers).
-inline size_t sweep_lds(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax) {
+// LDS layout and bytes of a sweep launch (slot rows of the lpw lines and the
+// interface-exchange buffers) for either tile body.
+inline asd::TileLayout sweep_layout(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax, int variant) {
     const int P = std::min(64 * wpl, pow2_floor(n));
-    return (size_t)asd::tile_layout(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax).total;
+    return variant == asd::SWEEP_CELL_SLOTS ? asd::tile_layout_cell(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax)
+                                            : asd::tile_layout(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax);
+}
+inline size_t sweep_lds(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax,
+                        int variant = asd::SWEEP_FACE_SLOTS) {
+    return (size_t)sweep_layout(es, ndim, n, lpw, wpl, nthreads, mmax, variant).total;
 }
 
-inline int sweep_threads_cap(int es, int mmax) { return asd::sweep_max_threads(es, mmax); }
+inline int sweep_threads_cap(int es, int mmax, int variant = asd::SWEEP_FACE_SLOTS) {
+    return variant == asd::SWEEP_CELL_SLOTS ? asd::sweep_cell_max_threads(es, mmax) : asd::sweep_max_threads(es, mmax);
+}
 
 // Fill *out for a line of n cells.  want_wpl / want_lpw: 0 = heuristic.
 // Returns false if no configuration fits.
-inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out, int io = 1);
+inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out, int io = 1,
+                                 int variant = asd::SWEEP_FACE_SLOTS);
 
 inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, int want_lpw, SweepCfg* out,
-                             int io = 1) {
-    if (want_wpl > 0) return choose_sweep_cfg_wpl(es, ndim, n, chi, want_wpl, want_lpw, out, io);
+                             int io = 1, int variant = asd::SWEEP_FACE_SLOTS) {
+    if (want_wpl > 0) return choose_sweep_cfg_wpl(es, ndim, n, chi, want_wpl, want_lpw, out, io, variant);
     // heuristic: the fewest waves per line that keep <= pref cells per lane;
     // otherwise the feasible shape with the fewest cells per lane
     const int pref = es == 8 ? 8 : 16;
@@ -57,7 +66,7 @@ inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, in
     bool found = false;
     for (int wpl = 1; wpl <= 16; wpl *= 2) {
         SweepCfg c;
-        if (!choose_sweep_cfg_wpl(es, ndim, n, chi, wpl, want_lpw, &c)) continue;
+        if (!choose_sweep_cfg_wpl(es, ndim, n, chi, wpl, want_lpw, &c, 1, variant)) continue;
         if (c.mmax <= pref) {
             *out = c;
             return true;
@@ -71,28 +80,32 @@ inline bool choose_sweep_cfg(int es, int ndim, int n, bool chi, int want_wpl, in
     return found;
 }
 
-inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out, int io) {
+inline bool choose_sweep_cfg_wpl(int es, int ndim, int n, bool chi, int wpl, int want_lpw, SweepCfg* out, int io,
+                                 int variant) {
     if (wpl < 1 || wpl > 16 || (wpl & (wpl - 1))) return false;
     if (io != 1 && io != 2) return false;
+    if (variant != asd::SWEEP_FACE_SLOTS && variant != asd::SWEEP_CELL_SLOTS) return false;
+    if (variant == asd::SWEEP_CELL_SLOTS && io != 1) return false;
     const int P = std::min(64 * wpl, pow2_floor(n));
     const int m = (n + P - 1) / P;
     int mmax = 1;
     while (mmax < m) mmax *= 2;
     if (mmax > 16) return false;
-    const int cap = sweep_threads_cap(es, mmax);
+    const int cap = sweep_threads_cap(es, mmax, variant);
     const int tpl = 64 * wpl * io;  // threads per line
     if (tpl > cap) return false;
     int lpw = want_lpw;
     if (lpw <= 0) lpw = std::max(1, 256 / (64 * wpl));
-    while (lpw > 1 && (tpl * lpw > cap || sweep_lds(es, ndim, n, lpw, wpl, tpl * lpw, mmax) > kLdsLimit))
+    while (lpw > 1 && (tpl * lpw > cap || sweep_lds(es, ndim, n, lpw, wpl, tpl * lpw, mmax, variant) > kLdsLimit))
         lpw /= 2;
     if (tpl * lpw > cap) return false;
-    if (sweep_lds(es, ndim, n, lpw, wpl, tpl * lpw, mmax) > kLdsLimit) return false;
+    if (sweep_lds(es, ndim, n, lpw, wpl, tpl * lpw, mmax, variant) > kLdsLimit) return false;
     out->wpl = wpl;
     out->lpw = lpw;
     out->P = P;
     out->mmax = mmax;
     out->io = io;
+    out->variant = variant;
     return true;
 }
 

@@ -60,7 +60,8 @@ struct SweepParams {
     int io_log2;      // log2(io): staging and stores use 64*wpl*io threads per line (io = 1 or 2)
     int lpw_log2;     // log2(lpw)
     int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)
-    TileLayout lds;   // LDS layout of a tile (tile_layout)
+    int variant;      // SWEEP_FACE_SLOTS (sweep_tile.h) or SWEEP_CELL_SLOTS (sweep_cell.h); host side only
+    TileLayout lds;   // LDS layout of a tile (tile_layout / tile_layout_cell)
     ReduceParams red;
 };
 
@@ -101,6 +102,16 @@ template <typename T, int MMAX>
 struct SweepBounds {
     static constexpr int bytes = (int)sizeof(T) * MMAX;
     static constexpr int max_threads = sweep_max_threads((int)sizeof(T), MMAX);
+};
+// The two tile bodies of a sweep (same result; see sweep.hip).
+enum SweepVariant : int { SWEEP_FACE_SLOTS = 0, SWEEP_CELL_SLOTS = 1 };
+// The cell-slot variant keeps seven arrays of MMAX values per lane.
+__host__ __device__ constexpr int sweep_cell_max_threads(int es, int mmax) {
+    return es * mmax >= 128 ? 256 : (es * mmax >= 32 ? 512 : 1024);
+}
+template <typename T, int MMAX>
+struct SweepCellBounds {
+    static constexpr int max_threads = sweep_cell_max_threads((int)sizeof(T), MMAX);
 };
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block,

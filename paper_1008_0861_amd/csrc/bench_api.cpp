@@ -24,19 +24,28 @@ extern "C" int asd_get_sweep_config(asd_grid g, int32_t axis, int32_t* wpl, int3
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-extern "C" int asd_set_sweep_shape(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io) {
+extern "C" int asd_set_sweep_kernel(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io,
+                                    int32_t variant) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
     if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
     if (!is_pow2(wpl) || !is_pow2(lpw)) return asd_fail(ASD_EINVAL, "wpl and lpw must be powers of two");
     if (io != 1 && io != 2) return asd_fail(ASD_EINVAL, "io must be 1 or 2");
+    if (variant != SWEEP_FACE_SLOTS && variant != SWEEP_CELL_SLOTS)
+        return asd_fail(ASD_EINVAL, "variant must be 0 (face slots) or 1 (cell slots)");
+    if (variant == SWEEP_CELL_SLOTS && io != 1) return asd_fail(ASD_EINVAL, "the cell-slot variant takes io = 1");
     SweepCfg c;
     const bool chi = (g->d.flags & ASD_FLAG_PER_CELL_CHI) != 0;
-    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c, io) || c.wpl != wpl ||
-        c.lpw != lpw || c.io != io)
-        return asd_fail(ASD_EUNSUPPORTED, "launch shape wpl=%d lpw=%d io=%d does not fit", wpl, lpw, io);
+    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c, io, variant) ||
+        c.wpl != wpl || c.lpw != lpw || c.io != io || c.variant != variant)
+        return asd_fail(ASD_EUNSUPPORTED, "launch shape wpl=%d lpw=%d io=%d variant=%d does not fit", wpl, lpw, io,
+                        variant);
     g->cfg[axis] = c;
     g->graph_valid = false;
     return ASD_OK;
+}
+
+extern "C" int asd_set_sweep_shape(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw, int32_t io) {
+    return asd_set_sweep_kernel(g, axis, wpl, lpw, io, SWEEP_FACE_SLOTS);
 }
 
 extern "C" int asd_set_sweep_config(asd_grid g, int32_t axis, int32_t wpl, int32_t lpw) {
@@ -48,6 +57,14 @@ extern "C" int asd_get_sweep_io(asd_grid g, int32_t axis, int32_t* io) {
     if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
     if (!io) return asd_fail(ASD_EINVAL, "NULL output");
     *io = g->cfg[axis].io;
+    return ASD_OK;
+}
+
+extern "C" int asd_get_sweep_variant(asd_grid g, int32_t axis, int32_t* variant) {
+    if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
+    if (axis < 0 || axis >= g->d.ndim) return asd_fail(ASD_EINVAL, "bad axis %d", axis);
+    if (!variant) return asd_fail(ASD_EINVAL, "NULL output");
+    *variant = g->cfg[axis].variant;
     return ASD_OK;
 }
 
@@ -157,9 +174,10 @@ static int time_chain(asd_grid g, double dt, int reps, const SweepCfg* cfg, floa
     return rc;
 }
 
-// Autotuner: for each sweep axis in turn, every admissible (waves per line,
-// lines per workgroup) shape is timed inside whole steps (the other axes at
-// their current shapes), and the fastest is kept; two passes.  A shape's time
+// Autotuner: for each sweep axis in turn, every admissible (tile body,
+// waves per line, lines per workgroup, io) shape is timed inside whole steps
+// (the other axes at their current shapes), and the fastest is kept; two
+// passes.  A shape's time
 // is the best of three timings: shapes a few per cent apart are otherwise
 // ranked by the noise of a single sub-millisecond timing.
 extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
@@ -176,12 +194,14 @@ extern "C" int asd_tune(asd_grid g, double dt, int32_t reps) {
         for (int axis = 0; axis < g->d.ndim; ++axis) {
             SweepCfg best = cur[axis];
             float best_ms = 1e30f;
-            for (int io = 1; io <= 2; ++io)
+            for (int variant = SWEEP_FACE_SLOTS; variant <= SWEEP_CELL_SLOTS; ++variant)
+            for (int io = 1; io <= (variant == SWEEP_CELL_SLOTS ? 1 : 2); ++io)
             for (int wpl = 1; wpl <= 16; wpl *= 2) {
                 for (int lpw = 1; wpl * lpw * io <= 16; lpw *= 2) {
                     SweepCfg c;
-                    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c, io)) continue;
-                    if (c.wpl != wpl || c.lpw != lpw || c.io != io) continue;
+                    if (!choose_sweep_cfg((int)g->es, g->d.ndim, (int)g->d.n[axis], chi, wpl, lpw, &c, io, variant))
+                        continue;
+                    if (c.wpl != wpl || c.lpw != lpw || c.io != io || c.variant != variant) continue;
                     SweepCfg trial[3] = {cur[0], cur[1], cur[2]};
                     trial[axis] = c;
                     float ms = 1e30f;

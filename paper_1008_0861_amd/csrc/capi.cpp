@@ -404,7 +404,8 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.io_log2 = ilog2(c.io);
     P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode & SWEEP_SOLVE_ONLY;
-    P.lds = tile_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.nthreads(), c.wpl, P.nseg_log2, c.mmax);
+    P.variant = c.variant;
+    P.lds = sweep_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant);
     if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
     *Pout = P;
     return ASD_OK;
@@ -432,7 +433,7 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
     if (nblocks_out) *nblocks_out = (int)nblocks;
     if (red.partials && nblocks > g->max_blocks)
         return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
-    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax);
+    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant);
     return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st),
                      "sweep launch");
 }
@@ -505,9 +506,9 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     const bool reverse = (g->d.flags & ASD_FLAG_REVERSE_ORDER) != 0;  // 2-D only
     int rc = ASD_OK;
     // The initial state's energy: reduced by the first sweep, which reads
-    // every cell of it once (2-step scheme in the order x, y), and folded
-    // before the first steps' fold; else by a standalone reduction.
-    const bool fuse_e0 = outs.any() && nsteps > 0 && !four && !reverse;
+    // every cell of it once (2-step scheme in the order x, y, no source), and
+    // folded before the first steps' fold; else by a standalone reduction.
+    const bool fuse_e0 = outs.any() && nsteps > 0 && !four && !reverse && !g->src;
     FoldParams f0{};
     bool f0_pending = false;
     if (outs.any() && !fuse_e0) {

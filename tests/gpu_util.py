@@ -51,7 +51,7 @@ class GpuProblem:
     """A problem resident on the GPU, advanced on a private stream."""
 
     def __init__(self, p, prec, stream=None, allow_unstable=False, four_step=False, reverse_order=False,
-                 chi_exp=0.0, chi_tref=1.0):
+                 chi_exp=0.0, chi_tref=1.0, variant=None):
         self.p = p
         self.prec = prec
         self.stream = stream or torch.cuda.Stream()
@@ -72,6 +72,12 @@ class GpuProblem:
             if getattr(p, "src", None) is not None:
                 self.Q = torch.from_numpy(p.src).to(dt).cuda()
                 self.g.set_field("Q", self.Q)
+        if variant is not None:
+            # every sweep on the given tile body, in its default shape with io = 1
+            for axis in range(len(p.shape)):
+                c = self.g.sweep_config(axis)
+                self.g.set_sweep_config(axis, c["wpl"], c["lpw"], 1, variant)
+                assert self.g.sweep_config(axis)["variant"] == variant
 
     def run(self, nsteps=None, scheme="si", dt=None, energy=False):
         nsteps = self.p.nsteps if nsteps is None else nsteps

@@ -205,7 +205,34 @@ def test_sweep_config_api(asd):
     assert L.asd_set_sweep_config(h, 0, 3, 1) == -1
     assert L.asd_set_sweep_config(h, 0, 1, 64) == -8
     assert L.asd_set_sweep_config(h, 5, 1, 1) == -1
+    # tile bodies: face slots (0, default) and cell slots (1, io = 1 only)
+    v = ctypes.c_int32()
+    assert L.asd_get_sweep_variant(h, 0, ctypes.byref(v)) == 0 and v.value == 0
+    assert L.asd_set_sweep_kernel(h, 0, 2, 4, 1, 1) == 0
+    assert L.asd_get_sweep_variant(h, 0, ctypes.byref(v)) == 0 and v.value == 1
+    assert L.asd_get_sweep_config(h, 0, ctypes.byref(w), ctypes.byref(l), ctypes.byref(p), ctypes.byref(m)) == 0
+    assert (w.value, l.value) == (2, 4)
+    assert L.asd_set_sweep_kernel(h, 0, 2, 4, 2, 1) == -1  # io 2 is face-slot only
+    assert L.asd_set_sweep_kernel(h, 0, 2, 4, 1, 2) == -1  # no such body
+    assert L.asd_set_sweep_kernel(h, 0, 1, 64, 1, 1) == -8  # does not fit
+    assert L.asd_set_sweep_shape(h, 0, 2, 2, 1) == 0       # back to face slots
+    assert L.asd_get_sweep_variant(h, 0, ctypes.byref(v)) == 0 and v.value == 0
     L.asd_destroy(h)
+
+
+def test_cell_body_longest_lines(asd):
+    """The cell-slot body stages 16 bytes per cell in FP32 (twice the face
+    slots): its longest 2-D FP32 line is 8192 cells, and longer lines refuse
+    it while the face-slot body takes them."""
+    L = asd.lib()
+    for n, fits in ((8192, True), (16109, False)):
+        h, d, _ = _fake_grid(asd, shape=(4, n), h=(1 / n, 1 / 4))
+        ok = False
+        for wpl in (1, 2, 4, 8, 16):
+            ok = ok or L.asd_set_sweep_kernel(h, 0, wpl, 1, 1, 1) == 0
+        assert ok == fits, n
+        assert L.asd_set_sweep_kernel(h, 0, 16, 1, 1, 0) == 0 or L.asd_set_sweep_kernel(h, 0, 8, 1, 1, 0) == 0
+        L.asd_destroy(h)
 
 
 def test_batch_refuses_chi_of_T(asd):
