@@ -257,12 +257,12 @@ def batched(stream, torch, asd, nsteps=100):
                       bx=torch.from_numpy(p.b[0]).float().cuda(), by=torch.from_numpy(p.b[1]).float().cuda())
                  for p in probs]
         b = asd.Batch(items, dtype=torch.float32)
-        mode, nthreads = b.tune(probe_steps=2)
+        mode, nthreads = b.tune(probe_steps=5)
         b.step(2)
     stream.synchronize()
     cells = sum(p.ncells for p in probs)
     out = {"problems": 256, "cells": cells, "steps": nsteps, "tuned_mode": mode, "tuned_threads": nthreads,
-           "graph_per_call": True}
+           "tuned_tile_body": ["face slots", "cell slots"][b.variant()], "graph_per_call": True}
     for name, m, energy in (("tuned", -1, False), ("tuned_energy", -1, True), ("persistent", 0, False),
                             ("persistent_energy", 0, True), ("grouped", 2, False), ("sequential", 1, False)):
         with torch.cuda.stream(stream):

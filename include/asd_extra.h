@@ -69,9 +69,17 @@ int asd_batch_set_graphs(asd_batch b, int32_t on);
  * (EUNSUPPORTED if some problem's lines do not fit). */
 int asd_batch_set_block(asd_batch b, int32_t nthreads);
 
-/* Autotuner: time modes 0 and 2 at every admissible work-group size on
- * probe_steps steps (this advances the problems' T), keep the fastest for
- * mode -1 and report it (nullable outputs).  Synchronises the stream. */
+/* Tile body of the batch kernels (ASD_SWEEP_FACE_SLOTS, the default, or
+ * ASD_SWEEP_CELL_SLOTS; see asd_set_sweep_kernel) at the current work-group
+ * size: EINVAL for another value, EUNSUPPORTED if some problem's lines do
+ * not fit that body. */
+int asd_batch_set_variant(asd_batch b, int32_t variant);
+int asd_batch_get_variant(asd_batch b, int32_t *variant);
+
+/* Autotuner: time modes 0 and 2 at every admissible work-group size and
+ * tile body on probe_steps steps (this advances the problems' T), keep the
+ * fastest for mode -1 and report it (nullable outputs; the body through
+ * asd_batch_get_variant).  Synchronises the stream. */
 int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t *best_mode, int32_t *best_threads);
 
 int asd_batch_destroy(asd_batch b);

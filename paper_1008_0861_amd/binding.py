@@ -35,7 +35,8 @@ EXPORTED = [
     "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_step_series", "asd_adjoint_workspace_bytes",
     "asd_adjoint_step", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
-    "asd_batch_destroy", "asd_batch_set_block", "asd_batch_tune", "asd_batch_step_energy", "asd_batch_status",
+    "asd_batch_destroy", "asd_batch_set_block", "asd_batch_set_variant", "asd_batch_get_variant", "asd_batch_tune",
+    "asd_batch_step_energy", "asd_batch_status",
     "asd_batch_set_graphs",
     "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io",
     "asd_set_sweep_kernel", "asd_get_sweep_variant", "asd_tune",
@@ -99,6 +100,8 @@ def lib():
             "asd_batch_step": (ctypes.c_int, [vp, i32, i32]),
             "asd_batch_destroy": (ctypes.c_int, [vp]),
             "asd_batch_set_block": (ctypes.c_int, [vp, i32]),
+            "asd_batch_set_variant": (ctypes.c_int, [vp, i32]),
+            "asd_batch_get_variant": (ctypes.c_int, [vp, P(i32)]),
             "asd_batch_tune": (ctypes.c_int, [vp, i32, P(i32), P(i32)]),
             "asd_batch_step_energy": (ctypes.c_int, [vp, i32, i32, vp]),
             "asd_batch_status": (ctypes.c_int, [vp, P(ctypes.c_uint32), P(dbl)]),
@@ -373,6 +376,15 @@ class Batch:
 
     def set_block(self, nthreads):
         check(lib().asd_batch_set_block(self.handle, int(nthreads)))
+
+    def set_variant(self, variant):
+        """Tile body of the batch kernels: 0 face slots, 1 cell slots."""
+        check(lib().asd_batch_set_variant(self.handle, int(variant)))
+
+    def variant(self):
+        v = ctypes.c_int32()
+        check(lib().asd_batch_get_variant(self.handle, ctypes.byref(v)))
+        return v.value
 
     def tune(self, probe_steps=2):
         m, t = ctypes.c_int32(), ctypes.c_int32()

@@ -168,12 +168,12 @@ struct BatchOut {
 };
 template <typename T>
 hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
-                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet,
+                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet, int variant,
                                    const BatchOut& out, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
-                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, double* partials,
-                                hipStream_t st);
+                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, int variant,
+                                double* partials, hipStream_t st);
 // Energy of every problem's current state into out.energy[p * stride + 0].
 template <typename T>
 hipError_t launch_batch_reduce0(const BatchProblem<T>* probs, int nprob, const BatchOut& out, hipStream_t st);

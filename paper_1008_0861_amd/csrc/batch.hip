@@ -18,6 +18,7 @@
 // EXT: T = 0 walls (the batch's problems share one boundary condition); the
 // tiles then read the wall flag and the limiter from each problem's
 // parameters.
+#include "sweep_cell.h"
 #include "sweep_tile.h"
 
 namespace asd {
@@ -63,8 +64,23 @@ __device__ __forceinline__ void block_reduce3(double s, M mn, M mx, double& S, d
     __syncthreads();  // r_* may be refilled by the next call
 }
 
-template <typename T, int MMAX, int LIMC, bool EXT>
-__global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
+// One line tile of a batch problem on either tile body (CELL: the
+// cell-slot body of sweep_cell.h).  Both end with a block barrier.
+template <typename T, int MMAX, int LIMC, bool EXT, bool CELL, bool REUSE>
+__device__ __forceinline__ void batch_tile(const SweepParams<T>& P, int l1_0, unsigned char* smem, double& lsum,
+                                           T& lmin, T& lmax) {
+    if constexpr (CELL)
+        cell::sweep_tile<T, 2, MMAX, LIMC, EXT>(P, l1_0, 0, smem, lsum, lmin, lmax);
+    else
+        sweep_tile<T, 2, MMAX, LIMC, EXT, REUSE>(P, l1_0, 0, smem, lsum, lmin, lmax);
+}
+template <typename T, int MMAX, bool CELL>
+struct BatchBounds {
+    static constexpr int max_threads = CELL ? SweepCellBounds<T, MMAX>::max_threads : SweepBounds<T, MMAX>::max_threads;
+};
+
+template <typename T, int MMAX, int LIMC, bool EXT, bool CELL>
+__global__ void __launch_bounds__((BatchBounds<T, MMAX, CELL>::max_threads))
     batch_persistent_kernel(const BatchProblem<T>* probs, const int* off, const int* list, int nsteps, BatchOut out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i0 = off[blockIdx.x], i1 = off[blockIdx.x + 1];
@@ -85,7 +101,7 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
                 T amin = T(__builtin_huge_val()), amax = T(-__builtin_huge_val());
                 const int ng = bp->ngroups[d];
                 for (int g = 0; g < ng; ++g) {
-                    sweep_tile<T, 2, MMAX, LIMC, EXT, true>(P, g * P.lpw, 0, smem_raw, lsum, lmin, lmax);
+                    batch_tile<T, MMAX, LIMC, EXT, CELL, true>(P, g * P.lpw, smem_raw, lsum, lmin, lmax);
                     acc += lsum;
                     amin = lmin < amin ? lmin : amin;
                     amax = lmax > amax ? lmax : amax;
@@ -113,8 +129,8 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     }
 }
 
-template <typename T, int MMAX, int LIMC, bool EXT>
-__global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
+template <typename T, int MMAX, int LIMC, bool EXT, bool CELL>
+__global__ void __launch_bounds__((BatchBounds<T, MMAX, CELL>::max_threads))
     batch_grouped_kernel(const BatchProblem<T>* probs, const int* group_start, int nprob, int d, double* partials) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int b = blockIdx.x;
@@ -128,7 +144,7 @@ __global__ void __launch_bounds__((SweepBounds<T, MMAX>::max_threads))
     P.red.partials = partials;
     double lsum;
     T lmin, lmax;
-    sweep_tile<T, 2, MMAX, LIMC, EXT>(P, (b - group_start[lo]) * P.lpw, 0, smem_raw, lsum, lmin, lmax);
+    batch_tile<T, MMAX, LIMC, EXT, CELL, false>(P, (b - group_start[lo]) * P.lpw, smem_raw, lsum, lmin, lmax);
     // block b's partial sits at index b: problem p's y-sweep tiles are
     // tile0[p] .. tile0[p] + ngroups[1] - 1
     if (partials) block_partials<T>(partials, lsum, lmin, lmax);
@@ -185,12 +201,15 @@ __global__ void __launch_bounds__(256) batch_fold_kernel(const BatchProblem<T>* 
 
 template <typename T, int MMAX, int LIMC, bool EXT>
 static hipError_t set_batch_attrs_lim(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)batch_persistent_kernel<T, MMAX, LIMC, EXT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)batch_grouped_kernel<T, MMAX, LIMC, EXT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    return e;
+    const void* fns[] = {(const void*)batch_persistent_kernel<T, MMAX, LIMC, EXT, false>,
+                         (const void*)batch_grouped_kernel<T, MMAX, LIMC, EXT, false>,
+                         (const void*)batch_persistent_kernel<T, MMAX, LIMC, EXT, true>,
+                         (const void*)batch_grouped_kernel<T, MMAX, LIMC, EXT, true>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 template <typename T, int MMAX>
 static hipError_t set_batch_attrs(int bytes) {
@@ -213,20 +232,29 @@ hipError_t batch_set_lds_limits(int bytes) {
 // The problems of a batch share one limiter and boundary condition
 // (checked by the host); van Leer without walls has its own straight-line
 // instantiation, T = 0 walls take the EXT one.
-#define ASD_BATCH_LAUNCH(KERNEL, MM, ...)                                                   \
+#define ASD_BATCH_LAUNCH_BODY(KERNEL, MM, CELL, ...)                                        \
     do {                                                                                    \
         if (dirichlet)                                                                      \
-            hipLaunchKernelGGL((KERNEL<T, MM, -1, true>), __VA_ARGS__);                     \
+            hipLaunchKernelGGL((KERNEL<T, MM, -1, true, CELL>), __VA_ARGS__);               \
         else if (limiter == LIM_VANLEER)                                                    \
-            hipLaunchKernelGGL((KERNEL<T, MM, LIM_VANLEER, false>), __VA_ARGS__);           \
+            hipLaunchKernelGGL((KERNEL<T, MM, LIM_VANLEER, false, CELL>), __VA_ARGS__);     \
         else                                                                                \
-            hipLaunchKernelGGL((KERNEL<T, MM, -1, false>), __VA_ARGS__);                    \
+            hipLaunchKernelGGL((KERNEL<T, MM, -1, false, CELL>), __VA_ARGS__);              \
+    } while (0)
+#define ASD_BATCH_LAUNCH(KERNEL, MM, ...)                                                   \
+    do {                                                                                    \
+        if (variant == SWEEP_CELL_SLOTS) ASD_BATCH_LAUNCH_BODY(KERNEL, MM, true, __VA_ARGS__);  \
+        else ASD_BATCH_LAUNCH_BODY(KERNEL, MM, false, __VA_ARGS__);                         \
     } while (0)
 
 template <typename T>
 hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off, const int* list, int nwg, int nsteps,
-                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet,
+                                   int mmax, int nthreads, size_t lds, int limiter, int dirichlet, int variant,
                                    const BatchOut& out, hipStream_t st) {
+    if ((variant != SWEEP_FACE_SLOTS && variant != SWEEP_CELL_SLOTS) ||
+        nthreads > (variant == SWEEP_CELL_SLOTS ? sweep_cell_max_threads((int)sizeof(T), mmax)
+                                                : sweep_max_threads((int)sizeof(T), mmax)))
+        return hipErrorInvalidValue;
     switch (mmax) {
         case 4: ASD_BATCH_LAUNCH(batch_persistent_kernel, 4, dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps, out); break;
         case 8: ASD_BATCH_LAUNCH(batch_persistent_kernel, 8, dim3(nwg), dim3(nthreads), lds, st, probs, off, list, nsteps, out); break;
@@ -238,8 +266,12 @@ hipError_t launch_batch_persistent(const BatchProblem<T>* probs, const int* off,
 
 template <typename T>
 hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_start, int nprob, int ngroups, int d,
-                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, double* partials,
-                                hipStream_t st) {
+                                int mmax, int nthreads, size_t lds, int limiter, int dirichlet, int variant,
+                                double* partials, hipStream_t st) {
+    if ((variant != SWEEP_FACE_SLOTS && variant != SWEEP_CELL_SLOTS) ||
+        nthreads > (variant == SWEEP_CELL_SLOTS ? sweep_cell_max_threads((int)sizeof(T), mmax)
+                                                : sweep_max_threads((int)sizeof(T), mmax)))
+        return hipErrorInvalidValue;
     switch (mmax) {
         case 4: ASD_BATCH_LAUNCH(batch_grouped_kernel, 4, dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d, partials); break;
         case 8: ASD_BATCH_LAUNCH(batch_grouped_kernel, 8, dim3(ngroups), dim3(nthreads), lds, st, probs, group_start, nprob, d, partials); break;
@@ -249,6 +281,7 @@ hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_s
     return hipGetLastError();
 }
 #undef ASD_BATCH_LAUNCH
+#undef ASD_BATCH_LAUNCH_BODY
 
 template <typename T>
 hipError_t launch_batch_reduce0(const BatchProblem<T>* probs, int nprob, const BatchOut& out, hipStream_t st) {
@@ -264,9 +297,9 @@ hipError_t launch_batch_fold(const BatchProblem<T>* probs, int nprob, const Batc
 
 #define ASD_BATCH_INST(T)                                                                                        \
     template hipError_t launch_batch_persistent<T>(const BatchProblem<T>*, const int*, const int*, int, int, int, \
-                                                   int, size_t, int, int, const BatchOut&, hipStream_t);          \
+                                                   int, size_t, int, int, int, const BatchOut&, hipStream_t);     \
     template hipError_t launch_batch_grouped<T>(const BatchProblem<T>*, const int*, int, int, int, int, int,     \
-                                                size_t, int, int, double*, hipStream_t);                        \
+                                                size_t, int, int, int, double*, hipStream_t);                   \
     template hipError_t launch_batch_reduce0<T>(const BatchProblem<T>*, int, const BatchOut&, hipStream_t);      \
     template hipError_t launch_batch_fold<T>(const BatchProblem<T>*, int, const BatchOut&, hipStream_t);
 ASD_BATCH_INST(float)

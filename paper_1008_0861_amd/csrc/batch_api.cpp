@@ -29,6 +29,7 @@ struct asd_batch_s {
     std::vector<char*> sub_ws;
     // launch shape shared by every problem in the batch kernels
     int mmax = 8, nthreads = 512, mode = 0;
+    int variant = SWEEP_FACE_SLOTS;  // tile body of every problem's sweeps
     size_t lds = 0;
     std::vector<SweepCfg> cfg;  // [2 * p + d]
     // device tables (workspace) and their host images
@@ -110,46 +111,52 @@ extern "C" int asd_batch_workspace_bytes(const asd_desc* descs, int32_t nprob, s
 }
 
 // Launch shape of problem line length n for a fixed workgroup size.
-static bool batch_line_cfg(int es, int n, int nthreads, int mmax, SweepCfg* out) {
+static bool batch_line_cfg(int es, int n, int nthreads, int mmax, int variant, SweepCfg* out) {
     for (int wpl = 1; 64 * wpl <= nthreads; wpl *= 2) {
         const int P = std::min(64 * wpl, pow2_floor(n));
         if ((n + P - 1) / P > mmax) continue;
         const int lpw = nthreads / (64 * wpl);
-        if (sweep_lds(es, 2, n, lpw, wpl, nthreads, mmax) > kLdsLimit) continue;
+        if (sweep_lds(es, 2, n, lpw, wpl, nthreads, mmax, variant) > kLdsLimit) continue;
         out->wpl = wpl;
         out->lpw = lpw;
         out->P = P;
         out->mmax = mmax;
+        out->variant = variant;
         return true;
     }
     return false;
 }
 
-// Choose (mmax, nthreads) for all problems; fills b->cfg and b->lds.
-static int batch_shape(asd_batch b, int nthreads) {
+// Choose (mmax, nthreads) for all problems on one tile body; fills b->cfg
+// and b->lds.
+static int batch_shape(asd_batch b, int nthreads, int variant) {
     const int es = b->d0.dtype == ASD_F64 ? 8 : 4;
     for (int mmax : {4, 8, 16}) {
-        if (nthreads > sweep_threads_cap(es, mmax)) continue;
+        if (nthreads > sweep_threads_cap(es, mmax, variant)) continue;
         std::vector<SweepCfg> cfg(2 * b->nprob);
         size_t lds = 0;
         bool ok = true;
         for (int p = 0; p < b->nprob && ok; ++p) {
             for (int d = 0; d < 2 && ok; ++d) {
                 const int n = (int)b->sub[p]->d.n[d];
-                ok = batch_line_cfg(es, n, nthreads, mmax, &cfg[2 * p + d]);
-                if (ok) lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, cfg[2 * p + d].wpl, nthreads, mmax));
+                ok = batch_line_cfg(es, n, nthreads, mmax, variant, &cfg[2 * p + d]);
+                if (ok)
+                    lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, cfg[2 * p + d].wpl, nthreads, mmax,
+                                                  variant));
             }
         }
         if (!ok) continue;
         b->mmax = mmax;
         b->nthreads = nthreads;
+        b->variant = variant;
         b->cfg = cfg;
         b->lds = lds;
         b->dirty = true;
         ++b->version;
         return ASD_OK;
     }
-    return asd_fail(ASD_EUNSUPPORTED, "no batch launch shape with %d threads fits every problem", nthreads);
+    return asd_fail(ASD_EUNSUPPORTED, "no batch launch shape with %d threads and tile body %d fits every problem",
+                    nthreads, variant);
 }
 
 extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws, size_t ws_bytes, void* stream,
@@ -199,8 +206,8 @@ extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws
         b->sub[p]->stats = b->d_stats + 3 * p;
         cur += align256(wb);
     }
-    rc = batch_shape(b, 512);
-    if (rc) rc = batch_shape(b, 256);
+    rc = batch_shape(b, 512, SWEEP_FACE_SLOTS);
+    if (rc) rc = batch_shape(b, 256, SWEEP_FACE_SLOTS);
     if (rc) {
         asd_batch_destroy(b);
         return rc;
@@ -244,7 +251,21 @@ extern "C" int asd_batch_set_block(asd_batch b, int32_t nthreads) {
     if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
     if (nthreads != 256 && nthreads != 512 && nthreads != 1024)
         return asd_fail(ASD_EINVAL, "nthreads must be 256, 512 or 1024");
-    return batch_shape(b, nthreads);
+    return batch_shape(b, nthreads, b->variant);
+}
+
+extern "C" int asd_batch_set_variant(asd_batch b, int32_t variant) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (variant != SWEEP_FACE_SLOTS && variant != SWEEP_CELL_SLOTS)
+        return asd_fail(ASD_EINVAL, "variant must be 0 (face slots) or 1 (cell slots)");
+    return batch_shape(b, b->nthreads, variant);
+}
+
+extern "C" int asd_batch_get_variant(asd_batch b, int32_t* variant) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (!variant) return asd_fail(ASD_EINVAL, "NULL output");
+    *variant = b->variant;
+    return ASD_OK;
 }
 
 // Build (if needed) and upload the launch tables.
@@ -326,14 +347,14 @@ static int enqueue_batch(asd_batch b, int nsteps, int mode, double* energy) {
     if (mode == 0) {
         if (e == hipSuccess)
             e = launch_batch_persistent<T>(probs, b->d_off, b->d_list, b->nwg, nsteps, b->mmax, b->nthreads, b->lds,
-                                           b->d0.limiter, dir, out, b->st);
+                                           b->d0.limiter, dir, b->variant, out, b->st);
     } else {
         int used = 0;
         for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
             for (int d = 0; d < 2 && e == hipSuccess; ++d) {
                 double* part = energy && d == 1 ? b->d_ring + (size_t)used * out.slot_stride : nullptr;
                 e = launch_batch_grouped<T>(probs, b->d_gs[d], b->nprob, b->ngroups[d], d, b->mmax, b->nthreads,
-                                            b->lds, b->d0.limiter, dir, part, b->st);
+                                            b->lds, b->d0.limiter, dir, b->variant, part, b->st);
             }
             if (e == hipSuccess && energy && (++used == b->ring_slots || s == nsteps - 1)) {
                 BatchOut f = out;
@@ -461,8 +482,9 @@ extern "C" int asd_batch_status(asd_batch b, uint32_t* flags, double* stats) {
 }
 
 // Time the persistent and grouped schedules at every admissible workgroup
-// size on `probe_steps` steps each and keep the fastest as mode -1.  The
-// problems' T are advanced by the probes; callers reset them afterwards.
+// size and tile body on `probe_steps` steps each and keep the fastest as
+// mode -1.  The problems' T are advanced by the probes; callers reset them
+// afterwards.
 extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mode, int32_t* best_threads) {
     if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
     if (probe_steps < 1) return asd_fail(ASD_EINVAL, "probe_steps must be >= 1");
@@ -470,10 +492,12 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return asd_fail(ASD_EHIP, "event create");
     float best = 1e30f;
-    int bm = 0, bt = b->nthreads;
+    int bm = 0, bt = b->nthreads, bv = b->variant;
     int rc = ASD_OK;
+    for (int variant : {(int)SWEEP_FACE_SLOTS, (int)SWEEP_CELL_SLOTS})
     for (int nt : {256, 512, 1024}) {
-        if (batch_shape(b, nt) != ASD_OK) continue;
+        if (rc) break;
+        if (batch_shape(b, nt, variant) != ASD_OK) continue;
         for (int mode : {0, 2}) {
             rc = asd_batch_step(b, probe_steps, mode);  // warm-up (tables, coefficients, graph capture)
             if (rc) break;
@@ -490,6 +514,7 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
                 best = ms;
                 bm = mode;
                 bt = nt;
+                bv = variant;
             }
         }
         if (rc) break;
@@ -497,7 +522,7 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    rc = batch_shape(b, bt);
+    rc = batch_shape(b, bt, bv);
     if (rc) return rc;
     b->mode = bm;
     if (best_mode) *best_mode = bm;

@@ -271,3 +271,30 @@ def test_batch_256_uneven_problems_full_size():
         print("problem %d %s: max %.3e, %d cells beyond 1e-5 (%.4f), mean %.2e" % r)
     bad = [r for r in rows if r[4] > 0.1 or r[2] > 5e-3 or r[5] > 1e-5]
     assert not bad, bad
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_batch_cell_body_matches_oracle(mode, prec, bc):
+    """The batch kernels on the cell-slot tile body (the autotuner's other
+    choice): every problem against the oracle, and the per-step FP64
+    energies."""
+    probs = _small_batch(12, 5)
+    if bc == "dirichlet":
+        probs = [dataclasses.replace(p, bc="dirichlet") for p in probs]
+    st = torch.cuda.Stream()
+    b, items = _gpu_batch(probs, prec, st, bc=bc)
+    b.set_variant(1)
+    assert b.variant() == 1
+    with torch.cuda.stream(st):
+        e = b.step(5, mode, energy=True)
+    st.synchronize()
+    e = e.cpu().numpy()
+    err = mixed_rel_err if bc == "dirichlet" else max_rel_err
+    for i, (p, it) in enumerate(zip(probs, items)):
+        ref, eref = oracle_run(p, prec, nsteps=5, energy=True)
+        got = it["T"].double().cpu().numpy()
+        assert err(got, ref) <= TOL[prec], (p.name, p.shape, err(got, ref))
+        if prec == "f64":
+            np.testing.assert_allclose(e[i], eref, rtol=1e-13, atol=1e-300)
