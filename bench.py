@@ -142,7 +142,7 @@ def kernel_source_digest():
     """Digest of the sources and build flags that define the timed sweep kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_tile.h", "asd_device.h", "asd_launch.h"):
+    for f in ("sweep.hip", "sweep_tile.h", "sweep_cell.h", "asd_device.h", "asd_launch.h"):
         h.update(open(os.path.join(ROOT, "paper_1008_0861_amd", "csrc", f), "rb").read())
     from paper_1008_0861_amd import build as _build
     h.update(repr((_build.FLAGS, _build.SOURCE_FLAGS.get("sweep.hip", []))).encode())

@@ -152,18 +152,33 @@ __global__ void __launch_bounds__((BatchBounds<T, MMAX, CELL>::max_threads))
 
 // Block p: FP64 energy of problem p's current state (its x-sweep input).
 template <typename T>
-__global__ void __launch_bounds__(256) batch_reduce0_kernel(const BatchProblem<T>* probs, BatchOut out) {
+__global__ void __launch_bounds__(1024) batch_reduce0_kernel(const BatchProblem<T>* probs, BatchOut out) {
     const BatchProblem<T>& bp = probs[blockIdx.x];
     const SweepParams<T>& P = bp.sweep[0];
     const int N = P.n * P.nt1;
-    double s = 0.0;
+    // four loads in flight per thread (four partial sums, combined in a
+    // fixed order)
+    constexpr int U4 = 4;
+    double s4[U4] = {0.0, 0.0, 0.0, 0.0};
     T mn = T(__builtin_huge_val()), mx = T(-__builtin_huge_val());
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const T v = P.U[i];
-        s += (double)v;
-        mn = v < mn ? v : mn;
-        mx = v > mx ? v : mx;
+    const int stride = (int)blockDim.x * U4;
+    for (int i0 = threadIdx.x; i0 < N; i0 += stride) {
+        T v[U4];
+#pragma unroll
+        for (int u = 0; u < U4; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            v[u] = i < N ? P.U[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U4; ++u) {
+            if (i0 + u * (int)blockDim.x < N) {
+                s4[u] += (double)v[u];
+                mn = v[u] < mn ? v[u] : mn;
+                mx = v[u] > mx ? v[u] : mx;
+            }
+        }
     }
+    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     double S, MN, MX;
     block_reduce3<T>(s, mn, mx, S, MN, MX);
     if (threadIdx.x == 0) out.energy[(size_t)blockIdx.x * out.stride] = S * bp.dV;
@@ -285,7 +300,7 @@ hipError_t launch_batch_grouped(const BatchProblem<T>* probs, const int* group_s
 
 template <typename T>
 hipError_t launch_batch_reduce0(const BatchProblem<T>* probs, int nprob, const BatchOut& out, hipStream_t st) {
-    hipLaunchKernelGGL(batch_reduce0_kernel<T>, dim3(nprob), dim3(256), 0, st, probs, out);
+    hipLaunchKernelGGL(batch_reduce0_kernel<T>, dim3(nprob), dim3(1024), 0, st, probs, out);
     return hipGetLastError();
 }
 
