@@ -32,9 +32,9 @@ static AdjPlan adj_plan(asd_grid g, int nsteps, int k) {
     p.k = k;
     p.nck = nsteps > 0 ? (nsteps + k - 1) / k : 1;
     p.field = align256((size_t)g->N * g->es);
-    // checkpoints + (k+1) recomputed states + k T* + transposed scratch +
+    // checkpoints + k recomputed states + k T* + transposed scratch +
     // lambda (both layouts) + mu
-    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k + 1) + 1 + 3);
+    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k) + 4);
     return p;
 }
 
