@@ -28,6 +28,7 @@ struct FoldParams {
     double* stats_out;   // nullable: {sum * dV, min, max} of the last reduction
     unsigned* flags;     // nullable: ORed with status bits
     const double* e0;    // nullable: reference energy for the drift flag
+    int e0_slot0;        // the drift reference is reduction 0 of this launch (each block folds it too)
     double dV;
 };
 
@@ -252,16 +253,15 @@ __device__ __forceinline__ void block_partials(double* partials, double s, M mn,
     }
 }
 
-// Fold reduction b = blockIdx.x of f: its nblocks partials in a fixed order
-// (thread i takes i, i+nthreads, ..., then a fixed tree).
-__device__ __forceinline__ void fold_partials(const FoldParams& f) {
+// Block-wide fold of nblocks partials (sum, min, max) in a fixed order
+// (thread i takes i, i+nthreads, ..., then a fixed tree); thread 0 gets
+// the result.  Every thread must call it.
+__device__ __forceinline__ void fold_slot(const double* part, int nblocks, double& S, double& MN, double& MX) {
     __shared__ double fs[16], fmn[16], fmx[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
-    const int b = blockIdx.x;
-    const double* part = f.partials + (size_t)b * f.slot_stride;
     double ts = 0.0, tmn = __builtin_huge_val(), tmx = -__builtin_huge_val();
-    for (int i = threadIdx.x; i < f.nblocks; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
         const double* pp = part + 3 * (size_t)i;
         ts += pp[0];
         tmn = fmin(tmn, pp[1]);
@@ -272,13 +272,28 @@ __device__ __forceinline__ void fold_partials(const FoldParams& f) {
     tmx = wave_max_lane63<double>(tmx);
     if (lane == 63) { fs[wid] = ts; fmn[wid] = tmn; fmx[wid] = tmx; }
     __syncthreads();
+    S = 0.0;
+    MN = fmn[0];
+    MX = fmx[0];
     if (threadIdx.x == 0) {
-        double S = 0.0, MN = fmn[0], MX = fmx[0];
         for (int w = 0; w < nw; ++w) {
             S += fs[w];
             MN = fmin(MN, fmn[w]);
             MX = fmax(MX, fmx[w]);
         }
+    }
+    __syncthreads();  // fs may be refilled by the next call
+}
+
+// Fold reduction b = blockIdx.x of f.
+__device__ __forceinline__ void fold_partials(const FoldParams& f) {
+    const int b = blockIdx.x;
+    double S, MN, MX;
+    fold_slot(f.partials + (size_t)b * f.slot_stride, f.nblocks, S, MN, MX);
+    // drift reference folded by this block too, in the same order as block 0
+    double S0 = 0.0, MN0, MX0;
+    if (f.e0_slot0 && b > 0) fold_slot(f.partials, f.nblocks, S0, MN0, MX0);
+    if (threadIdx.x == 0) {
         const double E = S * f.dV;
         if (f.energy_out) f.energy_out[b] = E;
         if (f.series_out) { f.series_out[3 * b] = E; f.series_out[3 * b + 1] = MN; f.series_out[3 * b + 2] = MX; }
@@ -289,8 +304,8 @@ __device__ __forceinline__ void fold_partials(const FoldParams& f) {
             // fma(S, dV, -E), the product's rounding error
             if (!__builtin_isfinite(E) || !__builtin_isfinite(MN) || !__builtin_isfinite(MX)) fl |= 1u;
             if (MN < 0.0) fl |= 2u;
-            if (f.e0) {
-                const double e0 = *f.e0;
+            if (f.e0 || (f.e0_slot0 && b > 0)) {
+                const double e0 = f.e0 ? *f.e0 : S0 * f.dV;
                 if (fabs(E - e0) > 1e-6 * fabs(e0)) fl |= 4u;
             }
             if (fl) atomicOr(f.flags, fl);

@@ -360,8 +360,11 @@ FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count,
     f.series_out = out.series ? out.series + 3 * first : nullptr;
     f.stats_out = g->stats;
     f.flags = g->flags;
-    // the energy is conserved only without T = 0 walls and sources
-    f.e0 = first > 0 && g->d.bc != ASD_BC_DIRICHLET && !g->src ? out.e0() : nullptr;
+    // the energy is conserved only without T = 0 walls and sources; a fold
+    // that starts at entry 0 checks against its own reduction 0
+    const bool conserved = g->d.bc != ASD_BC_DIRICHLET && !g->src;
+    f.e0 = first > 0 && conserved ? out.e0() : nullptr;
+    f.e0_slot0 = first == 0 && conserved;
     double dv = 1.0;
     for (int q = 0; q < g->d.ndim; ++q) dv *= g->d.h[q];
     f.dV = dv;
@@ -500,6 +503,15 @@ int check_dt(asd_grid g, double dt, bool explicit_scheme) {
 // every step's last kernel writes per-block partials into the next ring
 // slot, and one fold launch turns a full ring (or the last steps) into the
 // outputs of each of those steps, off the sweeps' critical path.
+// Workgroups of one launch of sweep d in the grid's current launch shape.
+static int64_t sweep_num_blocks(asd_grid g, int d) {
+    const SweepGeom G = sweep_geom(g->d.ndim, d);
+    const int64_t nz = g->d.ndim == 3 ? g->d.n[2] : 1;
+    const int64_t nax[3] = {g->d.n[0], g->d.n[1], nz};
+    const int lpw = g->cfg[d].lpw;
+    return (nax[G.t1] + lpw - 1) / lpw * nax[G.t2];
+}
+
 int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     const int nd = g->d.ndim;
     const bool four = (g->d.flags & ASD_FLAG_FOUR_STEP) != 0;
@@ -509,6 +521,10 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
     // every cell of it once (2-step scheme in the order x, y, no source), and
     // folded before the first steps' fold; else by a standalone reduction.
     const bool fuse_e0 = outs.any() && nsteps > 0 && !four && !reverse && !g->src;
+    // when the first sweep and the step's last sweep launch as many blocks,
+    // the initial state's partials take ring slot 0 and are folded with the
+    // first steps' (one fold launch fewer per call)
+    const bool e0_in_ring = fuse_e0 && sweep_num_blocks(g, 0) == sweep_num_blocks(g, g->d.ndim - 1);
     FoldParams f0{};
     bool f0_pending = false;
     if (outs.any() && !fuse_e0) {
@@ -525,7 +541,7 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
         if (r == ASD_OK) r = enqueue_sweep(g, d, dt, src, dst, mode, red, nullptr, nb);
         return r;
     };
-    int used = 0;  // ring slots holding unfolded steps
+    int used = e0_in_ring ? 1 : 0;  // ring slots holding unfolded entries
     for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
         const void* in = reverse ? g->tmp[1] : g->T;
         for (int i = 0; i < nd && rc == ASD_OK; ++i) {
@@ -535,7 +551,7 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
             ReduceParams red = no_reduce();
             if (produce) red.partials = ring_slot(g, used);
             if (fuse_e0 && s == 0 && i == 0) {
-                red.partials = ring_slot(g, g->ring_slots);
+                red.partials = e0_in_ring ? ring_slot(g, 0) : ring_slot(g, g->ring_slots);
                 red.of_input = 1;
             }
             int nb = 0;
@@ -553,7 +569,7 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
             } else if (!four) {
                 out = (d == nd - 1) ? g->T : g->tmp[d];
                 rc = sweep(d, in, out, src, red, &nb);
-                if (red.of_input) {
+                if (red.of_input && !e0_in_ring) {
                     f0 = make_fold(g, red.partials, nb, 1, outs, 0);
                     f0_pending = true;
                 }

@@ -189,6 +189,31 @@ def test_energy_series_across_fold_batches(scheme, graphs):
     np.testing.assert_allclose(e, eref, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("nsteps", [1, 2, 30, 31, 32, 33, 70])
+def test_energy_entry_zero_folded_with_the_steps(nsteps):
+    """Square grid, both sweeps with the same block count: the initial
+    state's partials (reduced by the first sweep from its input) share ring
+    slot 0 with the steps' and are folded with them; every fold length
+    around the ring's capacity (32 entries) gives the oracle's energies, no
+    status flag, and the series (E, min, max) of every state."""
+    p = _random_problem((64, 64), "periodic", seed=12, nsteps=nsteps)
+    _, eref = oracle_run(p, "f64", energy=True)
+    gp = GpuProblem(p, "f64")
+    for axis in range(2):
+        gp.g.set_sweep_config(axis, 1, 4)
+    _, e = gp.run(energy=True)
+    np.testing.assert_allclose(e, eref, rtol=1e-13, atol=0)
+    with torch.cuda.stream(gp.stream):
+        flags, stats = gp.g.status()
+    assert flags == 0
+    np.testing.assert_allclose(stats[0], eref[-1], rtol=1e-13)
+    gs = GpuProblem(p, "f64")
+    with torch.cuda.stream(gs.stream):
+        series = gs.g.step_series("si", p.dt, nsteps)
+    gs.stream.synchronize()
+    np.testing.assert_allclose(series.cpu().numpy()[:, 0], eref, rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("limiter", ["vanleer", "minmod", "mc", "linear"])
 def test_explicit_limiters_per_cell_chi(limiter):
     p = _random_problem((50, 70), "insulating", limiter=limiter, per_cell_chi=True, chi_perp=1e-3, seed=2)
