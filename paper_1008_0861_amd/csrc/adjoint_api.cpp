@@ -3,7 +3,8 @@
 //
 // Forward states are checkpointed every ckpt_every steps; the reverse pass
 // walks the segments backwards, recomputing each segment's states (T^n and
-// T*) from its checkpoint, then runs per step, last step first:
+// T*, which the x sweep stores in both layouts) from its checkpoint, then
+// runs per step, last step first:
 //     mu_y = A_y^-1 lambda                       (line solves, y)
 //     lambda* = mu_y + J_Sy(T*)^T mu_y; chi grads from the y faces
 //     mu_x = A_x^-1 lambda*                      (line solves, x)
@@ -142,9 +143,9 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
         const bool last_stored = c + 1 < pl.nck;
         if (last_stored) St[len] = ck[c + 1];
         for (int i = 0; i < len; ++i) {
-            rc = enqueue_sweep(g, 0, dt, St[i], tB, 0, no_reduce(), nullptr, nullptr);
-            if (rc) return rc;
-            rc = enqueue_permute_2d(g, tB, TS[i], false);
+            // T* in the y sweep's layout (tB) and, second store, in the
+            // natural layout the stencils read (TS[i])
+            rc = enqueue_sweep(g, 0, dt, St[i], tB, 0, no_reduce(), nullptr, nullptr, TS[i]);
             if (rc) return rc;
             if (i + 1 == len && last_stored) break;
             rc = enqueue_sweep(g, 1, dt, tB, St[i + 1], 0, no_reduce(), nullptr, nullptr);

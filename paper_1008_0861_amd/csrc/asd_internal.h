@@ -184,9 +184,11 @@ struct StepOut {
 // Fold of count consecutive reductions into entries first .. first+count-1 of out.
 asd::FoldParams make_fold(asd_grid g, const double* partials, int nblocks, int count, const StepOut& out, int first);
 inline double* ring_slot(asd_grid g, int i) { return g->ring + (size_t)i * g->max_blocks * 3; }
+// out2 (nullable): the output also written in the input layout (sweeps
+// whose output layout is transposed).
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
                   const asd::ReduceParams& red, const SweepCfg* cfg,
-                  int* nblocks_out);
+                  int* nblocks_out, void* out2 = nullptr);
 int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& out);
 int enqueue_explicit_loop(asd_grid g, double dt, int nsteps, const StepOut& out);
 int enqueue_permute_2d(asd_grid g, const void* in, void* out, bool a_to_b);

@@ -36,6 +36,7 @@ template <typename T>
 struct SweepParams {
     const T* U;       // input state
     T* out;           // output state (never aliases U)
+    T* out2;          // nullable: the output written a second time in U's layout (transposed-output sweeps)
     const T* alpha;   // normal coefficient of the face after each cell, in U's layout
     const T* beta1;   // transverse coefficient (axis t1) of that face
     const T* beta2;   // transverse coefficient (axis t2), 3-D only

@@ -418,12 +418,16 @@ template int fill_sweep_params<double>(asd_grid, int, const void*, void*, int, c
 
 template <typename T>
 static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode,
-                           const ReduceParams& red, const SweepCfg* override_cfg, int* nblocks_out) {
+                           const ReduceParams& red, const SweepCfg* override_cfg, int* nblocks_out, void* out2) {
     // the coefficients were computed for dt by prepare() (or enqueue_coef)
     const SweepCfg& c = override_cfg ? *override_cfg : g->cfg[d];
     SweepParams<T> P;
     int rc = fill_sweep_params<T>(g, d, in, out, rhs_mode, c, &P);
     if (rc) return rc;
+    if (out2) {
+        if (P.so_t1 != 1) return asd_fail(ASD_EUNSUPPORTED, "a second output needs a transposed-output sweep");
+        P.out2 = (T*)out2;
+    }
     if ((rhs_mode & SWEEP_SOURCE) && g->src) {
         if (sweep_geom(g->d.ndim, d).Lin != 0)
             return asd_fail(ASD_EUNSUPPORTED, "the source enters a sweep that reads the natural layout");
@@ -442,9 +446,9 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
 }
 
 int enqueue_sweep(asd_grid g, int d, double dt, const void* in, void* out, int rhs_mode, const ReduceParams& red,
-                  const SweepCfg* cfg, int* nblocks_out) {
-    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out)
-                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out);
+                  const SweepCfg* cfg, int* nblocks_out, void* out2) {
+    return g->es == 8 ? enqueue_sweep_t<double>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out, out2)
+                      : enqueue_sweep_t<float>(g, d, dt, in, out, rhs_mode, red, cfg, nblocks_out, out2);
 }
 
 // 2-D layout change A = [y][x] -> B = [x][y] (a_to_b) or back.

@@ -552,6 +552,8 @@ __device__ __forceinline__ void cell_solve_store(const SweepParams<T>& P, const 
         const int pstep = nthreads >> lpw_log2;
         T* ob = P.out + (l1_0 + l2 * P.so_t2);
         const bool qq_ok = l1_0 + qq < P.nt1;
+        // second copy in the input layout: lpw runs of consecutive cells per store
+        T* ob2 = P.out2 && qq_ok ? P.out2 + (unsigned)((l1_0 + qq) * P.si_t1 + l2 * P.si_t2) : nullptr;
         // pstep == spl: consecutive positions of a thread are ostep1 apart in LDS
         const unsigned char* rq = ctx.buf + qq * Lo.row1 + UPOS + cell_off1(p0, ES, pad);
         const unsigned o0 = (unsigned)(p0 * P.so_n + qq);
@@ -559,7 +561,11 @@ __device__ __forceinline__ void cell_solve_store(const SweepParams<T>& P, const 
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
             if (tid + it * nthreads >= ncell) break;
-            if (qq_ok) ob[o0 + it * ostep] = *reinterpret_cast<const T*>(rq + it * ostep1);
+            if (qq_ok) {
+                const T x = *reinterpret_cast<const T*>(rq + it * ostep1);
+                ob[o0 + it * ostep] = x;
+                if (ob2) ob2[p0 + it * pstep] = x;
+            }
         }
     } else if (line_ok) {
         // line-contiguous output

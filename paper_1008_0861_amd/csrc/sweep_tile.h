@@ -608,6 +608,8 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
         const int lq = l1_0 + qq;
         const bool qq_ok = lq < P.nt1;
         T* ob = P.out + (l1_0 + l2 * P.so_t2);
+        // second copy in the input layout: lpw runs of consecutive cells per store
+        T* ob2 = P.out2 && qq_ok ? P.out2 + (unsigned)(lq * P.si_t1 + l2 * P.si_t2) : nullptr;
         const unsigned char* rq = ctx.buf + qq * Lo.row1;
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
@@ -618,6 +620,7 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
                 lds_get_pair<T>(rq + slot_off(p, ES, pad), unused, d);
                 const T x = uu[it] + d;
                 ob[(unsigned)(p * P.so_n + qq)] = x;
+                if (ob2) ob2[p] = x;
                 if (reduce) {
                     const T rv = red_in ? uu[it] : x;
                     lsum += (double)rv;

@@ -113,3 +113,23 @@ def test_both_bodies_on_one_problem():
     b = GpuProblem(p, "f64", variant=CELL).run()
     assert max_rel_err(a, ref) <= TOL["f64"] and max_rel_err(b, ref) <= TOL["f64"]
     assert max_rel_err(a, b) <= 2 * TOL["f64"]
+
+
+@pytest.mark.parametrize("bc", ["periodic", "insulating"])
+def test_cell_body_adjoint_fp64(bc):
+    """The adjoint with every sweep on the cell-slot body (its recomputation
+    stores T* in both layouts through that body's second store) against
+    the reverse-mode reference."""
+    from oracle import torch_ref
+    from tests.test_gpu_adjoint import AdjGrid, _problem, _rel
+    b, T0, chi, h, dt = _problem((40, 56), 3, bc)
+    lam = np.random.default_rng(4).standard_normal(T0.shape)
+    gT_ref, gC_ref, _ = torch_ref.reverse_gradients(T0, b, chi, h, dt, 7, lam, periodic=bc == "periodic",
+                                                    chi_par=float(chi.max()))
+    ag = AdjGrid(b, chi, h, "f64", bc=bc)
+    for axis in range(2):
+        c = ag.g.sweep_config(axis)
+        ag.g.set_sweep_config(axis, c["wpl"], c["lpw"], 1, CELL)
+    gT, gC = ag.adjoint(T0, lam, dt, 7, 3)
+    assert _rel(gT, gT_ref) <= 1e-10
+    assert _rel(gC, gC_ref) <= 1e-10
