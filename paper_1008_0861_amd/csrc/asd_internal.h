@@ -164,6 +164,7 @@ enum : int {
     SWEEP_SOLVE_ONLY = 1,   // right-hand side = U (no transverse term)
     SWEEP_KEEP_LAYOUT = 2,  // output in the input layout
     SWEEP_SOURCE = 4,       // dt Q joins the right-hand side (input in the natural layout)
+    SWEEP_REDUCE_INPUT = 8, // the reduction (red) sums the input state instead of the output
 };
 
 template <typename T>

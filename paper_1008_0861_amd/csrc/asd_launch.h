@@ -16,7 +16,6 @@ namespace asd {
 // steps' partials, slot_stride doubles apart): block b folds reduction b.
 struct ReduceParams {
     double* partials;    // 3 doubles per block; nullptr disables the reduction
-    int of_input;        // reduce the sweep's input state (each cell once) instead of its output
 };
 struct FoldParams {
     const double* partials;  // nullptr: nothing to fold
@@ -36,7 +35,6 @@ template <typename T>
 struct SweepParams {
     const T* U;       // input state
     T* out;           // output state (never aliases U)
-    T* out2;          // nullable: the output written a second time in U's layout (transposed-output sweeps)
     const T* alpha;   // normal coefficient of the face after each cell, in U's layout
     const T* beta1;   // transverse coefficient (axis t1) of that face
     const T* beta2;   // transverse coefficient (axis t2), 3-D only
@@ -62,9 +60,13 @@ struct SweepParams {
     int io_log2;      // log2(io): staging and stores use 64*wpl*io threads per line (io = 1 or 2)
     int lpw_log2;     // log2(lpw)
     int rhs_mode;     // 0: full sweep; 1: solve only (right-hand side = U)
-    int variant;      // SWEEP_FACE_SLOTS (sweep_tile.h) or SWEEP_CELL_SLOTS (sweep_cell.h); host side only
+    int red_in;       // the block partials reduce the input state (each cell once) instead of the output
     TileLayout lds;   // LDS layout of a tile (tile_layout / tile_layout_cell)
     ReduceParams red;
+    // nullable: the output written a second time in U's layout (transposed-
+    // output sweeps, EXT instantiations).  Last, so that the fields before it
+    // keep the offsets the kernels' first scalar loads are laid out for.
+    T* out2;
 };
 
 // Face coefficients of the sweep along axis d, written in that sweep's
@@ -117,7 +119,7 @@ struct SweepCellBounds {
 };
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block,
-                        size_t lds, hipStream_t st);
+                        size_t lds, hipStream_t st, int variant);
 hipError_t sweep_set_lds_limits(int bytes);
 
 // ---------------------------------------------------------------- explicit

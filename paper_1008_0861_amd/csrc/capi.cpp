@@ -407,7 +407,6 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.io_log2 = ilog2(c.io);
     P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode & SWEEP_SOLVE_ONLY;
-    P.variant = c.variant;
     P.lds = sweep_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant);
     if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
     *Pout = P;
@@ -435,13 +434,15 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
         P.dtq = (T)dt;
     }
     P.red = red;
+    P.red_in = (rhs_mode & SWEEP_REDUCE_INPUT) != 0;
     const int nb1 = (P.nt1 + c.lpw - 1) / c.lpw;
     const int64_t nblocks = (int64_t)nb1 * P.nt2;
     if (nblocks_out) *nblocks_out = (int)nblocks;
     if (red.partials && nblocks > g->max_blocks)
         return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
     const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant);
-    return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st),
+    return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st,
+                                     c.variant),
                      "sweep launch");
 }
 
@@ -554,10 +555,8 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
             const int src = i == 0 ? SWEEP_SOURCE : 0;  // dt Q joins the first sweep
             ReduceParams red = no_reduce();
             if (produce) red.partials = ring_slot(g, used);
-            if (fuse_e0 && s == 0 && i == 0) {
-                red.partials = e0_in_ring ? ring_slot(g, 0) : ring_slot(g, g->ring_slots);
-                red.of_input = 1;
-            }
+            const bool red_in = fuse_e0 && s == 0 && i == 0;
+            if (red_in) red.partials = e0_in_ring ? ring_slot(g, 0) : ring_slot(g, g->ring_slots);
             int nb = 0;
             void* out;
             if (reverse) {
@@ -572,8 +571,8 @@ int enqueue_si_loop(asd_grid g, double dt, int nsteps, const StepOut& outs) {
                 }
             } else if (!four) {
                 out = (d == nd - 1) ? g->T : g->tmp[d];
-                rc = sweep(d, in, out, src, red, &nb);
-                if (red.of_input && !e0_in_ring) {
+                rc = sweep(d, in, out, src | (red_in ? SWEEP_REDUCE_INPUT : 0), red, &nb);
+                if (red_in && !e0_in_ring) {
                     f0 = make_fold(g, red.partials, nb, 1, outs, 0);
                     f0_pending = true;
                 }

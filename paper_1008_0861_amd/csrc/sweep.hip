@@ -93,12 +93,13 @@ __global__ void __launch_bounds__((SweepCellBounds<T, MMAX>::max_threads))
 // walls or a source take a third that also reads those.
 template <typename T, int NDIM>
 static hipError_t launch_sweep_dim(const SweepParams<T>& P, int mmax, dim3 grid, dim3 block, size_t lds,
-                                   hipStream_t st) {
-    const bool ext = P.dirichlet || P.Q;
-    const bool cellv = P.variant == SWEEP_CELL_SLOTS;
+                                   hipStream_t st, int variant) {
+    // T = 0 walls, a source or a second output take the EXT instantiation
+    const bool ext = P.dirichlet || P.Q || P.out2;
+    const bool cellv = variant == SWEEP_CELL_SLOTS;
     if (P.lpw != (1 << P.lpw_log2) || 64 * P.wpl != (1 << P.spl_log2) || P.spl_log2 > 15 || P.lpw_log2 > 15 ||
         P.lds.pad < 0 || P.lds.pad > 31 || P.io_log2 < 0 || P.io_log2 > 1 || (cellv && P.io_log2 != 0) ||
-        (P.variant != SWEEP_FACE_SLOTS && !cellv) || (int)block.x != (P.lpw << (P.spl_log2 + P.io_log2)) ||
+        (variant != SWEEP_FACE_SLOTS && !cellv) || (int)block.x != (P.lpw << (P.spl_log2 + P.io_log2)) ||
         (int)block.x > (cellv ? sweep_cell_max_threads((int)sizeof(T), mmax) : sweep_max_threads((int)sizeof(T), mmax)))
         return hipErrorInvalidValue;
     // the kernel's leading (preloaded) arguments; P.rhs_mode holds 0 or SWEEP_SOLVE_ONLY
@@ -169,13 +170,13 @@ hipError_t sweep_set_lds_limits(int bytes) {
 
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T>& P, int ndim, int mmax, dim3 grid, dim3 block, size_t lds,
-                        hipStream_t st) {
-    if (ndim == 2) return launch_sweep_dim<T, 2>(P, mmax, grid, block, lds, st);
-    return launch_sweep_dim<T, 3>(P, mmax, grid, block, lds, st);
+                        hipStream_t st, int variant) {
+    if (ndim == 2) return launch_sweep_dim<T, 2>(P, mmax, grid, block, lds, st, variant);
+    return launch_sweep_dim<T, 3>(P, mmax, grid, block, lds, st, variant);
 }
 
-template hipError_t launch_sweep<float>(const SweepParams<float>&, int, int, dim3, dim3, size_t, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepParams<float>&, int, int, dim3, dim3, size_t, hipStream_t, int);
 template hipError_t launch_sweep<double>(const SweepParams<double>&, int, int, dim3, dim3, size_t,
-                                         hipStream_t);
+                                         hipStream_t, int);
 
 }  // namespace asd

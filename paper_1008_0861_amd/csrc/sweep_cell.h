@@ -48,9 +48,9 @@
 // dominant M-matrices: no pivoting anywhere.
 //
 // LIMC: the limiter as a compile-time constant (straight-line code), or -1
-// to read it from the parameters.  EXT: compile in T = 0 walls and the
-// source term (read from the parameters); without it that code is absent
-// and the host never passes either.
+// to read it from the parameters.  EXT: compile in T = 0 walls, the source
+// term and the second output copy (read from the parameters); without it
+// that code is absent and the host never passes any of them.
 #pragma once
 
 #include "asd_device.h"
@@ -518,7 +518,7 @@ __device__ __forceinline__ void cell_solve_store(const SweepParams<T>& P, const 
     // the lane's own slots (the U positions are never part of an exchange)
     // (the FP64 sum, min and max of the written values, or of the input
     // state's: U of the slots, the source being excluded by the host)
-    const bool red_in = P.red.of_input != 0;
+    const bool red_in = P.red_in != 0;
     lsum = 0.0;
     lmin = T(__builtin_huge_val());
     lmax = T(-__builtin_huge_val());
@@ -552,8 +552,9 @@ __device__ __forceinline__ void cell_solve_store(const SweepParams<T>& P, const 
         const int pstep = nthreads >> lpw_log2;
         T* ob = P.out + (l1_0 + l2 * P.so_t2);
         const bool qq_ok = l1_0 + qq < P.nt1;
-        // second copy in the input layout: lpw runs of consecutive cells per store
-        T* ob2 = P.out2 && qq_ok ? P.out2 + (unsigned)((l1_0 + qq) * P.si_t1 + l2 * P.si_t2) : nullptr;
+        // second copy in the input layout (EXT instantiations only): lpw runs
+        // of consecutive cells per store
+        T* ob2 = EXT && P.out2 && qq_ok ? P.out2 + (unsigned)((l1_0 + qq) * P.si_t1 + l2 * P.si_t2) : nullptr;
         // pstep == spl: consecutive positions of a thread are ostep1 apart in LDS
         const unsigned char* rq = ctx.buf + qq * Lo.row1 + UPOS + cell_off1(p0, ES, pad);
         const unsigned o0 = (unsigned)(p0 * P.so_n + qq);

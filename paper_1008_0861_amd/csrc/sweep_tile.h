@@ -49,9 +49,9 @@
 // pivoting anywhere.
 //
 // LIMC: the limiter as a compile-time constant (straight-line code), or -1
-// to read it from the parameters.  EXT: compile in T = 0 walls and the
-// source term (read from the parameters); without it that code is absent
-// and the host never passes either.
+// to read it from the parameters.  EXT: compile in T = 0 walls, the source
+// term and the second output copy (read from the parameters); without it
+// that code is absent and the host never passes any of them.
 #pragma once
 
 #include "asd_device.h"
@@ -594,7 +594,7 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
 
     // ---------------- phase 3: out = U + delta, stored
     const bool reduce = P.red.partials != nullptr;
-    const bool red_in = P.red.of_input != 0;  // the input's cells instead (each stored cell once)
+    const bool red_in = P.red_in != 0;  // the input's cells instead (each stored cell once)
     lsum = 0.0;
     lmin = T(__builtin_huge_val());
     lmax = T(-__builtin_huge_val());
@@ -608,8 +608,9 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
         const int lq = l1_0 + qq;
         const bool qq_ok = lq < P.nt1;
         T* ob = P.out + (l1_0 + l2 * P.so_t2);
-        // second copy in the input layout: lpw runs of consecutive cells per store
-        T* ob2 = P.out2 && qq_ok ? P.out2 + (unsigned)(lq * P.si_t1 + l2 * P.si_t2) : nullptr;
+        // second copy in the input layout (EXT instantiations only): lpw runs
+        // of consecutive cells per store
+        T* ob2 = EXT && P.out2 && qq_ok ? P.out2 + (unsigned)(lq * P.si_t1 + l2 * P.si_t2) : nullptr;
         const unsigned char* rq = ctx.buf + qq * Lo.row1;
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
