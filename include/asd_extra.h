@@ -76,8 +76,9 @@ int asd_batch_set_block(asd_batch b, int32_t nthreads);
 int asd_batch_set_variant(asd_batch b, int32_t variant);
 int asd_batch_get_variant(asd_batch b, int32_t *variant);
 
-/* Autotuner: time modes 0 and 2 at every admissible work-group size and
- * tile body on probe_steps steps (this advances the problems' T), keep the
+/* Autotuner: time modes 0 and 2 at every admissible work-group size,
+ * per-lane capacity (4, 8 or 16 cells) and tile body on probe_steps steps
+ * (this advances the problems' T), keep the
  * fastest for mode -1 and report it (nullable outputs; the body through
  * asd_batch_get_variant).  Synchronises the stream. */
 int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t *best_mode, int32_t *best_threads);

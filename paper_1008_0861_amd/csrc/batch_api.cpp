@@ -127,11 +127,13 @@ static bool batch_line_cfg(int es, int n, int nthreads, int mmax, int variant, S
     return false;
 }
 
-// Choose (mmax, nthreads) for all problems on one tile body; fills b->cfg
-// and b->lds.
-static int batch_shape(asd_batch b, int nthreads, int variant) {
+// Choose the per-lane capacity (the smallest from mmax_from up that fits
+// every problem) for a workgroup size and tile body; fills b->cfg and
+// b->lds.  A larger capacity gives long lines fewer waves each.
+static int batch_shape(asd_batch b, int nthreads, int variant, int mmax_from = 4) {
     const int es = b->d0.dtype == ASD_F64 ? 8 : 4;
     for (int mmax : {4, 8, 16}) {
+        if (mmax < mmax_from) continue;
         if (nthreads > sweep_threads_cap(es, mmax, variant)) continue;
         std::vector<SweepCfg> cfg(2 * b->nprob);
         size_t lds = 0;
@@ -482,8 +484,8 @@ extern "C" int asd_batch_status(asd_batch b, uint32_t* flags, double* stats) {
 }
 
 // Time the persistent and grouped schedules at every admissible workgroup
-// size and tile body on `probe_steps` steps each and keep the fastest as
-// mode -1.  The problems' T are advanced by the probes; callers reset them
+// size, per-lane capacity and tile body on `probe_steps` steps each and keep
+// the fastest as mode -1.  The problems' T are advanced by the probes; callers reset them
 // afterwards.
 extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mode, int32_t* best_threads) {
     if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
@@ -492,12 +494,13 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return asd_fail(ASD_EHIP, "event create");
     float best = 1e30f;
-    int bm = 0, bt = b->nthreads, bv = b->variant;
+    int bm = 0, bt = b->nthreads, bv = b->variant, bx = b->mmax;
     int rc = ASD_OK;
     for (int variant : {(int)SWEEP_FACE_SLOTS, (int)SWEEP_CELL_SLOTS})
+    for (int mx : {4, 8, 16})
     for (int nt : {256, 512, 1024}) {
         if (rc) break;
-        if (batch_shape(b, nt, variant) != ASD_OK) continue;
+        if (batch_shape(b, nt, variant, mx) != ASD_OK || b->mmax != mx) continue;
         for (int mode : {0, 2}) {
             rc = asd_batch_step(b, probe_steps, mode);  // warm-up (tables, coefficients, graph capture)
             if (rc) break;
@@ -515,6 +518,7 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
                 bm = mode;
                 bt = nt;
                 bv = variant;
+                bx = mx;
             }
         }
         if (rc) break;
@@ -522,7 +526,7 @@ extern "C" int asd_batch_tune(asd_batch b, int32_t probe_steps, int32_t* best_mo
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    rc = batch_shape(b, bt, bv);
+    rc = batch_shape(b, bt, bv, bx);
     if (rc) return rc;
     b->mode = bm;
     if (best_mode) *best_mode = bm;
