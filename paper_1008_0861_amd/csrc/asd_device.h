@@ -226,6 +226,10 @@ template <typename T>
 __device__ __forceinline__ T ldg_off(const T* base, unsigned byte_off) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(base) + byte_off);
 }
+template <typename T>
+__device__ __forceinline__ void stg_off(T* base, unsigned byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + byte_off) = v;
+}
 
 // first three elements of a slot only (the fourth is left untouched)
 template <typename T>

@@ -564,7 +564,12 @@ __device__ __forceinline__ void cell_solve_store(const SweepParams<T>& P, const 
             if (tid + it * nthreads >= ncell) break;
             if (qq_ok) {
                 const T x = *reinterpret_cast<const T*>(rq + it * ostep1);
-                ob[o0 + it * ostep] = x;
+                // 2-D: a 32-bit byte offset from the uniform base (a 2-D field
+                // stays below 4 GiB); 3-D: a 32-bit element index
+                if (NDIM == 2)
+                    stg_off(ob, (o0 + it * ostep) * (unsigned)ES, x);
+                else
+                    ob[o0 + it * ostep] = x;
                 if (ob2) ob2[p0 + it * pstep] = x;
             }
         }

@@ -620,7 +620,12 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
                 T unused, d;
                 lds_get_pair<T>(rq + slot_off(p, ES, pad), unused, d);
                 const T x = uu[it] + d;
-                ob[(unsigned)(p * P.so_n + qq)] = x;
+                // 2-D: a 32-bit byte offset from the uniform base (a 2-D field
+                // stays below 4 GiB); 3-D: a 32-bit element index
+                if (NDIM == 2)
+                    stg_off(ob, (unsigned)(p * P.so_n + qq) * (unsigned)ES, x);
+                else
+                    ob[(unsigned)(p * P.so_n + qq)] = x;
                 if (ob2) ob2[p] = x;
                 if (reduce) {
                     const T rv = red_in ? uu[it] : x;
@@ -666,18 +671,21 @@ __device__ __forceinline__ void load_store_u(const SweepParams<T>& P, const Tile
         const int pstep = (int)blockDim.x >> P.lpw_log2;
         const int lq = c.l1_0 + qq;
         const bool qq_ok = lq < P.nt1;
-        const T* uq = P.U + (qq_ok ? (unsigned)(lq * P.si_t1 + c.l2 * P.si_t2) : 0u);
+        // the tile's first line as a uniform base, the lane's line and cell
+        // as a 32-bit byte offset (the tile's lines span a few MB at most)
+        const T* tileU = P.U + (unsigned)(c.l1_0 * P.si_t1 + c.l2 * P.si_t2);
+        const unsigned ob0 = qq_ok ? (unsigned)(qq * P.si_t1) * (unsigned)sizeof(T) : 0u;
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
             const int p = p0 + it * pstep;
-            uu[it] = (qq_ok && p < n) ? uq[p] : T(0);
+            uu[it] = (qq_ok && p < n) ? ldg_off(tileU, ob0 + (unsigned)p * (unsigned)sizeof(T)) : T(0);
         }
     } else {
         const T* lineU = P.U + c.base;
 #pragma unroll
         for (int it = 0; it < MMAX; ++it) {
             const int p = c.k + (it << (P.spl_log2 + P.io_log2));
-            uu[it] = (c.line_ok && p < n) ? lineU[p] : T(0);
+            uu[it] = (c.line_ok && p < n) ? ldg_off(lineU, (unsigned)p * (unsigned)sizeof(T)) : T(0);
         }
     }
 }
