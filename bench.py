@@ -362,10 +362,12 @@ def explicit_3d(stream, torch, asd, nsteps=50):
 
 def adjoint_1024(stream, torch, asd, n=1024, nsteps=50, ckpt_every=10):
     """The adjoint workload: 1024^2 FP32, per-cell chi, 50 semi-implicit
-    steps with checkpoints every 10, sweep launch shapes autotuned.  Times
-    the forward steps and the backward pass (checkpointed recomputation plus
-    the reverse sweeps, gradients with respect to T0 and chi) separately,
-    medians of 3."""
+    steps with checkpoints every 10, sweep launch shapes autotuned.  Times,
+    medians of 3: the forward steps alone (captured loop); the forward that
+    stores the checkpoints (asd_adjoint_forward); the backward from those
+    checkpoints (recomputation plus the reverse sweeps, gradients with
+    respect to T0 and chi; asd_adjoint_step_stored); and the backward that
+    takes its own checkpoints from T0 (asd_adjoint_step)."""
     import numpy as np
     import synth
 
@@ -382,23 +384,39 @@ def adjoint_1024(stream, torch, asd, n=1024, nsteps=50, ckpt_every=10):
         g.tune(p.dt, reps=10)  # launch shapes of the sweeps (forward and reverse share them)
         T.copy_(T0)
         lam = torch.from_numpy(np.random.default_rng(7).standard_normal(p.T0.shape)).float().cuda()
+        ws = g.adjoint_workspace(nsteps, ckpt_every)
 
     def fwd():
         T.copy_(T0)
         g.step_semi_implicit(p.dt, nsteps)
 
-    def bwd():
+    def fwd_ckpt():
+        T.copy_(T0)
+        g.adjoint_forward(p.dt, nsteps, ckpt_every, ws)
+
+    def bwd_stored():
+        g.adjoint_stored(p.dt, nsteps, ckpt_every, ws, lam)
+
+    def bwd_from_T0():
         g.adjoint(p.dt, nsteps, ckpt_every, T0, lam)
 
     with torch.cuda.stream(stream):
         fwd()
-        bwd()
+        fwd_ckpt()
+        bwd_stored()
+        bwd_from_T0()
         tf = sorted(timed(fwd, stream, torch) for _ in range(3))[1]
-        tb = sorted(timed(bwd, stream, torch) for _ in range(3))[1]
+        tfc = sorted(timed(fwd_ckpt, stream, torch) for _ in range(3))[1]
+        tb = sorted(timed(bwd_stored, stream, torch) for _ in range(3))[1]
+        tb0 = sorted(timed(bwd_from_T0, stream, torch) for _ in range(3))[1]
     N = n * n
+    # the differentiable map runs fwd_ckpt then bwd_stored; the ratio is of
+    # those two, and the backward that takes its own checkpoints (from T0)
+    # is reported beside it
     return {"cells": N, "steps": nsteps, "ckpt_every": ckpt_every, "forward_ms": round(tf, 3),
-            "backward_ms": round(tb, 3), "backward_over_forward": round(tb / tf, 2),
-            "backward_Gcells": round(N * nsteps / (tb * 1e-3) / 1e9, 3)}
+            "forward_ckpt_ms": round(tfc, 3), "backward_ms": round(tb, 3),
+            "backward_over_forward": round(tb / tfc, 2), "backward_over_plain_forward": round(tb / tf, 2),
+            "backward_from_T0_ms": round(tb0, 3), "backward_Gcells": round(N * nsteps / (tb * 1e-3) / 1e9, 3)}
 
 
 def ring512(stream, torch, asd):

@@ -172,6 +172,24 @@ int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, 
                      const void *dev_lambda_final, void *dev_grad_T0, void *dev_grad_chi,
                      void *dev_adj_ws, size_t adj_ws_bytes);
 
+/* The same derivative split into its forward and reverse halves, for
+ * callers that run the forward steps anyway (a differentiable step map):
+ * asd_adjoint_forward advances the grid's T in place by nsteps semi-implicit
+ * steps (the states of asd_step_semi_implicit, without energy output) and
+ * stores the states at steps 0, k, 2k, ... (k = ckpt_every) in the first
+ * ceil(nsteps/k) fields of dev_adj_ws (asd_adjoint_workspace_bytes bytes).
+ * asd_adjoint_step_stored then computes what asd_adjoint_step computes from
+ * those stored states instead of from dev_T0, without the checkpoint pass;
+ * it must be given the same grid, dt, nsteps and ckpt_every, and the grid's
+ * b and chi fields must not change in between.  It leaves the checkpoints in
+ * place, so several reverse passes (several lambda_N) can follow one forward.
+ * Errors as for asd_adjoint_step. */
+int asd_adjoint_forward(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, void *dev_adj_ws,
+                        size_t adj_ws_bytes);
+int asd_adjoint_step_stored(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every,
+                            const void *dev_lambda_final, void *dev_grad_T0, void *dev_grad_chi,
+                            void *dev_adj_ws, size_t adj_ws_bytes);
+
 /* Synchronise the grid's stream and report status flags (ASD_STATUS_*)
  * from an FP64 reduction of the current T; stats (nullable, 3 doubles)
  * receives {sum T dV, min T, max T}. */

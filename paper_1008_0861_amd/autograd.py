@@ -1,6 +1,8 @@
 """torch.autograd.Function over the C ABI: nsteps semi-implicit steps as a
-differentiable map (T0, chi) -> T_N, with the hand-written adjoint of
-asd_adjoint_step (checkpointed recomputation) as its backward."""
+differentiable map (T0, chi) -> T_N.  The forward runs asd_adjoint_forward
+(the steps, storing a checkpoint every ckpt_every steps); the backward is the
+hand-written adjoint asd_adjoint_step_stored, which recomputes each segment
+from its stored checkpoint."""
 import torch
 
 from . import binding
@@ -23,22 +25,24 @@ class SemiImplicitSteps(torch.autograd.Function):
             grid.set_field("chi", chi_c)
             T = T0.detach().clone()
             grid.set_field("T", T)
-            grid.step_semi_implicit(dt, nsteps)
+            ws = grid.adjoint_forward(dt, nsteps, ckpt_every)
         cur.wait_stream(grid.stream)
-        ctx.save_for_backward(T0.detach(), chi_c)
+        ctx.save_for_backward(chi_c)
+        ctx.ws = ws  # the checkpoints (states at steps 0, k, 2k, ...)
         ctx.grid, ctx.dt, ctx.nsteps, ctx.k = grid, dt, nsteps, ckpt_every
         return T
 
     @staticmethod
     def backward(ctx, gT):
-        T0, chi = ctx.saved_tensors
+        (chi,) = ctx.saved_tensors
         grid = ctx.grid
         cur = torch.cuda.current_stream()
         grid.stream.wait_stream(cur)
         with torch.cuda.stream(grid.stream):
             grid.set_field("chi", chi)
-            gT0, gchi = grid.adjoint(ctx.dt, ctx.nsteps, ctx.k, T0, gT.contiguous(), grad_chi=True)
+            gT0, gchi = grid.adjoint_stored(ctx.dt, ctx.nsteps, ctx.k, ctx.ws, gT.contiguous(), grad_chi=True)
         cur.wait_stream(grid.stream)
+        ctx.ws = None
         return gT0, gchi, None, None, None, None
 
 

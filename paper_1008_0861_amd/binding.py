@@ -33,7 +33,7 @@ STATUS_NONFINITE, STATUS_NEG_T, STATUS_ENERGY_DRIFT = 1, 2, 4
 EXPORTED = [
     "asd_last_error", "asd_workspace_bytes", "asd_init_grid", "asd_set_field",
     "asd_step_semi_implicit", "asd_step_explicit_limited", "asd_step_series", "asd_adjoint_workspace_bytes",
-    "asd_adjoint_step", "asd_status", "asd_destroy",
+    "asd_adjoint_step", "asd_adjoint_forward", "asd_adjoint_step_stored", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
     "asd_batch_destroy", "asd_batch_set_block", "asd_batch_set_variant", "asd_batch_get_variant", "asd_batch_tune",
     "asd_batch_step_energy", "asd_batch_status",
@@ -92,6 +92,8 @@ def lib():
             "asd_step_series": (ctypes.c_int, [vp, i32, dbl, i32, vp]),
             "asd_adjoint_workspace_bytes": (ctypes.c_int, [vp, i32, i32, P(sz)]),
             "asd_adjoint_step": (ctypes.c_int, [vp, dbl, i32, i32, vp, vp, vp, vp, vp, sz]),
+            "asd_adjoint_forward": (ctypes.c_int, [vp, dbl, i32, i32, vp, sz]),
+            "asd_adjoint_step_stored": (ctypes.c_int, [vp, dbl, i32, i32, vp, vp, vp, vp, sz]),
             "asd_status": (ctypes.c_int, [vp, P(ctypes.c_uint32), P(dbl)]),
             "asd_destroy": (ctypes.c_int, [vp]),
             "asd_batch_workspace_bytes": (ctypes.c_int, [P(Desc), i32, P(sz)]),
@@ -287,6 +289,32 @@ class Grid:
                                      ctypes.c_void_p(gC.data_ptr()) if gC is not None else None,
                                      ctypes.c_void_p(ws.data_ptr()), n.value))
         self._adj_ws = ws  # keep alive until the stream has used it
+        return gT, gC
+
+    def adjoint_workspace(self, nsteps, ckpt_every):
+        """A device workspace of asd_adjoint_workspace_bytes bytes."""
+        n = ctypes.c_size_t()
+        check(lib().asd_adjoint_workspace_bytes(self.handle, int(nsteps), int(ckpt_every), ctypes.byref(n)))
+        return torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+
+    def adjoint_forward(self, dt, nsteps, ckpt_every, ws=None):
+        """nsteps semi-implicit steps of T in place, storing the reverse
+        pass's checkpoints in ws (allocated if None); returns ws."""
+        if ws is None:
+            ws = self.adjoint_workspace(nsteps, ckpt_every)
+        check(lib().asd_adjoint_forward(self.handle, float(dt), int(nsteps), int(ckpt_every),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return ws
+
+    def adjoint_stored(self, dt, nsteps, ckpt_every, ws, lam, grad_chi=True):
+        """dL/dT0 (and dL/dchi) from the checkpoints adjoint_forward left in ws."""
+        self._check_tensor(lam)
+        gT = torch.empty_like(lam)
+        gC = torch.empty_like(lam) if grad_chi else None
+        check(lib().asd_adjoint_step_stored(self.handle, float(dt), int(nsteps), int(ckpt_every),
+                                            ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(gT.data_ptr()),
+                                            ctypes.c_void_p(gC.data_ptr()) if gC is not None else None,
+                                            ctypes.c_void_p(ws.data_ptr()), ws.numel()))
         return gT, gC
 
     def sweep_config(self, axis):

@@ -86,9 +86,31 @@ static int stencil(asd_grid g, int d, double dt, const void* mu, const void* U, 
     return ASD_OK;
 }
 
+// The forward steps of asd_adjoint_forward: the grid's T advanced in place
+// (x sweep T -> tmp0, y sweep tmp0 -> T, as in the stepping loop), with the
+// states at steps 0, k, 2k, ... written to the workspace's checkpoint
+// fields (the y sweep of a checkpoint step writes there directly and the
+// next step reads it there).  The last step always ends in T.
+static int forward_ckpt(asd_grid g, double dt, int nsteps, int k, char* ws) {
+    const AdjPlan pl = adj_plan(g, nsteps, k);
+    auto ck = [&](int c) { return (void*)(ws + (size_t)c * pl.field); };
+    int rc = enqueue_copy(g, g->T, ck(0));
+    const void* in = g->T;
+    for (int s = 0; s < nsteps && rc == ASD_OK; ++s) {
+        rc = enqueue_sweep(g, 0, dt, in, g->tmp[0], 0, no_reduce(), nullptr, nullptr);
+        if (rc) break;
+        const int c = (s + 1) / k;
+        void* out = ((s + 1) % k == 0 && c < pl.nck) ? ck(c) : g->T;
+        rc = enqueue_sweep(g, 1, dt, g->tmp[0], out, 0, no_reduce(), nullptr, nullptr);
+        in = out;
+    }
+    return rc;
+}
+
+// stored: the checkpoints are already in ws (asd_adjoint_forward); T0 unused
 template <typename T>
 static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, const void* lamN, void* gT0,
-                     void* gchi, char* ws) {
+                     void* gchi, char* ws, bool stored) {
     const AdjPlan pl = adj_plan(g, nsteps, k);
     char* cur = ws;
     auto take = [&]() {
@@ -111,9 +133,9 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
     void* mu = take();
     int rc;
     // forward pass: checkpoints at steps 0, k, 2k, ...
-    rc = enqueue_copy(g, T0, ck[0]);
+    if (!stored) rc = enqueue_copy(g, T0, ck[0]);
     if (rc) return rc;
-    for (int c = 1; c < pl.nck; ++c) {
+    for (int c = 1; c < pl.nck && !stored; ++c) {
         const void* in = ck[c - 1];
         for (int i = 0; i < k; ++i) {
             void* out = (i == k - 1) ? ck[c] : S[1];
@@ -170,31 +192,56 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
     return enqueue_permute_2d(g, lamB, gT0, false);
 }
 
-extern "C" int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, const void* dev_T0,
-                                const void* dev_lambda_final, void* dev_grad_T0, void* dev_grad_chi, void* dev_adj_ws,
-                                size_t adj_ws_bytes) {
-    int rc = adj_check(g, nsteps, ckpt_every);
+// Checks shared by the three adjoint entry points; on success the grid's
+// coefficients are prepared for dt.
+static int adj_validate(asd_grid g, double dt, int nsteps, int k, bool grad_chi, const void* ws, size_t ws_bytes) {
+    int rc = adj_check(g, nsteps, k);
     if (rc) return rc;
     if (!(std::isfinite(dt) && dt > 0.0)) return asd_fail(ASD_EINVAL, "dt must be finite and > 0");
-    if (!dev_T0 || !dev_lambda_final || !dev_grad_T0) return asd_fail(ASD_EINVAL, "NULL state pointer");
-    if (dev_grad_chi && !(g->d.flags & ASD_FLAG_PER_CELL_CHI))
+    if (grad_chi && !(g->d.flags & ASD_FLAG_PER_CELL_CHI))
         return asd_fail(ASD_EINVAL, "grad_chi needs ASD_FLAG_PER_CELL_CHI");
     if (g->d.flags & (ASD_FLAG_FOUR_STEP | ASD_FLAG_REVERSE_ORDER))
         return asd_fail(ASD_EUNSUPPORTED, "the adjoint is of the 2-step scheme in the order x, y");
     if (g->d.chi_exp != 0.0) return asd_fail(ASD_EUNSUPPORTED, "the adjoint takes a chi that does not depend on T");
     if (g->d.bc == ASD_BC_DIRICHLET || g->src)
         return asd_fail(ASD_EUNSUPPORTED, "the adjoint is for periodic or insulating grids without a source");
-    if (!dev_adj_ws) return asd_fail(ASD_EWORKSPACE, "adjoint workspace is NULL");
-    if ((uintptr_t)dev_adj_ws & 255) return asd_fail(ASD_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
-    const AdjPlan pl = adj_plan(g, nsteps, ckpt_every);
-    if (adj_ws_bytes < pl.total)
-        return asd_fail(ASD_EWORKSPACE, "adjoint workspace too small: %zu < %zu bytes", adj_ws_bytes, pl.total);
+    if (!ws) return asd_fail(ASD_EWORKSPACE, "adjoint workspace is NULL");
+    if ((uintptr_t)ws & 255) return asd_fail(ASD_EWORKSPACE, "adjoint workspace must be 256-byte aligned");
+    const AdjPlan pl = adj_plan(g, nsteps, k);
+    if (ws_bytes < pl.total)
+        return asd_fail(ASD_EWORKSPACE, "adjoint workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
     rc = check_fields(g, false);
     if (rc) return rc;
-    rc = prepare(g, dt);
+    return prepare(g, dt);
+}
+
+extern "C" int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, const void* dev_T0,
+                                const void* dev_lambda_final, void* dev_grad_T0, void* dev_grad_chi, void* dev_adj_ws,
+                                size_t adj_ws_bytes) {
+    if (g && (!dev_T0 || !dev_lambda_final || !dev_grad_T0)) return asd_fail(ASD_EINVAL, "NULL state pointer");
+    int rc = adj_validate(g, dt, nsteps, ckpt_every, dev_grad_chi != nullptr, dev_adj_ws, adj_ws_bytes);
     if (rc) return rc;
     return g->es == 8 ? adjoint_t<double>(g, dt, nsteps, ckpt_every, dev_T0, dev_lambda_final, dev_grad_T0,
-                                          dev_grad_chi, (char*)dev_adj_ws)
+                                          dev_grad_chi, (char*)dev_adj_ws, false)
                       : adjoint_t<float>(g, dt, nsteps, ckpt_every, dev_T0, dev_lambda_final, dev_grad_T0,
-                                         dev_grad_chi, (char*)dev_adj_ws);
+                                         dev_grad_chi, (char*)dev_adj_ws, false);
+}
+
+extern "C" int asd_adjoint_forward(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, void* dev_adj_ws,
+                                   size_t adj_ws_bytes) {
+    int rc = adj_validate(g, dt, nsteps, ckpt_every, false, dev_adj_ws, adj_ws_bytes);
+    if (rc) return rc;
+    return forward_ckpt(g, dt, nsteps, ckpt_every, (char*)dev_adj_ws);
+}
+
+extern "C" int asd_adjoint_step_stored(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every,
+                                       const void* dev_lambda_final, void* dev_grad_T0, void* dev_grad_chi,
+                                       void* dev_adj_ws, size_t adj_ws_bytes) {
+    if (g && (!dev_lambda_final || !dev_grad_T0)) return asd_fail(ASD_EINVAL, "NULL state pointer");
+    int rc = adj_validate(g, dt, nsteps, ckpt_every, dev_grad_chi != nullptr, dev_adj_ws, adj_ws_bytes);
+    if (rc) return rc;
+    return g->es == 8 ? adjoint_t<double>(g, dt, nsteps, ckpt_every, nullptr, dev_lambda_final, dev_grad_T0,
+                                          dev_grad_chi, (char*)dev_adj_ws, true)
+                      : adjoint_t<float>(g, dt, nsteps, ckpt_every, nullptr, dev_lambda_final, dev_grad_T0,
+                                         dev_grad_chi, (char*)dev_adj_ws, true);
 }

@@ -273,3 +273,35 @@ def test_noalloc_validation_before_any_gpu_call(asd):
                                                   None)
     assert rc == -1
     assert asd.noalloc_scratch_bytes() == 64 << 20
+
+
+def test_adjoint_entry_points_validate_before_any_gpu_call(asd):
+    """asd_adjoint_step, asd_adjoint_forward and asd_adjoint_step_stored share
+    one validation: null grid or pointers, bad dt or counts, workspace
+    missing / misaligned / too small, grad_chi without per-cell chi, fields
+    not set; all are refused before the device is touched."""
+    L = asd.lib()
+    h, d, _ = _fake_grid(asd)
+    fake = ctypes.c_void_p(1 << 24)
+    ws_n = ctypes.c_size_t()
+    assert L.asd_adjoint_workspace_bytes(h, 12, 5, ctypes.byref(ws_n)) == 0
+    # 3 checkpoints + 2 x 5 segment states + 4 scratch fields of 64 x 48 FP32
+    assert ws_n.value == (3 + 10 + 4) * ((64 * 48 * 4 + 255) // 256 * 256)
+    ws, n = ctypes.c_void_p(1 << 26), ws_n.value
+    assert L.asd_adjoint_forward(None, 1e-3, 12, 5, ws, n) == -1
+    assert L.asd_adjoint_step_stored(None, 1e-3, 12, 5, fake, fake, None, ws, n) == -1
+    for bad_dt in (0.0, -1.0, math.nan, math.inf):
+        assert L.asd_adjoint_forward(h, bad_dt, 12, 5, ws, n) == -1
+        assert L.asd_adjoint_step_stored(h, bad_dt, 12, 5, fake, fake, None, ws, n) == -1
+    assert L.asd_adjoint_forward(h, 1e-3, -1, 5, ws, n) == -1
+    assert L.asd_adjoint_forward(h, 1e-3, 12, 0, ws, n) == -1
+    assert L.asd_adjoint_step_stored(h, 1e-3, 12, 5, None, fake, None, ws, n) == -1
+    assert L.asd_adjoint_step_stored(h, 1e-3, 12, 5, fake, None, None, ws, n) == -1
+    assert L.asd_adjoint_step_stored(h, 1e-3, 12, 5, fake, fake, fake, ws, n) == -1  # grad_chi, no per-cell chi
+    assert L.asd_adjoint_forward(h, 1e-3, 12, 5, None, n) == -5
+    assert L.asd_adjoint_forward(h, 1e-3, 12, 5, ctypes.c_void_p((1 << 26) + 64), n) == -5
+    assert L.asd_adjoint_forward(h, 1e-3, 12, 5, ws, n - 1) == -5
+    assert L.asd_adjoint_step_stored(h, 1e-3, 12, 5, fake, fake, None, ws, n - 1) == -5
+    assert L.asd_adjoint_forward(h, 1e-3, 12, 5, ws, n) == -4  # T, b not set
+    assert L.asd_adjoint_step_stored(h, 1e-3, 12, 5, fake, fake, None, ws, n) == -4
+    assert L.asd_destroy(h) == 0

@@ -192,3 +192,53 @@ def test_adjoint_1024_fp32_against_central_differences():
         print(f"\n{which}: {32 - skipped} of 32 cells checked, {skipped} on a limiter kink")
         assert skipped <= 8, (which, skipped)
     assert not bad, bad
+
+
+def _stored_vs_recomputed(ag, T0, lams, dt, nsteps, k):
+    """asd_adjoint_forward then asd_adjoint_step_stored (once per lambda, on
+    one set of checkpoints) against asd_step_semi_implicit and
+    asd_adjoint_step; returns the max differences."""
+    with torch.cuda.stream(ag.stream):
+        t0 = torch.from_numpy(T0).to(ag.dt).cuda()
+        T_step = t0.clone()
+        ag.g.set_field("T", T_step)
+        ag.g.step_semi_implicit(dt, nsteps)
+        T_fwd = t0.clone()
+        ag.g.set_field("T", T_fwd)
+        ws = ag.g.adjoint_forward(dt, nsteps, k)
+        out = []
+        for lam in lams:
+            la = torch.from_numpy(lam).to(ag.dt).cuda()
+            stored = ag.g.adjoint_stored(dt, nsteps, k, ws, la)
+            recomputed = ag.g.adjoint(dt, nsteps, k, t0, la)
+            out.append((stored, recomputed))
+    ag.stream.synchronize()
+    assert torch.equal(T_fwd, T_step)
+    for (sT, sC), (rT, rC) in out:
+        assert torch.equal(sT, rT) and torch.equal(sC, rC)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("nsteps,k", [(12, 1), (12, 5), (12, 12), (12, 50), (13, 4), (0, 3)])
+def test_stored_checkpoints_give_the_same_states_and_gradients(prec, nsteps, k):
+    """The checkpointing forward leaves T exactly as the stepping entry point
+    does, and the reverse pass from its checkpoints equals the reverse pass
+    that takes its own (same kernels, same states: bit for bit), also for a
+    second lambda on the same checkpoints."""
+    b, T0, chi, h, dt = _problem((48, 40), 21)
+    rng = np.random.default_rng(22)
+    lams = [rng.standard_normal(T0.shape) for _ in range(2)]
+    _stored_vs_recomputed(AdjGrid(b, chi, h, prec), T0, lams, dt, nsteps, k)
+
+
+def test_stored_checkpoints_1024_fp32_workload():
+    """The adjoint workload's shape (1024^2 FP32, 50 steps, checkpoints every
+    10) with the sweeps autotuned, so the tuned launch shapes run."""
+    p = synth.adjoint_problem(n=1024, nsteps=50)
+    ag = AdjGrid(p.b, p.chi, p.h, "f32")
+    with torch.cuda.stream(ag.stream):
+        T = torch.from_numpy(p.T0).float().cuda()
+        ag.g.set_field("T", T)
+        ag.g.tune(p.dt, reps=3)
+    lam = np.random.default_rng(23).standard_normal(p.T0.shape)
+    _stored_vs_recomputed(ag, p.T0, [lam], p.dt, p.nsteps, 10)
