@@ -165,7 +165,12 @@ int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, double *dev
  * dL/dT_0 into dev_grad_T0 and, when dev_grad_chi is not NULL, dL/dchi per
  * cell (needs ASD_FLAG_PER_CELL_CHI).  The forward states are recomputed
  * from checkpoints taken every ckpt_every steps.  dev_adj_ws: device scratch
- * of asd_adjoint_workspace_bytes bytes.  The grid's T field is not touched.
+ * of asd_adjoint_workspace_bytes bytes (the checkpoints, two segments' states
+ * and four work fields).  The grid's T field is not touched.  With more than
+ * one segment the recomputation of the next segment runs on a second stream
+ * of the grid's own (created on the first such call, default priority, freed
+ * by asd_destroy) beside the reverse pass; the work is ordered by events and
+ * joined back into the grid's stream before the call returns.
  * The derivative of a limiter at a kink (ab = 0) is taken as zero. */
 int asd_adjoint_workspace_bytes(asd_grid g, int32_t nsteps, int32_t ckpt_every, size_t *bytes);
 int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, const void *dev_T0,

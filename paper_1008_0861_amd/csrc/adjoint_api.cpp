@@ -13,7 +13,9 @@
 // symmetric).  All buffers live in the caller's adjoint workspace.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "asd_internal.h"
 
@@ -24,6 +26,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct AdjPlan {
     int nck;         // checkpoints (states at steps 0, k, 2k, ...)
     int k;
+    int nbuf;        // segment state sets: 2 when there are several segments
     size_t field;    // bytes per state
     size_t total;
 };
@@ -32,11 +35,46 @@ static AdjPlan adj_plan(asd_grid g, int nsteps, int k) {
     AdjPlan p{};
     p.k = k;
     p.nck = nsteps > 0 ? (nsteps + k - 1) / k : 1;
+    p.nbuf = p.nck > 1 ? 2 : 1;
     p.field = align256((size_t)g->N * g->es);
-    // checkpoints + k recomputed states + k T* + transposed scratch +
-    // lambda (both layouts) + mu
-    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k) + 4);
+    // checkpoints + per state set (k recomputed states + k T*) + transposed
+    // scratch + lambda (both layouts) + mu
+    p.total = p.field * ((size_t)p.nck + (size_t)(2 * k * p.nbuf) + 4);
     return p;
+}
+
+// The second stream and the events of the overlapped reverse pass, created
+// on a grid's first adjoint call with several segments (default priority,
+// no implicit ordering with other streams: only the events order it).
+static int adj_streams(asd_grid g) {
+    if (g->aux) return ASD_OK;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return asd_fail(ASD_EHIP, "adjoint: stream create failed");
+    for (int i = 0; i < kAuxEvents; ++i) {
+        if (hipEventCreateWithFlags(&g->aux_ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(g->aux_ev[j]);
+            (void)hipStreamDestroy(s);
+            return asd_fail(ASD_EHIP, "adjoint: event create failed");
+        }
+    }
+    g->aux = s;
+    return ASD_OK;
+}
+
+// enqueue_* launch on g->st: this points it at another stream for a scope
+struct OnStream {
+    asd_grid g;
+    hipStream_t saved;
+    OnStream(asd_grid g_, hipStream_t s) : g(g_), saved(g_->st) { g->st = s; }
+    ~OnStream() { g->st = saved; }
+};
+
+// `waiter` waits for what `signaller` has enqueued so far
+static int stream_wait(hipStream_t signaller, hipStream_t waiter, hipEvent_t ev) {
+    if (hipEventRecord(ev, signaller) != hipSuccess || hipStreamWaitEvent(waiter, ev, 0) != hipSuccess)
+        return asd_fail(ASD_EHIP, "adjoint: stream ordering failed");
+    return ASD_OK;
 }
 
 static int adj_check(asd_grid g, int nsteps, int k) {
@@ -107,7 +145,14 @@ static int forward_ckpt(asd_grid g, double dt, int nsteps, int k, char* ws) {
     return rc;
 }
 
-// stored: the checkpoints are already in ws (asd_adjoint_forward); T0 unused
+// stored: the checkpoints are already in ws (asd_adjoint_forward); T0 unused.
+//
+// With several segments the recomputation of segment c-1 (on the grid's
+// second stream) overlaps the reverse pass over segment c (on the grid's
+// stream): the two work on different state sets (c & 1), and each waits
+// only for what it reads.  Event i of the grid:
+//   0: fork (the reverse pass's inputs are ready) and the final join,
+//   1 + s: state set s has been recomputed,  3 + s: set s has been consumed.
 template <typename T>
 static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, const void* lamN, void* gT0,
                      void* gchi, char* ws, bool stored) {
@@ -118,27 +163,29 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
         cur += pl.field;
         return (void*)p;
     };
-    void* ck[4096];
-    if (pl.nck > 4096) return asd_fail(ASD_EUNSUPPORTED, "too many checkpoints (nsteps/ckpt_every > 4096)");
+    std::vector<void*> ck(pl.nck);
     for (int c = 0; c < pl.nck; ++c) ck[c] = take();
-    void* S[1025];
-    void* TS[1024];
-    if (k > 1024) return asd_fail(ASD_EUNSUPPORTED, "ckpt_every must be <= 1024");
-    S[0] = nullptr;
-    for (int i = 1; i <= k; ++i) S[i] = take();
-    for (int i = 0; i < k; ++i) TS[i] = take();
+    std::vector<void*> S[2], TS[2];  // per set: recomputed states T^{ck k + i} (i >= 1), T* of each step
+    for (int s = 0; s < pl.nbuf; ++s) {
+        S[s].assign(k + 1, nullptr);
+        for (int i = 1; i <= k; ++i) S[s][i] = take();
+    }
+    for (int s = 0; s < pl.nbuf; ++s) {
+        TS[s].assign(k, nullptr);
+        for (int i = 0; i < k; ++i) TS[s][i] = take();
+    }
     void* tB = take();
     void* lam = take();   // lambda* (after a y sweep's reverse), layout A
     void* lamB = take();  // lambda^n (after an x sweep's reverse), layout B: the y solve's input
     void* mu = take();
-    int rc;
+    int rc = ASD_OK;
     // forward pass: checkpoints at steps 0, k, 2k, ...
     if (!stored) rc = enqueue_copy(g, T0, ck[0]);
     if (rc) return rc;
     for (int c = 1; c < pl.nck && !stored; ++c) {
         const void* in = ck[c - 1];
         for (int i = 0; i < k; ++i) {
-            void* out = (i == k - 1) ? ck[c] : S[1];
+            void* out = (i == k - 1) ? ck[c] : S[0][1];
             rc = enqueue_sweep(g, 0, dt, in, tB, 0, no_reduce(), nullptr, nullptr);
             if (rc) return rc;
             rc = enqueue_sweep(g, 1, dt, tB, out, 0, no_reduce(), nullptr, nullptr);
@@ -155,40 +202,81 @@ static int adjoint_t(asd_grid g, double dt, int nsteps, int k, const void* T0, c
                                   : launch_fill_u32((unsigned*)gchi, 0u, g->N, g->st);
         if (e != hipSuccess) return asd_fail(ASD_EHIP, "clear grad_chi: %s", hipGetErrorString(e));
     }
-    void* St[1025];  // this segment's states T^{ck k + i}
-    for (int c = pl.nck - 1; c >= 0; --c) {
-        const int len = std::min(k, nsteps - c * k);
-        St[0] = ck[c];
-        for (int i = 1; i <= len; ++i) St[i] = S[i];
-        // the segment's last state is the next checkpoint, except in the
-        // last segment: that y sweep is not run again
+    auto seg_len = [&](int c) { return std::min(k, nsteps - c * k); };
+    // segment c's states T^{ck k + i}, i = 0 .. len, in set s: the last is
+    // the next checkpoint, except in the last segment
+    auto state = [&](int c, int s, int i) -> void* {
+        if (i == 0) return ck[c];
+        if (i == seg_len(c) && c + 1 < pl.nck) return ck[c + 1];
+        return S[s][i];
+    };
+    auto recompute = [&](int c, int s) {
+        const int len = seg_len(c);
         const bool last_stored = c + 1 < pl.nck;
-        if (last_stored) St[len] = ck[c + 1];
         for (int i = 0; i < len; ++i) {
             // T* in the y sweep's layout (tB) and, second store, in the
-            // natural layout the stencils read (TS[i])
-            rc = enqueue_sweep(g, 0, dt, St[i], tB, 0, no_reduce(), nullptr, nullptr, TS[i]);
-            if (rc) return rc;
-            if (i + 1 == len && last_stored) break;
-            rc = enqueue_sweep(g, 1, dt, tB, St[i + 1], 0, no_reduce(), nullptr, nullptr);
-            if (rc) return rc;
+            // natural layout the stencils read (TS)
+            int r = enqueue_sweep(g, 0, dt, state(c, s, i), tB, 0, no_reduce(), nullptr, nullptr, TS[s][i]);
+            if (r) return r;
+            if (i + 1 == len && last_stored) break;  // that y sweep's output is stored
+            r = enqueue_sweep(g, 1, dt, tB, state(c, s, i + 1), 0, no_reduce(), nullptr, nullptr);
+            if (r) return r;
         }
-        for (int i = len - 1; i >= 0; --i) {
+        return ASD_OK;
+    };
+    auto reverse = [&](int c, int s) {
+        for (int i = seg_len(c) - 1; i >= 0; --i) {
             // y sweep: T* -> T^{n+1}; lambda arrives in the y solve's layout
-            rc = enqueue_sweep(g, 1, dt, lamB, mu, 1, no_reduce(), nullptr, nullptr);
-            if (rc) return rc;
-            rc = stencil<T>(g, 1, dt, mu, TS[i], St[i + 1], lam, false, gchi);
-            if (rc) return rc;
+            int r = enqueue_sweep(g, 1, dt, lamB, mu, 1, no_reduce(), nullptr, nullptr);
+            if (r) return r;
+            r = stencil<T>(g, 1, dt, mu, TS[s][i], state(c, s, i + 1), lam, false, gchi);
+            if (r) return r;
             // x sweep: T^n -> T*; the solve writes mu in the natural layout
             // directly (line-contiguous store, no transpose), the stencil
             // writes lambda^n in the layout of the next y solve
-            rc = enqueue_sweep(g, 0, dt, lam, mu, SWEEP_SOLVE_ONLY | SWEEP_KEEP_LAYOUT, no_reduce(), nullptr,
-                               nullptr);
-            if (rc) return rc;
-            rc = stencil<T>(g, 0, dt, mu, St[i], TS[i], lamB, true, gchi);
-            if (rc) return rc;
+            r = enqueue_sweep(g, 0, dt, lam, mu, SWEEP_SOLVE_ONLY | SWEEP_KEEP_LAYOUT, no_reduce(), nullptr, nullptr);
+            if (r) return r;
+            r = stencil<T>(g, 0, dt, mu, state(c, s, i), TS[s][i], lamB, true, gchi);
+            if (r) return r;
         }
+        return ASD_OK;
+    };
+    const int last = pl.nck - 1;
+    if (pl.nbuf == 1) {
+        rc = recompute(0, 0);
+        if (rc == ASD_OK) rc = reverse(0, 0);
+    } else {
+        rc = adj_streams(g);
+        if (rc) return rc;
+        hipStream_t mst = g->st, aux = g->aux;
+        rc = stream_wait(mst, aux, g->aux_ev[0]);
+        auto recompute_aux = [&](int c) {
+            OnStream on(g, aux);
+            int r = recompute(c, c & 1);
+            if (r == ASD_OK && hipEventRecord(g->aux_ev[1 + (c & 1)], aux) != hipSuccess)
+                r = asd_fail(ASD_EHIP, "adjoint: event record failed");
+            return r;
+        };
+        if (rc == ASD_OK) rc = recompute_aux(last);
+        for (int c = last; c >= 0 && rc == ASD_OK; --c) {
+            if (c >= 1) {
+                // set (c - 1) & 1 was last read by the reverse pass over c + 1
+                if (c + 1 <= last && hipStreamWaitEvent(aux, g->aux_ev[3 + ((c + 1) & 1)], 0) != hipSuccess)
+                    rc = asd_fail(ASD_EHIP, "adjoint: stream wait failed");
+                if (rc == ASD_OK) rc = recompute_aux(c - 1);
+            }
+            if (rc == ASD_OK && hipStreamWaitEvent(mst, g->aux_ev[1 + (c & 1)], 0) != hipSuccess)
+                rc = asd_fail(ASD_EHIP, "adjoint: stream wait failed");
+            if (rc == ASD_OK) rc = reverse(c, c & 1);
+            if (rc == ASD_OK && hipEventRecord(g->aux_ev[3 + (c & 1)], mst) != hipSuccess)
+                rc = asd_fail(ASD_EHIP, "adjoint: event record failed");
+        }
+        // join: nothing of this call stays pending on the second stream,
+        // also when an enqueue above failed
+        const int rj = stream_wait(aux, mst, g->aux_ev[0]);
+        if (rc == ASD_OK) rc = rj;
     }
+    if (rc) return rc;
     return enqueue_permute_2d(g, lamB, gT0, false);
 }
 

@@ -120,6 +120,7 @@ struct GraphEntry {
     uint64_t last_use = 0;
 };
 static constexpr int kGraphCacheEntries = 4;
+static constexpr int kAuxEvents = 5;
 
 struct asd_grid_s {
     asd_desc d{};
@@ -150,6 +151,10 @@ struct asd_grid_s {
     bool graph_valid = false;
     GraphEntry graphs[kGraphCacheEntries];
     uint64_t graph_clock = 0;
+    // the adjoint's second stream (recomputation beside the reverse pass)
+    // and its events; created by the first adjoint call that needs them
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_ev[kAuxEvents] = {};
 };
 
 // capi.cpp

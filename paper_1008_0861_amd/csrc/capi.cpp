@@ -207,6 +207,11 @@ extern "C" int asd_destroy(asd_grid g) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
     for (GraphEntry& e : g->graphs)
         if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (g->aux) {
+        (void)hipStreamSynchronize(g->aux);
+        for (hipEvent_t& e : g->aux_ev) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(g->aux);
+    }
     delete g;
     return ASD_OK;
 }

@@ -284,9 +284,13 @@ def test_adjoint_entry_points_validate_before_any_gpu_call(asd):
     h, d, _ = _fake_grid(asd)
     fake = ctypes.c_void_p(1 << 24)
     ws_n = ctypes.c_size_t()
+    field = (64 * 48 * 4 + 255) // 256 * 256
+    # one segment: one set of segment states
+    assert L.asd_adjoint_workspace_bytes(h, 5, 5, ctypes.byref(ws_n)) == 0
+    assert ws_n.value == (1 + 10 + 4) * field
+    # 3 checkpoints + 2 sets of 2 x 5 segment states + 4 work fields of 64 x 48 FP32
     assert L.asd_adjoint_workspace_bytes(h, 12, 5, ctypes.byref(ws_n)) == 0
-    # 3 checkpoints + 2 x 5 segment states + 4 scratch fields of 64 x 48 FP32
-    assert ws_n.value == (3 + 10 + 4) * ((64 * 48 * 4 + 255) // 256 * 256)
+    assert ws_n.value == (3 + 20 + 4) * field
     ws, n = ctypes.c_void_p(1 << 26), ws_n.value
     assert L.asd_adjoint_forward(None, 1e-3, 12, 5, ws, n) == -1
     assert L.asd_adjoint_step_stored(None, 1e-3, 12, 5, fake, fake, None, ws, n) == -1

@@ -242,3 +242,8 @@ def test_stored_checkpoints_1024_fp32_workload():
         ag.g.tune(p.dt, reps=3)
     lam = np.random.default_rng(23).standard_normal(p.T0.shape)
     _stored_vs_recomputed(ag, p.T0, [lam], p.dt, p.nsteps, 10)
+    # five segments (the recomputation on the second stream beside the
+    # reverse pass) against one segment (one stream), bit for bit
+    five = ag.adjoint(p.T0, lam, p.dt, p.nsteps, 10)
+    one = ag.adjoint(p.T0, lam, p.dt, p.nsteps, 50)
+    assert np.array_equal(five[0], one[0]) and np.array_equal(five[1], one[1])
