@@ -76,6 +76,30 @@ def test_nested_minmod_is_four_argument_minmod(orc):
         assert orc.lim4("minmod", *v) == ref
 
 
+def test_nested_mc_hand_values(orc):
+    """MC nested as L(L(a,b), L(c,d)), (a, b) the two one-sided differences
+    of one cell and (c, d) of the other, each MC(x, y) = minmod(2x, 2y,
+    (x+y)/2).  Values worked by hand:
+      (1,3,3,9): MC(1,3) = min(2,6,2) = 2, MC(3,9) = min(6,18,6) = 6,
+                 MC(2,6) = min(4,12,4) = 4  (the pairing (a,d),(b,c) would
+                 give MC(MC(1,9), MC(3,3)) = MC(2,3) = 2.5);
+      (1,2,8,8): MC(1,2) = 1.5, MC(8,8) = 8, MC(1.5,8) = min(3,16,4.75) = 3;
+      (1,1,9,9): MC(1,1) = 1, MC(9,9) = 9, MC(1,9) = min(2,18,5) = 2;
+      (4,4,4,4): 4;  one pair of mixed sign: 0;  all negated: negated."""
+    cases = [((1, 3, 3, 9), 4.0), ((1, 2, 8, 8), 3.0), ((1, 1, 9, 9), 2.0), ((4, 4, 4, 4), 4.0),
+             ((1, -3, 3, 9), 0.0), ((1, 3, -3, 9), 0.0), ((1, 3, -3, -9), 0.0)]
+    for v, ref in cases:
+        assert orc.lim4("mc", *v) == ref, v
+        assert orc.lim4("mc", *[-x for x in v]) == -ref, v
+    # the pairs commute, and so do the arguments within a pair
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        a, b_, c, d = rng.standard_normal(4) * rng.choice([1e-2, 1.0, 1e2])
+        got = orc.lim4("mc", a, b_, c, d)
+        for w in ((b_, a, c, d), (a, b_, d, c), (c, d, a, b_)):
+            assert orc.lim4("mc", *w) == pytest.approx(got, rel=1e-15, abs=0)
+
+
 def test_linear_nested_is_arithmetic_mean(orc):
     rng = np.random.default_rng(3)
     for _ in range(100):
