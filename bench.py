@@ -103,7 +103,7 @@ def sweep_duration_in_loop(g, p, stream, torch, steps=400):
     with torch.cuda.stream(stream):
         g.step_semi_implicit(p.dt, 10)
         ms = timed(lambda: g.step_semi_implicit(p.dt, steps), stream, torch)
-    g.set_graphs(True)
+    g.set_graphs("auto")
     return ms / (2 * steps)
 
 

@@ -139,11 +139,20 @@ int asd_get_sweep_variant(asd_grid g, int32_t axis, int32_t *variant);
  * b set.  Synchronises the stream. */
 int asd_tune(asd_grid g, double dt, int32_t reps);
 
-/* Enable (1) or disable (0) hipGraph capture of multi-step calls (on by
- * default; used only with a non-default stream).  A graph holds at most 2048
+/* hipGraph capture of multi-step calls (only with a non-default stream):
+ * ASD_GRAPHS_OFF launches every call directly; ASD_GRAPHS_AUTO (the
+ * default) captures calls of 64 steps or more and launches shorter calls
+ * directly (a graph launch starts its first kernel later than a direct
+ * launch, which costs a short call more than the host-side launches do);
+ * ASD_GRAPHS_ALWAYS captures every call of 2 steps or more.  A captured call
+ * is replayed from a small per-grid cache.  A graph holds at most 2048
  * steps: longer calls replay it and launch the remainder directly, or, when
- * they produce per-step outputs, launch every step directly. */
-int asd_set_graphs(asd_grid g, int32_t on);
+ * they produce per-step outputs, launch every step directly.  EINVAL for
+ * another mode. */
+#define ASD_GRAPHS_OFF 0
+#define ASD_GRAPHS_AUTO 1
+#define ASD_GRAPHS_ALWAYS 2
+int asd_set_graphs(asd_grid g, int32_t mode);
 
 /* ------------------------------------------------------------ measurement
  * Time one sweep kernel in isolation.  reps == 0: enqueue one sweep chain

@@ -28,6 +28,7 @@ FLAG_ALLOW_UNSTABLE = 2
 FLAG_FOUR_STEP = 4
 FLAG_REVERSE_ORDER = 8
 STATUS_NONFINITE, STATUS_NEG_T, STATUS_ENERGY_DRIFT = 1, 2, 4
+GRAPHS_OFF, GRAPHS_AUTO, GRAPHS_ALWAYS = 0, 1, 2
 
 # every entry point of include/asd.h and include/asd_extra.h
 EXPORTED = [
@@ -333,8 +334,11 @@ class Grid:
         check(lib().asd_tune(self.handle, float(dt), int(reps)))
         return [self.sweep_config(a) for a in range(len(self.shape))]
 
-    def set_graphs(self, on):
-        check(lib().asd_set_graphs(self.handle, 1 if on else 0))
+    def set_graphs(self, mode):
+        """Graph capture of step calls: False (never), "auto" (the default:
+        calls of 64 steps or more), True (every call of 2 steps or more)."""
+        code = {False: GRAPHS_OFF, "auto": GRAPHS_AUTO, True: GRAPHS_ALWAYS}[mode]
+        check(lib().asd_set_graphs(self.handle, code))
 
     def bench_sweep(self, axis, dt, reps):
         """Enqueue reps launches of one sweep kernel (T -> scratch) for timing."""

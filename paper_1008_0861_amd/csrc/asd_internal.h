@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "../../include/asd.h"
+#include "../../include/asd_extra.h"
 #include "asd_device.h"
 #include "asd_launch.h"
 
@@ -120,6 +121,11 @@ struct GraphEntry {
     uint64_t last_use = 0;
 };
 static constexpr int kGraphCacheEntries = 4;
+// ASD_GRAPHS_AUTO captures calls of at least this many steps; shorter calls
+// launch directly (a graph launch starts its first kernel several
+// microseconds later than a direct launch, more than the host-side launch
+// cost of a short call)
+static constexpr int kGraphMinSteps = 64;
 static constexpr int kAuxEvents = 5;
 
 struct asd_grid_s {
@@ -147,7 +153,7 @@ struct asd_grid_s {
     // graph cache of step loops: a few captured loops, least recently used
     // replaced first; graph_valid = false marks every entry stale (fields,
     // coefficients or launch shapes changed)
-    bool use_graphs = true;
+    int graph_mode = ASD_GRAPHS_AUTO;  // ASD_GRAPHS_OFF / _AUTO / _ALWAYS
     bool graph_valid = false;
     GraphEntry graphs[kGraphCacheEntries];
     uint64_t graph_clock = 0;
@@ -156,6 +162,13 @@ struct asd_grid_s {
     hipStream_t aux = nullptr;
     hipEvent_t aux_ev[kAuxEvents] = {};
 };
+
+// whether a step call of nsteps steps replays a captured graph (only on a
+// non-default stream)
+inline bool graphs_for(asd_grid_s* g, int nsteps) {
+    if (!g->st || nsteps < 2) return false;
+    return g->graph_mode == ASD_GRAPHS_ALWAYS || (g->graph_mode == ASD_GRAPHS_AUTO && nsteps >= kGraphMinSteps);
+}
 
 // capi.cpp
 int asd_fail(int code, const char* fmt, ...);

@@ -202,7 +202,7 @@ extern "C" int asd_batch_init(const asd_desc* descs, int32_t nprob, void* dev_ws
             asd_batch_destroy(b);
             return rc;
         }
-        b->sub[p]->use_graphs = false;
+        b->sub[p]->graph_mode = ASD_GRAPHS_OFF;
         // the sequential schedule's folds report into the batch's per-problem status
         b->sub[p]->flags = b->d_flags + p;
         b->sub[p]->stats = b->d_stats + 3 * p;

@@ -68,9 +68,11 @@ extern "C" int asd_get_sweep_variant(asd_grid g, int32_t axis, int32_t* variant)
     return ASD_OK;
 }
 
-extern "C" int asd_set_graphs(asd_grid g, int32_t on) {
+extern "C" int asd_set_graphs(asd_grid g, int32_t mode) {
     if (!g) return asd_fail(ASD_EINVAL, "grid is NULL");
-    g->use_graphs = on != 0;
+    if (mode != ASD_GRAPHS_OFF && mode != ASD_GRAPHS_AUTO && mode != ASD_GRAPHS_ALWAYS)
+        return asd_fail(ASD_EINVAL, "graph mode must be ASD_GRAPHS_OFF, _AUTO or _ALWAYS");
+    g->graph_mode = mode;
     g->graph_valid = false;
     return ASD_OK;
 }

@@ -618,7 +618,7 @@ extern "C" int asd_step_semi_implicit(asd_grid g, double dt, int32_t nsteps, dou
     // the legacy default stream cannot be captured: launch eagerly there
     StepOut o;
     o.energy = dev_energy;
-    if (g->use_graphs && g->st && nsteps >= 2) return run_si_graph(g, dt, nsteps, o);
+    if (graphs_for(g, nsteps)) return run_si_graph(g, dt, nsteps, o);
     return enqueue_si_loop(g, dt, nsteps, o);
 }
 
@@ -704,7 +704,7 @@ extern "C" int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, 
     if (rc) return rc;
     StepOut o;
     o.energy = dev_energy;
-    if (g->use_graphs && g->st && nsteps >= 2) return run_explicit_graph(g, dt, nsteps, o);
+    if (graphs_for(g, nsteps)) return run_explicit_graph(g, dt, nsteps, o);
     return enqueue_explicit_loop(g, dt, nsteps, o);
 }
 
@@ -723,7 +723,7 @@ extern "C" int asd_step_series(asd_grid g, int32_t scheme, double dt, int32_t ns
     if (rc) return rc;
     StepOut o;
     o.series = dev_series;
-    if (g->use_graphs && g->st && nsteps >= 2)
+    if (graphs_for(g, nsteps))
         return ex ? run_explicit_graph(g, dt, nsteps, o) : run_si_graph(g, dt, nsteps, o);
     return ex ? enqueue_explicit_loop(g, dt, nsteps, o) : enqueue_si_loop(g, dt, nsteps, o);
 }

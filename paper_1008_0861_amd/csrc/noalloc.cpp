@@ -69,7 +69,7 @@ extern "C" int asd_step_semi_implicit_noalloc(const asd_desc* desc, void* dev_T,
     if (rc) return rc;
     rc = init_grid_in_place(&g, desc, ws, kNoallocScratchBytes, stream);
     if (rc) return rc;
-    g.use_graphs = false;
+    g.graph_mode = ASD_GRAPHS_OFF;
     g.T = dev_T;
     g.b[0] = const_cast<void*>(dev_bx);
     g.b[1] = const_cast<void*>(dev_by);

@@ -309,3 +309,20 @@ def test_adjoint_entry_points_validate_before_any_gpu_call(asd):
     assert L.asd_adjoint_forward(h, 1e-3, 12, 5, ws, n) == -4  # T, b not set
     assert L.asd_adjoint_step_stored(h, 1e-3, 12, 5, fake, fake, None, ws, n) == -4
     assert L.asd_destroy(h) == 0
+
+
+def test_graph_mode_validation(asd):
+    """asd_set_graphs takes ASD_GRAPHS_OFF / _AUTO / _ALWAYS (the values the
+    header defines) and refuses anything else; no device work."""
+    src = open(os.path.join(ROOT, "include", "asd_extra.h")).read()
+    consts = dict(re.findall(r"#define (ASD_GRAPHS_\w+) (\d+)", src))
+    assert {k: int(v) for k, v in consts.items()} == {
+        "ASD_GRAPHS_OFF": asd.GRAPHS_OFF, "ASD_GRAPHS_AUTO": asd.GRAPHS_AUTO, "ASD_GRAPHS_ALWAYS": asd.GRAPHS_ALWAYS}
+    L = asd.lib()
+    h, _, _ = _fake_grid(asd)
+    for m in (asd.GRAPHS_OFF, asd.GRAPHS_AUTO, asd.GRAPHS_ALWAYS):
+        assert L.asd_set_graphs(h, m) == 0
+    for m in (-1, 3, 7):
+        assert L.asd_set_graphs(h, m) == -1
+    assert L.asd_set_graphs(None, 1) == -1
+    assert L.asd_destroy(h) == 0

@@ -290,6 +290,7 @@ def test_energy_conserved_and_deterministic_100_steps():
 def test_graph_and_eager_paths_agree():
     p = synth.grf2d_problem(256, nsteps=12)
     g1 = GpuProblem(p, "f32")
+    g1.g.set_graphs(True)  # capture the 12-step calls (the default launches them directly)
     g2 = GpuProblem(p, "f32")
     g2.g.set_graphs(False)
     a = g1.run()
@@ -301,6 +302,21 @@ def test_graph_and_eager_paths_agree():
         b = g2.run(nsteps=12)
         torch.cuda.synchronize()
         assert np.array_equal(a, b)
+
+
+def test_default_graph_mode_captures_long_calls_only():
+    """The default mode launches a short call directly and replays a captured
+    graph for a call of 64 steps or more; both agree with the eager path bit
+    for bit, the long call also on replays with eager work in between."""
+    p = synth.grf2d_problem(256, nsteps=70)
+    auto = GpuProblem(p, "f32")
+    eager = GpuProblem(p, "f32")
+    eager.g.set_graphs(False)
+    for n in (12, 70, 70, 70):
+        a = auto.run(nsteps=n)
+        b = eager.run(nsteps=n)
+        torch.cuda.synchronize()
+        assert np.array_equal(a, b), n
 
 
 def test_launch_shapes_agree():
