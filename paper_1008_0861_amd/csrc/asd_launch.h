@@ -147,12 +147,16 @@ int explicit_num_blocks(int ndim, const int n[3]);
 
 // ------------------------------------------------------------------- batch
 // One problem of a batch: its x sweep (T -> T*, transposed) and y sweep
-// (T* -> T), the number of line groups (tiles) of each, where its y-sweep
-// tiles start in the batch-wide tile numbering, and its cell volume.
+// (T* -> T), the number of line groups (tiles) of each, the per-lane
+// capacity of each sweep's tiles (the batch's MMAX, or half of it when the
+// problem's lines fit: a shorter line then runs the smaller tile instead of
+// padding every lane to the batch's capacity), where its y-sweep tiles start
+// in the batch-wide tile numbering, and its cell volume.
 template <typename T>
 struct BatchProblem {
     SweepParams<T> sweep[2];
     int ngroups[2];
+    int mmax[2];
     int tile0;        // first y-sweep tile of this problem among all problems' y-sweep tiles
     int dirichlet;    // T = 0 walls (the energy is not conserved: no drift flag)
     double dV;

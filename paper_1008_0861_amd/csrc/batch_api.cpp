@@ -111,16 +111,23 @@ extern "C" int asd_batch_workspace_bytes(const asd_desc* descs, int32_t nprob, s
 }
 
 // Launch shape of problem line length n for a fixed workgroup size.
+// A problem's line shape under the batch's workgroup size and per-lane
+// capacity mmax: the fewest waves per line that fit, and the tile's own
+// capacity, mmax or (when its lines fit) mmax / 2 (the batch kernels run
+// either; a line shorter than the batch's longest then does not pad every
+// lane to the longest one's capacity).
 static bool batch_line_cfg(int es, int n, int nthreads, int mmax, int variant, SweepCfg* out) {
     for (int wpl = 1; 64 * wpl <= nthreads; wpl *= 2) {
         const int P = std::min(64 * wpl, pow2_floor(n));
-        if ((n + P - 1) / P > mmax) continue;
+        const int m = (n + P - 1) / P;
+        if (m > mmax) continue;
         const int lpw = nthreads / (64 * wpl);
-        if (sweep_lds(es, 2, n, lpw, wpl, nthreads, mmax, variant) > kLdsLimit) continue;
+        const int own = mmax >= 4 && 2 * m <= mmax ? mmax / 2 : mmax;
+        if (sweep_lds(es, 2, n, lpw, wpl, nthreads, own, variant) > kLdsLimit) continue;
         out->wpl = wpl;
         out->lpw = lpw;
         out->P = P;
-        out->mmax = mmax;
+        out->mmax = own;
         out->variant = variant;
         return true;
     }
@@ -143,8 +150,8 @@ static int batch_shape(asd_batch b, int nthreads, int variant, int mmax_from = 4
                 const int n = (int)b->sub[p]->d.n[d];
                 ok = batch_line_cfg(es, n, nthreads, mmax, variant, &cfg[2 * p + d]);
                 if (ok)
-                    lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, cfg[2 * p + d].wpl, nthreads, mmax,
-                                                  variant));
+                    lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, cfg[2 * p + d].wpl, nthreads,
+                                                  cfg[2 * p + d].mmax, variant));
             }
         }
         if (!ok) continue;
@@ -287,6 +294,7 @@ static int batch_tables(asd_batch b) {
             if (rc) return rc;
             const int nt1 = probs[p].sweep[d].nt1, lpw = b->cfg[2 * p + d].lpw;
             probs[p].ngroups[d] = (nt1 + lpw - 1) / lpw;
+            probs[p].mmax[d] = b->cfg[2 * p + d].mmax;
         }
         probs[p].dirichlet = g->d.bc == ASD_BC_DIRICHLET;
         probs[p].dV = g->d.h[0] * g->d.h[1];
