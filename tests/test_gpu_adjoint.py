@@ -247,3 +247,29 @@ def test_stored_checkpoints_1024_fp32_workload():
     five = ag.adjoint(p.T0, lam, p.dt, p.nsteps, 10)
     one = ag.adjoint(p.T0, lam, p.dt, p.nsteps, 50)
     assert np.array_equal(five[0], one[0]) and np.array_equal(five[1], one[1])
+
+
+def test_autograd_two_forwards_before_backward():
+    """Two forward calls on one grid with different chi, then both backward
+    passes: each keeps its own checkpoints, and the backward sets its own chi
+    again, so both gradients match the reverse-mode reference."""
+    b, T0, chi, h, dt = _problem((32, 40), 31)
+    chi2 = chi * np.exp(0.2 * synth.smoothed_normal(chi.shape, 32, 2.0))
+    cmax = float(max(chi.max(), chi2.max()))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = asd.Grid(b[0].shape, h, bc="periodic", dtype=torch.float64, chi_par=cmax, per_cell_chi=True)
+        g.set_b(*[torch.from_numpy(c).cuda() for c in b])
+        t0s = [torch.from_numpy(T0).cuda().requires_grad_(True) for _ in range(2)]
+        chs = [torch.from_numpy(c).cuda().requires_grad_(True) for c in (chi, chi2)]
+        outs = [semi_implicit_steps(t0s[i], chs[i], g, dt, 7, 3) for i in range(2)]
+        for o in outs:
+            (o ** 2).sum().backward()
+    torch.cuda.synchronize()
+    for i, c in enumerate((chi, chi2)):
+        TN = torch_ref.run(torch.from_numpy(T0), [torch.from_numpy(v) for v in b], torch.from_numpy(c), h, dt, 7,
+                           chi_par=cmax).numpy()
+        gT_ref, gC_ref, _ = torch_ref.reverse_gradients(T0, b, c, h, dt, 7, 2.0 * TN, chi_par=cmax)
+        assert _rel(outs[i].detach().cpu().numpy(), TN) <= 1e-12
+        assert _rel(t0s[i].grad.cpu().numpy(), gT_ref) <= 1e-9
+        assert _rel(chs[i].grad.cpu().numpy(), gC_ref) <= 1e-9
