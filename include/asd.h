@@ -170,7 +170,9 @@ int asd_step_explicit_limited(asd_grid g, double dt, int32_t nsteps, double *dev
  * one segment the recomputation of the next segment runs on a second stream
  * of the grid's own (created on the first such call, default priority, freed
  * by asd_destroy) beside the reverse pass; the work is ordered by events and
- * joined back into the grid's stream before the call returns.
+ * joined back into the grid's stream before the call returns.  That first
+ * call creates the stream and its events, so it must not run while the
+ * grid's stream is being captured into a graph; later calls may.
  * The derivative of a limiter at a kink (ab = 0) is taken as zero. */
 int asd_adjoint_workspace_bytes(asd_grid g, int32_t nsteps, int32_t ckpt_every, size_t *bytes);
 int asd_adjoint_step(asd_grid g, double dt, int32_t nsteps, int32_t ckpt_every, const void *dev_T0,
