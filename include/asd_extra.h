@@ -76,6 +76,15 @@ int asd_batch_set_block(asd_batch b, int32_t nthreads);
 int asd_batch_set_variant(asd_batch b, int32_t variant);
 int asd_batch_get_variant(asd_batch b, int32_t *variant);
 
+/* Per-lane capacity of the batch kernels: the smallest of 4, 8, 16 cells at
+ * or above mmax that fits every problem at the current work-group size and
+ * tile body (each problem then runs that capacity, half of it, or with
+ * capacity 16 also 4).  With capacity 16 on the face-slot body, problems
+ * whose lines have 257 to 512 cells run two lines per wave (32 lanes per
+ * line).  EINVAL for mmax other
+ * than 4, 8 or 16, EUNSUPPORTED if nothing fits. */
+int asd_batch_set_capacity(asd_batch b, int32_t mmax);
+
 /* Autotuner: time modes 0 and 2 at every admissible work-group size,
  * per-lane capacity (4, 8 or 16 cells) and tile body on probe_steps steps
  * (this advances the problems' T), keep the

@@ -37,6 +37,7 @@ EXPORTED = [
     "asd_adjoint_step", "asd_adjoint_forward", "asd_adjoint_step_stored", "asd_status", "asd_destroy",
     "asd_batch_workspace_bytes", "asd_batch_init", "asd_batch_set_problem", "asd_batch_step",
     "asd_batch_destroy", "asd_batch_set_block", "asd_batch_set_variant", "asd_batch_get_variant", "asd_batch_tune",
+    "asd_batch_set_capacity",
     "asd_batch_step_energy", "asd_batch_status",
     "asd_batch_set_graphs",
     "asd_get_sweep_config", "asd_set_sweep_config", "asd_set_sweep_shape", "asd_get_sweep_io",
@@ -104,6 +105,7 @@ def lib():
             "asd_batch_destroy": (ctypes.c_int, [vp]),
             "asd_batch_set_block": (ctypes.c_int, [vp, i32]),
             "asd_batch_set_variant": (ctypes.c_int, [vp, i32]),
+            "asd_batch_set_capacity": (ctypes.c_int, [vp, i32]),
             "asd_batch_get_variant": (ctypes.c_int, [vp, P(i32)]),
             "asd_batch_tune": (ctypes.c_int, [vp, i32, P(i32), P(i32)]),
             "asd_batch_step_energy": (ctypes.c_int, [vp, i32, i32, vp]),
@@ -412,6 +414,11 @@ class Batch:
     def set_variant(self, variant):
         """Tile body of the batch kernels: 0 face slots, 1 cell slots."""
         check(lib().asd_batch_set_variant(self.handle, int(variant)))
+
+    def set_capacity(self, mmax):
+        """Per-lane capacity of the batch kernels (4, 8 or 16 cells; 16 on
+        the face body runs lines of 32-512 cells two per wave)."""
+        check(lib().asd_batch_set_capacity(self.handle, int(mmax)))
 
     def variant(self):
         v = ctypes.c_int32()

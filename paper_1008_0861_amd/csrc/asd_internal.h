@@ -18,7 +18,8 @@
 struct SweepCfg {
     int wpl = 1, lpw = 1, P = 2, mmax = 1, io = 1;
     int variant = asd::SWEEP_FACE_SLOTS;
-    int nthreads() const { return 64 * wpl * io * lpw; }
+    int half = 0;  // two lines per wave (32 lanes per line; face body, batches only)
+    int nthreads() const { return (half ? 32 : 64 * wpl * io) * lpw; }
 };
 
 // gfx950: 160 KiB of LDS per workgroup; keep 2 KiB for static shared data.
@@ -38,14 +39,15 @@ inline int ilog2(int v) {
 
 // LDS layout and bytes of a sweep launch (slot rows of the lpw lines and the
 // interface-exchange buffers) for either tile body.
-inline asd::TileLayout sweep_layout(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax, int variant) {
-    const int P = std::min(64 * wpl, pow2_floor(n));
+inline asd::TileLayout sweep_layout(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax, int variant,
+                                    int half = 0) {
+    const int P = half ? 32 : std::min(64 * wpl, pow2_floor(n));
     return variant == asd::SWEEP_CELL_SLOTS ? asd::tile_layout_cell(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax)
                                             : asd::tile_layout(es, ndim, n, lpw, nthreads, wpl, ilog2(P), mmax);
 }
 inline size_t sweep_lds(int es, int ndim, int n, int lpw, int wpl, int nthreads, int mmax,
-                        int variant = asd::SWEEP_FACE_SLOTS) {
-    return (size_t)sweep_layout(es, ndim, n, lpw, wpl, nthreads, mmax, variant).total;
+                        int variant = asd::SWEEP_FACE_SLOTS, int half = 0) {
+    return (size_t)sweep_layout(es, ndim, n, lpw, wpl, nthreads, mmax, variant, half).total;
 }
 
 inline int sweep_threads_cap(int es, int mmax, int variant = asd::SWEEP_FACE_SLOTS) {

@@ -157,6 +157,7 @@ struct BatchProblem {
     SweepParams<T> sweep[2];
     int ngroups[2];
     int mmax[2];
+    int half[2];  // two lines per wave (capacity-16 face-body tiles of 257-512-cell lines)
     int tile0;        // first y-sweep tile of this problem among all problems' y-sweep tiles
     int dirichlet;    // T = 0 walls (the energy is not conserved: no drift flag)
     double dV;

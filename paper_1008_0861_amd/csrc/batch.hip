@@ -66,19 +66,33 @@ __device__ __forceinline__ void block_reduce3(double s, M mn, M mx, double& S, d
 
 // One line tile of a batch problem on either tile body (CELL: the
 // cell-slot body of sweep_cell.h).  Both end with a block barrier.
-template <typename T, int MMAX, int LIMC, bool EXT, bool CELL, bool REUSE>
+template <typename T, int MMAX, int LIMC, bool EXT, bool CELL, bool REUSE, bool HALF = false>
 __device__ __forceinline__ void batch_tile(const SweepParams<T>& P, int l1_0, unsigned char* smem, double& lsum,
                                            T& lmin, T& lmax) {
     if constexpr (CELL)
         cell::sweep_tile<T, 2, MMAX, LIMC, EXT>(P, l1_0, 0, smem, lsum, lmin, lmax);
     else
-        sweep_tile<T, 2, MMAX, LIMC, EXT, REUSE>(P, l1_0, 0, smem, lsum, lmin, lmax);
+        sweep_tile<T, 2, MMAX, LIMC, EXT, REUSE, HALF>(P, l1_0, 0, smem, lsum, lmin, lmax);
 }
-// The tile at the problem's own capacity mm (MMAX or MMAX / 2; uniform
-// over the block, which belongs to one problem).
+// The tile at the problem's own capacity mm (MMAX, MMAX / 2, or 4 in the
+// capacity-16 kernels) and line packing (half: two lines per wave,
+// capacity-16 face-body kernels only); uniform over the block, which
+// belongs to one problem.
 template <typename T, int MMAX, int LIMC, bool EXT, bool CELL, bool REUSE>
-__device__ __forceinline__ void batch_tile_cap(int mm, const SweepParams<T>& P, int l1_0, unsigned char* smem,
-                                               double& lsum, T& lmin, T& lmax) {
+__device__ __forceinline__ void batch_tile_cap(int mm, int half, const SweepParams<T>& P, int l1_0,
+                                               unsigned char* smem, double& lsum, T& lmin, T& lmax) {
+    if constexpr (MMAX == 16 && !CELL) {
+        if (half) {
+            batch_tile<T, MMAX, LIMC, EXT, CELL, REUSE, true>(P, l1_0, smem, lsum, lmin, lmax);
+            return;
+        }
+    }
+    if constexpr (MMAX == 16) {
+        if (mm <= 4) {
+            batch_tile<T, 4, LIMC, EXT, CELL, REUSE>(P, l1_0, smem, lsum, lmin, lmax);
+            return;
+        }
+    }
     if constexpr (MMAX >= 4) {
         if (mm < MMAX) {
             batch_tile<T, MMAX / 2, LIMC, EXT, CELL, REUSE>(P, l1_0, smem, lsum, lmin, lmax);
@@ -114,8 +128,8 @@ __global__ void __launch_bounds__((BatchBounds<T, MMAX, CELL>::max_threads))
                 T amin = T(__builtin_huge_val()), amax = T(-__builtin_huge_val());
                 const int ng = bp->ngroups[d];
                 for (int g = 0; g < ng; ++g) {
-                    batch_tile_cap<T, MMAX, LIMC, EXT, CELL, true>(bp->mmax[d], P, g * P.lpw, smem_raw, lsum, lmin,
-                                                                  lmax);
+                    batch_tile_cap<T, MMAX, LIMC, EXT, CELL, true>(bp->mmax[d], bp->half[d], P, g * P.lpw, smem_raw,
+                                                                  lsum, lmin, lmax);
                     acc += lsum;
                     amin = lmin < amin ? lmin : amin;
                     amax = lmax > amax ? lmax : amax;
@@ -158,8 +172,8 @@ __global__ void __launch_bounds__((BatchBounds<T, MMAX, CELL>::max_threads))
     P.red.partials = partials;
     double lsum;
     T lmin, lmax;
-    batch_tile_cap<T, MMAX, LIMC, EXT, CELL, false>(probs[lo].mmax[d], P, (b - group_start[lo]) * P.lpw, smem_raw,
-                                                    lsum, lmin, lmax);
+    batch_tile_cap<T, MMAX, LIMC, EXT, CELL, false>(probs[lo].mmax[d], probs[lo].half[d], P,
+                                                    (b - group_start[lo]) * P.lpw, smem_raw, lsum, lmin, lmax);
     // block b's partial sits at index b: problem p's y-sweep tiles are
     // tile0[p] .. tile0[p] + ngroups[1] - 1
     if (partials) block_partials<T>(partials, lsum, lmin, lmax);

@@ -117,18 +117,37 @@ extern "C" int asd_batch_workspace_bytes(const asd_desc* descs, int32_t nprob, s
 // either; a line shorter than the batch's longest then does not pad every
 // lane to the longest one's capacity).
 static bool batch_line_cfg(int es, int n, int nthreads, int mmax, int variant, SweepCfg* out) {
+    // capacity 16 on the face body: lines of 257-512 cells take half a wave
+    // each (32 lanes of 9-16 cells, two lines per wave); shorter lines do
+    // better on the one-line tiles of capacity 4 or 8
+    if (variant == SWEEP_FACE_SLOTS && mmax == 16 && n > 256 && (n + 31) / 32 <= 16 && nthreads >= 64) {
+        const int lpw = nthreads / 32;
+        if (sweep_lds(es, 2, n, lpw, 1, nthreads, 16, variant, 1) <= kLdsLimit) {
+            out->wpl = 1;
+            out->lpw = lpw;
+            out->P = 32;
+            out->mmax = 16;
+            out->io = 1;
+            out->variant = variant;
+            out->half = 1;
+            return true;
+        }
+    }
     for (int wpl = 1; 64 * wpl <= nthreads; wpl *= 2) {
         const int P = std::min(64 * wpl, pow2_floor(n));
         const int m = (n + P - 1) / P;
         if (m > mmax) continue;
         const int lpw = nthreads / (64 * wpl);
-        const int own = mmax >= 4 && 2 * m <= mmax ? mmax / 2 : mmax;
+        // the tile's own capacity: mmax, mmax / 2, or (capacity 16) 4
+        int own = mmax >= 4 && 2 * m <= mmax ? mmax / 2 : mmax;
+        if (mmax == 16 && m <= 4) own = 4;
         if (sweep_lds(es, 2, n, lpw, wpl, nthreads, own, variant) > kLdsLimit) continue;
         out->wpl = wpl;
         out->lpw = lpw;
         out->P = P;
         out->mmax = own;
         out->variant = variant;
+        out->half = 0;
         return true;
     }
     return false;
@@ -151,7 +170,7 @@ static int batch_shape(asd_batch b, int nthreads, int variant, int mmax_from = 4
                 ok = batch_line_cfg(es, n, nthreads, mmax, variant, &cfg[2 * p + d]);
                 if (ok)
                     lds = std::max(lds, sweep_lds(es, 2, n, cfg[2 * p + d].lpw, cfg[2 * p + d].wpl, nthreads,
-                                                  cfg[2 * p + d].mmax, variant));
+                                                  cfg[2 * p + d].mmax, variant, cfg[2 * p + d].half));
             }
         }
         if (!ok) continue;
@@ -270,6 +289,12 @@ extern "C" int asd_batch_set_variant(asd_batch b, int32_t variant) {
     return batch_shape(b, b->nthreads, variant);
 }
 
+extern "C" int asd_batch_set_capacity(asd_batch b, int32_t mmax) {
+    if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
+    if (mmax != 4 && mmax != 8 && mmax != 16) return asd_fail(ASD_EINVAL, "capacity must be 4, 8 or 16");
+    return batch_shape(b, b->nthreads, b->variant, mmax);
+}
+
 extern "C" int asd_batch_get_variant(asd_batch b, int32_t* variant) {
     if (!b) return asd_fail(ASD_EINVAL, "batch is NULL");
     if (!variant) return asd_fail(ASD_EINVAL, "NULL output");
@@ -295,6 +320,7 @@ static int batch_tables(asd_batch b) {
             const int nt1 = probs[p].sweep[d].nt1, lpw = b->cfg[2 * p + d].lpw;
             probs[p].ngroups[d] = (nt1 + lpw - 1) / lpw;
             probs[p].mmax[d] = b->cfg[2 * p + d].mmax;
+            probs[p].half[d] = b->cfg[2 * p + d].half;
         }
         probs[p].dirichlet = g->d.bc == ASD_BC_DIRICHLET;
         probs[p].dV = g->d.h[0] * g->d.h[1];

@@ -408,11 +408,11 @@ int fill_sweep_params(asd_grid g, int d, const void* in, void* out, int rhs_mode
     P.lpw = c.lpw;
     P.P = c.P;
     P.nseg_log2 = ilog2(c.P);
-    P.spl_log2 = ilog2(64 * c.wpl);
+    P.spl_log2 = c.half ? 5 : ilog2(64 * c.wpl);
     P.io_log2 = ilog2(c.io);
     P.lpw_log2 = ilog2(c.lpw);
     P.rhs_mode = rhs_mode & SWEEP_SOLVE_ONLY;
-    P.lds = sweep_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant);
+    P.lds = sweep_layout((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant, c.half);
     if (P.si_n != 1) return asd_fail(ASD_EUNSUPPORTED, "sweep input must be contiguous along the line");
     *Pout = P;
     return ASD_OK;
@@ -445,7 +445,7 @@ static int enqueue_sweep_t(asd_grid g, int d, double dt, const void* in, void* o
     if (nblocks_out) *nblocks_out = (int)nblocks;
     if (red.partials && nblocks > g->max_blocks)
         return asd_fail(ASD_EUNSUPPORTED, "too many blocks for the reduction scratch");
-    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant);
+    const size_t lds = sweep_lds((int)sizeof(T), g->d.ndim, P.n, c.lpw, c.wpl, c.nthreads(), c.mmax, c.variant, c.half);
     return hip_check(launch_sweep<T>(P, g->d.ndim, c.mmax, dim3((unsigned)nblocks), dim3(c.nthreads()), lds, g->st,
                                      c.variant),
                      "sweep launch");

@@ -102,7 +102,9 @@ struct TileCtx {
     int neg1m, neg1p, neg2m, neg2p;  // T = 0 walls: that transverse neighbour is the odd ghost
 };
 
-template <typename T, int NDIM, bool EXT>
+// HALF: two lines per wave (lanes 0-31 and 32-63), a line's solve spread
+// over 32 lanes (short lines in batches); the line index is then per lane.
+template <typename T, int NDIM, bool EXT, bool HALF = false>
 __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0, int l2, unsigned char* buf) {
     const int sio_log2 = P.spl_log2 + P.io_log2;
     const bool periodic = P.periodic != 0;
@@ -110,10 +112,17 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const SweepParams<T>& P, int l1_0
     TileCtx<T> c;
     c.l1_0 = l1_0;
     c.l2 = l2;
-    c.q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> sio_log2);
-    c.k = threadIdx.x & ((1 << sio_log2) - 1);
-    c.w = __builtin_amdgcn_readfirstlane(c.k >> 6);
-    c.lane = c.k & 63;
+    if constexpr (HALF) {
+        c.q = (int)threadIdx.x >> 5;
+        c.k = threadIdx.x & 31;
+        c.w = 0;
+        c.lane = c.k;
+    } else {
+        c.q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> sio_log2);
+        c.k = threadIdx.x & ((1 << sio_log2) - 1);
+        c.w = __builtin_amdgcn_readfirstlane(c.k >> 6);
+        c.lane = c.k & 63;
+    }
     c.l1 = l1_0 + c.q;
     c.line_ok = c.l1 < P.nt1;
     c.buf = buf;
@@ -165,14 +174,15 @@ struct ChunkData {
 // Cell n is cell 0 on a periodic line (the wrap neighbour); cells past the
 // line's end are otherwise clamped to its last cell (their values are not
 // used).
-template <typename T, int NDIM>
+template <typename T, int NDIM, bool HALF = false>
 __device__ __forceinline__ void load_chunk(const SweepParams<T>& P, const TileCtx<T>& c, int chunk, bool face,
                                            ChunkData<T>& r) {
     constexpr int ES = (int)sizeof(T);
+    constexpr int CL = HALF ? 5 : 6;  // log2 of the cells per chunk (lanes per line)
     const bool solve_only = P.rhs_mode != 0;
     const int n = P.n;
-    int p = (chunk << 6) + c.lane;
-    if ((chunk << 6) + 63 >= n) p = p < n ? p : (p == n && P.periodic ? 0 : n - 1);  // wave-uniform test
+    int p = (chunk << CL) + c.lane;
+    if ((chunk << CL) + (1 << CL) - 1 >= n) p = p < n ? p : (p == n && P.periodic ? 0 : n - 1);  // wave-uniform test
     const unsigned bo = (unsigned)p * (unsigned)ES;
     r.u = ldg_off(c.gU, bo);
     if (!solve_only) {
@@ -197,21 +207,29 @@ template <typename T>
 __device__ __forceinline__ T rotate_down(T v) {
     return dpp_mov<0x134, 0xf>(v, v);
 }
+// The same within each half of the wave (lane i takes lane i+1 mod 32 of
+// its half): two lines per wave.
+template <typename T>
+__device__ __forceinline__ T rotate_down_half(T v, int lane32) {
+    return __shfl(v, (lane32 + 1) & 31, 32);
+}
 
 // Stages the tile's faces: for every cell p of the line,
 //   Phi_f = alpha_f (U_{p+1} - U_p) + sum_t beta_t,f L(s_t(p+1), s_t(p))
 // and (alpha_f, Phi_f) into the face's slot.  Loads go in batches of up to
 // nine chunks; the last chunk of a batch waits for the next batch's first
 // (its lane 63 needs it).
-template <typename T, int NDIM, int MMAX, int LIMC, bool EXT>
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT, bool HALF = false>
 __device__ __forceinline__ void stage_tile(const SweepParams<T>& P, const TileCtx<T>& c) {
     constexpr int ES = (int)sizeof(T);
+    constexpr int CL = HALF ? 5 : 6;  // log2 of the cells per chunk
+    auto rot = [&](T v) { return HALF ? rotate_down_half<T>(v, c.lane) : rotate_down<T>(v); };
     constexpr int CH = MMAX < 8 ? MMAX + 1 : 9;
     const bool solve_only = P.rhs_mode != 0;
     const int lim = LIMC >= 0 ? LIMC : P.limiter;
     const int n = P.n;
-    const int wio_log2 = P.spl_log2 + P.io_log2 - 6;  // staging waves per line: wpl * io
-    const int nch = (n + 63) >> 6;
+    const int wio_log2 = HALF ? 0 : P.spl_log2 + P.io_log2 - 6;  // staging waves per line: wpl * io
+    const int nch = (n + (1 << CL) - 1) >> CL;
     const int cpw = (nch + (1 << wio_log2) - 1) >> wio_log2;
     const int c0 = c.w * cpw;
     const int jn = min(cpw, nch - c0);  // this wave's chunks (wave-uniform, may be <= 0)
@@ -228,7 +246,7 @@ __device__ __forceinline__ void stage_tile(const SweepParams<T>& P, const TileCt
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int jj = j0 + j;  // chunk jj of the wave; jj == jn: the extra chunk
-            if (jj <= jn) load_chunk<T, NDIM>(P, c, jj < jn ? c0 + jj : cnext, jj < jn, r[j]);
+            if (jj <= jn) load_chunk<T, NDIM, HALF>(P, c, jj < jn ? c0 + jj : cnext, jj < jn, r[j]);
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
@@ -243,18 +261,18 @@ __device__ __forceinline__ void stage_tile(const SweepParams<T>& P, const TileCt
                     s2 = EXT ? cell_slope<T>(lim, c.neg2m ? -u : r[j].u2m, u, c.neg2p ? -u : r[j].u2p)
                              : cell_slope<T>(lim, r[j].u2m, u, r[j].u2p);
             }
-            const T nru = rotate_down<T>(u);
+            const T nru = rot(u);
             T nrs1 = T(0), nrs2 = T(0);
             if (!solve_only) {
-                nrs1 = rotate_down<T>(s1);
-                if (NDIM == 3) nrs2 = rotate_down<T>(s2);
+                nrs1 = rot(s1);
+                if (NDIM == 3) nrs2 = rot(s2);
             }
             if (jj > 0) {
                 // faces of chunk jj-1: the right neighbours from its own
                 // rotation, lane 63's from this chunk's lane 0
-                const bool last_lane = c.lane == 63;
+                const bool last_lane = c.lane == (1 << CL) - 1;
                 const T un = last_lane ? nru : ru;
-                const int p = ((c0 + jj - 1) << 6) + c.lane;
+                const int p = ((c0 + jj - 1) << CL) + c.lane;
                 if (p < n) {
                     T a = pa;
                     T phi = a * (un - pu);
@@ -291,7 +309,7 @@ __device__ __forceinline__ void stage_tile(const SweepParams<T>& P, const TileCt
 // tile layout), so the segment length is a compile-time constant and the
 // per-cell bounds tests vanish.  REUSE: the block stages another tile in
 // the same LDS afterwards (a closing barrier).
-template <typename T, int NDIM, int MMAX, int LIMC, bool EXT, bool FULL, bool REUSE>
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT, bool FULL, bool REUSE, bool HALF = false>
 __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileCtx<T>& ctx, unsigned char* smem,
                                             const T (&uu)[MMAX], double& lsum, T& lmin, T& lmax) {
     constexpr int ES = (int)sizeof(T);
@@ -312,11 +330,12 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
     // ---------------- phase 2: per-lane segment elimination
     // Segments are interleaved over the line's waves: lane l of wave w owns
     // segment kseg = l * wpl + w.
-    const int wpl_log2 = spl_log2 - 6;
+    const int wpl_log2 = HALF ? 0 : spl_log2 - 6;
+    constexpr int SW = HALF ? 32 : 64;  // lanes that exchange by shuffles: one line's
     const int sio_log2 = spl_log2 + P.io_log2;
     const int nseg = 1 << P.nseg_log2;
     const bool part = k < spl;  // this thread takes part in the solve
-    const int kseg = ((k & 63) << wpl_log2) | (k >> 6);
+    const int kseg = HALF ? k : ((k & 63) << wpl_log2) | (k >> 6);
     const bool active = part && line_ok && kseg < nseg;
     const int s0 = active ? (FULL ? kseg * MMAX : (kseg * n) >> P.nseg_log2) : 0;
     const int m = FULL ? MMAX : (active ? (((kseg + 1) * n) >> P.nseg_log2) - s0 : 1);
@@ -430,7 +449,7 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
     if (P.wpl == 1) {
         // one wave per line: lane == segment; shuffles only, no barrier
         const int kr = (k + 1) & (nseg - 1);
-        const T Yp = __shfl(Y, kr, 64), Up = __shfl(Uc, kr, 64), Vp = __shfl(V, kr, 64);
+        const T Yp = __shfl(Y, kr, SW), Up = __shfl(Uc, kr, SW), Vp = __shfl(V, kr, SW);
         if (active) {
             const T ib = fast_rcp<T>(be - ae * hp + ce * Up);
             Ra = ae * wp * ib;
@@ -441,8 +460,8 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
         }
         for (int s = 1; s < nseg; s <<= 1) {
             const int km = (k - s) & (nseg - 1), kp = (k + s) & (nseg - 1);
-            const T am = __shfl(Ra, km, 64), cm = __shfl(Rc, km, 64), dm = __shfl(Rd, km, 64);
-            const T ap = __shfl(Ra, kp, 64), cp = __shfl(Rc, kp, 64), dp = __shfl(Rd, kp, 64);
+            const T am = __shfl(Ra, km, SW), cm = __shfl(Rc, km, SW), dm = __shfl(Rd, km, SW);
+            const T ap = __shfl(Ra, kp, SW), cp = __shfl(Rc, kp, SW), dp = __shfl(Rd, kp, SW);
             if (k < nseg) {
                 const T ib = fast_rcp<T>(T(1) - Ra * cm - Rc * ap);
                 const T na = -Ra * am, nc = -Rc * cp, nd = Rd - Ra * dm - Rc * dp;
@@ -452,7 +471,7 @@ __device__ __forceinline__ void solve_store(const SweepParams<T>& P, const TileC
             }
         }
         XR = Rd * fast_rcp<T>(T(1) + Ra + Rc);
-        XL = __shfl(XR, (k - 1) & (nseg - 1), 64);
+        XL = __shfl(XR, (k - 1) & (nseg - 1), SW);
     } else {
         // several waves per line.  Exchanges between waves go through two
         // LDS buffers used alternately: a buffer is rewritten only after the
@@ -692,20 +711,20 @@ __device__ __forceinline__ void load_store_u(const SweepParams<T>& P, const Tile
 
 // One whole tile (phases 1-3) in the LDS buffer at smem.  REUSE: the caller
 // stages further tiles in the same LDS afterwards.
-template <typename T, int NDIM, int MMAX, int LIMC, bool EXT = false, bool REUSE = false>
+template <typename T, int NDIM, int MMAX, int LIMC, bool EXT = false, bool REUSE = false, bool HALF = false>
 __device__ __forceinline__ void sweep_tile(const SweepParams<T>& P, int l1_0, int l2, unsigned char* smem,
                                            double& lsum, T& lmin, T& lmax) {
-    const TileCtx<T> c = tile_ctx<T, NDIM, EXT>(P, l1_0, l2, smem);
-    stage_tile<T, NDIM, MMAX, LIMC, EXT>(P, c);
+    const TileCtx<T> c = tile_ctx<T, NDIM, EXT, HALF>(P, l1_0, l2, smem);
+    stage_tile<T, NDIM, MMAX, LIMC, EXT, HALF>(P, c);
     // U of the cells this thread stores in phase 3 (same lines, still in
     // cache): loaded now, so that the solve hides their latency
     T uu[MMAX];
     load_store_u<T, MMAX>(P, c, uu);
     __syncthreads();
     if (P.lds.aligned)
-        solve_store<T, NDIM, MMAX, LIMC, EXT, true, REUSE>(P, c, smem, uu, lsum, lmin, lmax);
+        solve_store<T, NDIM, MMAX, LIMC, EXT, true, REUSE, HALF>(P, c, smem, uu, lsum, lmin, lmax);
     else
-        solve_store<T, NDIM, MMAX, LIMC, EXT, false, REUSE>(P, c, smem, uu, lsum, lmin, lmax);
+        solve_store<T, NDIM, MMAX, LIMC, EXT, false, REUSE, HALF>(P, c, smem, uu, lsum, lmin, lmax);
 }
 
 }  // namespace asd

@@ -326,3 +326,8 @@ def test_graph_mode_validation(asd):
         assert L.asd_set_graphs(h, m) == -1
     assert L.asd_set_graphs(None, 1) == -1
     assert L.asd_destroy(h) == 0
+
+
+def test_batch_capacity_validation(asd):
+    L = asd.lib()
+    assert L.asd_batch_set_capacity(None, 16) == -1

@@ -298,3 +298,61 @@ def test_batch_cell_body_matches_oracle(mode, prec, bc):
         assert err(got, ref) <= TOL[prec], (p.name, p.shape, err(got, ref))
         if prec == "f64":
             np.testing.assert_allclose(e[i], eref, rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("prec,nthreads", [("f64", 256), ("f32", 256), ("f32", 512)])
+def test_batch_two_lines_per_wave_matches_oracle(mode, prec, bc, nthreads):
+    """Capacity 16 on the face body: problems whose lines have 257-512
+    cells run two lines per wave (32 lanes each), the others the one-line
+    tiles of capacity 4, 8 or 16; every problem against the oracle, and the
+    FP64 energies.
+    (FP64 tiles of capacity 16 take at most 256 threads.)"""
+    # sides on both sides of 256: a problem's x and y lines choose their
+    # tiles separately
+    probs = synth.batch_problems(nprob=8, master_seed=7, sides=np.array([7, 64, 130, 272, 320, 512]), nsteps=5)
+    if bc == "dirichlet":
+        probs = [dataclasses.replace(p, bc="dirichlet") for p in probs]
+    assert any(max(p.shape) > 256 for p in probs) and any(min(p.shape) <= 256 for p in probs)
+    st = torch.cuda.Stream()
+    b, items = _gpu_batch(probs, prec, st, bc=bc)
+    b.set_variant(0)
+    b.set_block(nthreads)
+    b.set_capacity(16)
+    with torch.cuda.stream(st):
+        e = b.step(5, mode, energy=True)
+    st.synchronize()
+    e = e.cpu().numpy()
+    err = mixed_rel_err if bc == "dirichlet" else max_rel_err
+    for i, (p, it) in enumerate(zip(probs, items)):
+        ref, eref = oracle_run(p, prec, nsteps=5, energy=True)
+        got = it["T"].double().cpu().numpy()
+        assert err(got, ref) <= TOL[prec], (p.name, p.shape, err(got, ref))
+        if prec == "f64":
+            np.testing.assert_allclose(e[i], eref, rtol=1e-13, atol=1e-300)
+
+
+def test_batch_256_two_lines_per_wave_fp64_10_steps():
+    """The 256-problem workload (lines of 64-512 cells: those above 256 cells
+    two per wave, the others on the capacity-4 and -8 tiles) in FP64, 10
+    steps, grouped and persistent schedules at capacity 16: cell by cell
+    against the oracle at 1e-12, the two schedules bit for bit."""
+    probs = synth.batch_problems(nprob=256, master_seed=40, nsteps=10)
+    st = torch.cuda.Stream()
+    b, items = _gpu_batch(probs, "f64", st)
+    b.set_variant(0)
+    b.set_block(256)
+    b.set_capacity(16)
+    res = {}
+    for m in (0, 2):
+        with torch.cuda.stream(st):
+            for p, it in zip(probs, items):
+                it["T"].copy_(torch.from_numpy(p.T0))
+            b.step(10, m)
+        st.synchronize()
+        res[m] = [it["T"].cpu().numpy() for it in items]
+    refs = _oracle_all(probs, "f64", 10)
+    for i, p in enumerate(probs):
+        assert np.array_equal(res[0][i], res[2][i]), i
+        assert max_rel_err(res[2][i], refs[i]) <= TOL["f64"], (i, p.shape)
