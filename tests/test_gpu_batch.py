@@ -29,6 +29,16 @@ def _gpu_batch(probs, prec, stream, bc="periodic"):
     return b, items
 
 
+def _energy_rtol(p):
+    """Bar for a problem's FP64 energy against the oracle's: both sum N
+    positive cell values in FP64, the oracle in order, the GPU in per-tile
+    partials folded per problem, so the two differ by rounding that grows
+    like sqrt(N) eps (random-walk estimate, 4x margin); 1e-13 at the small
+    problems' sizes, 3e-13 at 512 x 272 cells."""
+    n = p.shape[0] * p.shape[1]
+    return max(1e-13, 4 * np.sqrt(n) * np.finfo(np.float64).eps)
+
+
 def _small_batch(n, seed):
     sides = np.array([3, 7, 16, 33, 64, 65, 96, 130, 192])
     return synth.batch_problems(nprob=n, master_seed=seed, sides=sides, nsteps=5)
@@ -330,7 +340,7 @@ def test_batch_two_lines_per_wave_matches_oracle(mode, prec, bc, nthreads):
         got = it["T"].double().cpu().numpy()
         assert err(got, ref) <= TOL[prec], (p.name, p.shape, err(got, ref))
         if prec == "f64":
-            np.testing.assert_allclose(e[i], eref, rtol=1e-13, atol=1e-300)
+            np.testing.assert_allclose(e[i], eref, rtol=_energy_rtol(p), atol=1e-300)
 
 
 def test_batch_256_two_lines_per_wave_fp64_10_steps():
@@ -356,3 +366,4 @@ def test_batch_256_two_lines_per_wave_fp64_10_steps():
     for i, p in enumerate(probs):
         assert np.array_equal(res[0][i], res[2][i]), i
         assert max_rel_err(res[2][i], refs[i]) <= TOL["f64"], (i, p.shape)
+
